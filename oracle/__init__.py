@@ -1,0 +1,160 @@
+"""CPU oracle for the QLA time step (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg import
+this package. It shares no code with the GPU library. The heavy lifting is the
+plain FP64 C implementation in `qla_oracle.c` (one full-lattice pass per
+operator of Eq. 2e14, OpenMP over rows); this module loads it with ctypes and
+adds numpy front ends. `symbol.py` (Fourier symbol of one homogeneous step) and
+`spectral.py` (spectral solution of Eqs. 2d1-2d6) are independent references
+used only to pin the oracle.
+
+Layout: a state is a float64 array q[6, ny, nx] holding (q0..q5) of Eq. (3b3),
+x fastest.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC_PATH = os.path.join(_HERE, "qla_oracle.c")
+
+V_SKEW_HALF, V_PAPER, V_NONE = 0, 1, 2
+
+# Operator codes, in the order of the C enum.
+(OP_CX, OP_CX_DAG, OP_CY, OP_CY_DAG,
+ OP_S14_PX, OP_S14_MX, OP_S25_PX, OP_S25_MX,
+ OP_S03_PY, OP_S03_MY, OP_S25_PY, OP_S25_MY,
+ OP_VX, OP_VY, OP_UX, OP_UY, OP_STEP) = range(17)
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc into liboracle.so next to its source."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp,
+                        _SRC_PATH, "-lm"], check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.qla_oracle_coefficients.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                dp, dp, dp, dp]
+        lib.qla_oracle_coefficients.restype = ctypes.c_int
+        lib.qla_oracle_apply.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_int, dp, dp]
+        lib.qla_oracle_apply.restype = ctypes.c_int
+        lib.qla_oracle_advance.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int, dp, dp, ctypes.c_longlong]
+        lib.qla_oracle_advance.restype = ctypes.c_int
+        lib.qla_oracle_energy.argtypes = [ctypes.c_int, ctypes.c_int, dp]
+        lib.qla_oracle_energy.restype = ctypes.c_double
+        lib.qla_oracle_packet.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+        lib.qla_oracle_packet.restype = ctypes.c_int
+        lib.qla_oracle_threads.argtypes = []
+        lib.qla_oracle_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _index(n: np.ndarray) -> np.ndarray:
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    if n.ndim != 2:
+        raise ValueError("n must be a 2D [ny, nx] array")
+    return n
+
+
+def _state(q: np.ndarray, ny: int, nx: int) -> np.ndarray:
+    if q.shape != (6, ny, nx) or q.dtype != np.float64 or not q.flags.c_contiguous:
+        raise ValueError("state must be a C-contiguous float64 array of shape (6, ny, nx)")
+    return q
+
+
+def threads() -> int:
+    return int(_load().qla_oracle_threads())
+
+
+def coefficients(n: np.ndarray, delta: float):
+    """(theta, beta_x, beta_y) per site: Eq. (2e4) and Eq. (2e13) with centred differences."""
+    n = _index(n)
+    ny, nx = n.shape
+    th, bx, by = (np.empty_like(n) for _ in range(3))
+    rc = _load().qla_oracle_coefficients(nx, ny, float(delta), _ptr(n), _ptr(th), _ptr(bx),
+                                         _ptr(by))
+    if rc:
+        raise ValueError(f"qla_oracle_coefficients failed ({rc})")
+    return th, bx, by
+
+
+def packet(n: np.ndarray, x0: float, y0: float, sigma: float, lam: float, phi: float = 0.0,
+           amp: float = 1.0, planar: bool = True) -> np.ndarray:
+    """Initial state q[6, ny, nx] of a one-way E_z packet (Section V initial conditions)."""
+    n = _index(n)
+    ny, nx = n.shape
+    q = np.zeros((6, ny, nx), dtype=np.float64)
+    rc = _load().qla_oracle_packet(nx, ny, _ptr(n), float(x0), float(y0), float(sigma),
+                                   float(lam), float(phi), float(amp), int(bool(planar)), _ptr(q))
+    if rc:
+        raise ValueError(f"qla_oracle_packet failed ({rc})")
+    return q
+
+
+def packet_from(n: np.ndarray, p) -> np.ndarray:
+    """`packet` for a workloads.Packet description."""
+    return packet(n, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
+
+
+def apply(op: int, q: np.ndarray, n: np.ndarray, delta: float, vmode: int = V_SKEW_HALF):
+    """Apply one operator (OP_* code) to q in place and return q."""
+    n = _index(n)
+    ny, nx = n.shape
+    _state(q, ny, nx)
+    rc = _load().qla_oracle_apply(int(op), nx, ny, float(delta), int(vmode), _ptr(n), _ptr(q))
+    if rc:
+        raise ValueError(f"qla_oracle_apply failed ({rc})")
+    return q
+
+
+def advance(q: np.ndarray, n: np.ndarray, delta: float, steps: int,
+            vmode: int = V_SKEW_HALF) -> np.ndarray:
+    """Advance q in place by `steps` steps of Eq. (2e14) and return it."""
+    n = _index(n)
+    ny, nx = n.shape
+    _state(q, ny, nx)
+    rc = _load().qla_oracle_advance(nx, ny, float(delta), int(vmode), _ptr(n), _ptr(q),
+                                    int(steps))
+    if rc:
+        raise ValueError(f"qla_oracle_advance failed ({rc})")
+    return q
+
+
+def energy(q: np.ndarray) -> float:
+    """Eq. (A13): sum of q_c^2 over components and sites (no cell-area factor)."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    if q.ndim != 3 or q.shape[0] != 6:
+        raise ValueError("state must have shape (6, ny, nx)")
+    return float(_load().qla_oracle_energy(q.shape[2], q.shape[1], _ptr(q)))
+
+
+def physical_fields(q: np.ndarray, n: np.ndarray):
+    """(Ez, Bx, By) from the E_z triple: Ez = q2 / n, Bx = q3, By = q4 (Eq. 3b3, c = 1)."""
+    return q[2] / n, q[3].copy(), q[4].copy()

@@ -1,0 +1,395 @@
+"""Pins of the CPU oracle to what the paper and the mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: the printed
+LCU matrices (Eqs. 2f1-2f7), the Fourier algebra of the printed operator
+products (Eqs. 2e6, 2e9, 2e10), the continuum Maxwell equations (Eqs. 2d1-2d6),
+unitarity, closed-form translation in vacuum, a spectral solution of the PDE,
+and the textbook normal-incidence Fresnel reflectance.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from oracle import spectral, symbol
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "lcu_matrices.txt")
+
+
+# --------------------------------------------------------------------------------------
+# helpers
+def _load_golden():
+    mats, name = {}, None
+    with open(GOLDEN) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("["):
+                name = line[1:-1]
+                mats[name] = []
+            else:
+                mats[name].append(line.split())
+    return mats
+
+
+def _eval(mat, beta):
+    out = np.zeros((6, 6))
+    for r, row in enumerate(mat):
+        for c, tok in enumerate(row):
+            sign = -1.0 if tok.startswith("-") else 1.0
+            t = tok.lstrip("-")
+            if t in ("0", "1"):
+                v = float(t)
+            else:
+                k = int(t[1])
+                v = math.cos(beta[k]) if t[0] == "c" else math.sin(beta[k])
+            out[r, c] = sign * v
+    return out
+
+
+def _site_matrices(op, n, delta, vmode):
+    """Dense 6x6 matrix of a site-local operator at every site, column by column."""
+    ny, nx = n.shape
+    cols = []
+    for c in range(6):
+        q = np.zeros((6, ny, nx))
+        q[c] = 1.0
+        oracle.apply(op, q, n, delta, vmode)
+        cols.append(q)
+    # M[y, x, r, c]
+    return np.stack(cols, axis=-1).transpose(1, 2, 0, 3)
+
+
+def _smooth_random_index(nx, ny, seed, lo=1.0, hi=3.0):
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx)[None, :] * 2 * np.pi / nx
+    y = np.arange(ny)[:, None] * 2 * np.pi / ny
+    f = np.zeros((ny, nx))
+    for _ in range(4):
+        a, b = rng.integers(0, 3, size=2)
+        f += rng.normal() * np.cos(a * x + b * y + rng.uniform(0, 2 * np.pi))
+    f = (f - f.min()) / (np.ptp(f) + 1e-300)
+    return lo + (hi - lo) * f
+
+
+# --------------------------------------------------------------------------------------
+# potentials against the printed linear combination of unitaries
+def test_lcu_sum_pins_vx_including_row_q5():
+    g = _load_golden()
+    rng = np.random.default_rng(1)
+    n = rng.uniform(1.0, 3.0, size=(4, 5))
+    delta = 0.7
+    _, bx, by = oracle.coefficients(n, delta)
+    M = _site_matrices(oracle.OP_VX, n, delta, oracle.V_PAPER)
+    for y in range(4):
+        for x in range(5):
+            beta = [bx[y, x], by[y, x], bx[y, x], by[y, x]]  # isotropic: b0=b2, b1=b3
+            lcu = 0.5 * sum(_eval(g[k], beta) for k in ("L_x1", "L_x2", "L_x3", "L_x4"))
+            np.testing.assert_allclose(M[y, x], lcu, atol=1e-15)
+            printed = _eval(g["V_x"], beta)
+            # the printed V_x agrees with its own LCU everywhere except the q5 <- q1 entry
+            diff = np.argwhere(np.abs(printed - lcu) > 1e-15)
+            if abs(bx[y, x]) > 1e-12:
+                assert [tuple(d) for d in diff] == [(5, 1)]
+
+
+def test_lcu_sum_pins_vy_outside_row_q3():
+    g = _load_golden()
+    rng = np.random.default_rng(2)
+    n = rng.uniform(1.0, 3.0, size=(5, 4))
+    delta = 0.7
+    _, bx, by = oracle.coefficients(n, delta)
+    M = _site_matrices(oracle.OP_VY, n, delta, oracle.V_PAPER)
+    for y in range(5):
+        for x in range(4):
+            beta = [bx[y, x], by[y, x], bx[y, x], by[y, x]]
+            lcu = 0.5 * sum(_eval(g[k], beta) for k in ("L_y1", "L_y2", "L_y3", "L_y4"))
+            # the LCU reproduces the printed V_y exactly (including its row q3) ...
+            np.testing.assert_allclose(lcu, _eval(g["V_y"], beta), atol=1e-15)
+            keep = [0, 1, 2, 4, 5]
+            np.testing.assert_allclose(M[y, x][keep], lcu[keep], atol=1e-15)
+            # ... whose row q3 is not the identity at beta = 0, contradicting Eq. (2e10);
+            # the oracle's row q3 has cos/sin exchanged.
+            np.testing.assert_allclose(M[y, x][3], [0, 0, math.sin(beta[3]), math.cos(beta[3]), 0, 0],
+                                       atol=1e-15)
+
+
+def test_vy_row_q3_reading_is_the_homogeneous_limit_and_eq_2d4_sign():
+    # beta = 0 (uniform n): every potential must be the identity (Eq. 2e10 is the
+    # homogeneous scheme); to first order Eq. (2d4) needs q3 += +beta3 q2.
+    n = np.full((4, 4), 1.6)
+    M = _site_matrices(oracle.OP_VY, n, 0.5, oracle.V_PAPER)
+    np.testing.assert_array_equal(M[0, 0], np.eye(6))
+    n = 1.5 + 0.01 * np.arange(8)[:, None] * np.ones((1, 4))
+    delta = 0.1
+    _, _, by = oracle.coefficients(n, delta)
+    M = _site_matrices(oracle.OP_VY, n, delta, oracle.V_PAPER)
+    y = 3
+    assert by[y, 0] > 0
+    assert abs(M[y, 0][3, 2] - by[y, 0]) < by[y, 0] ** 3
+
+
+def test_beta_is_delta_squared_gradient_over_n_squared():
+    # Eq. (2e13) with a centred difference: second-order accurate in the cell size.
+    nx, delta = 64, 0.3
+    x = np.arange(nx)
+    k = 2 * np.pi / nx
+    n = np.broadcast_to(2.0 + 0.5 * np.sin(k * x)[None, :], (3, nx)).copy()
+    th, bx, by = oracle.coefficients(n, delta)
+    dndx_phys = 0.5 * k * np.cos(k * x) / delta          # d n / d(physical x)
+    exact = delta ** 2 * dndx_phys / n[0] ** 2
+    err = np.abs(bx[0] - exact).max() / np.abs(exact).max()
+    assert err < k * k / 6 * 1.01 and err > k * k / 6 * 0.5   # sin(k)/k - 1 ~ -k^2/6
+    np.testing.assert_array_equal(by, 0.0)
+    np.testing.assert_allclose(th, delta / (4 * n), rtol=0, atol=0)
+
+
+# --------------------------------------------------------------------------------------
+# unitarity
+def test_collisions_and_streams_are_orthogonal():
+    rng = np.random.default_rng(3)
+    n = rng.uniform(1.0, 3.0, size=(6, 7))
+    q0 = rng.normal(size=(6, 6, 7))
+    for fwd, back in ((oracle.OP_CX, oracle.OP_CX_DAG), (oracle.OP_CY, oracle.OP_CY_DAG),
+                      (oracle.OP_S14_PX, oracle.OP_S14_MX), (oracle.OP_S25_PX, oracle.OP_S25_MX),
+                      (oracle.OP_S03_PY, oracle.OP_S03_MY), (oracle.OP_S25_PY, oracle.OP_S25_MY)):
+        q = q0.copy()
+        oracle.apply(fwd, q, n, 0.9)
+        assert abs(oracle.energy(q) / oracle.energy(q0) - 1) < 1e-14
+        oracle.apply(back, q, n, 0.9)
+        np.testing.assert_allclose(q, q0, atol=1e-14)
+
+
+@pytest.mark.parametrize("op", ["UX", "UY"])
+def test_collide_stream_preserves_norm_in_any_medium(op):
+    rng = np.random.default_rng(4)
+    n = rng.uniform(1.0, 3.0, size=(9, 11))       # arbitrary, even discontinuous, n
+    q = rng.normal(size=(6, 9, 11))
+    e0 = oracle.energy(q)
+    code = oracle.OP_UX if op == "UX" else oracle.OP_UY
+    for _ in range(50):
+        oracle.apply(code, q, n, 0.5)
+    assert abs(oracle.energy(q) / e0 - 1) < 1e-13
+
+
+def test_skew_half_step_conserves_energy_paper_step_does_not():
+    n = _smooth_random_index(24, 20, seed=5)
+    rng = np.random.default_rng(5)
+    q = rng.normal(size=(6, 20, 24))
+    e0 = oracle.energy(q)
+    q1 = oracle.advance(q.copy(), n, 0.5, 100, oracle.V_SKEW_HALF)
+    assert abs(oracle.energy(q1) / e0 - 1) < 1e-13
+    q2 = oracle.advance(q.copy(), n, 0.5, 100, oracle.V_PAPER)
+    assert abs(oracle.energy(q2) / e0 - 1) > 1e-6     # the printed potentials are not unitary
+
+
+# --------------------------------------------------------------------------------------
+# Fourier algebra and the continuum limit
+@pytest.mark.parametrize("which", ["UX", "UY", "STEP"])
+def test_oracle_reproduces_the_fourier_symbol_exactly(which):
+    nx, ny, nval, delta = 16, 12, 1.7, 0.3
+    kx, ky = 2 * np.pi * 3 / nx, 2 * np.pi * 2 / ny
+    theta = delta / (4 * nval)
+    if which == "UX":
+        M, code, steps = symbol.u_x(kx, theta), oracle.OP_UX, 1
+    elif which == "UY":
+        M, code, steps = symbol.u_y(ky, theta), oracle.OP_UY, 1
+    else:
+        M, code, steps = symbol.step(kx, ky, nval, delta), oracle.OP_STEP, 7
+    rng = np.random.default_rng(6)
+    v = rng.normal(size=6) + 1j * rng.normal(size=6)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    phase = np.exp(1j * (kx * X + ky * Y))
+    q = np.ascontiguousarray(np.real(v[:, None, None] * phase[None]))
+    n = np.full((ny, nx), nval)
+    for _ in range(steps):
+        oracle.apply(code, q, n, delta)
+    w = np.linalg.matrix_power(M, steps) @ v
+    expect = np.real(w[:, None, None] * phase[None])
+    np.testing.assert_allclose(q, expect, atol=1e-13)
+
+
+@pytest.mark.parametrize("K", [(3.0, 0.0), (0.0, 2.0), (2.0, 1.5)])
+def test_step_recovers_maxwell_to_second_order(K):
+    # U_y U_x = exp(delta^2 G + O(delta^4)) with G the symbol of Eqs. (2d1)-(2d6)
+    # (Eq. 2e7, 2e10: dt = delta^2, error O(delta^2) relative to the generator).
+    Kx, Ky = K
+    nval = 1.7
+    G = symbol.maxwell_generator(Kx, Ky, nval)
+    errs = []
+    for delta in (0.1, 0.05, 0.025, 0.0125):
+        M = symbol.step(Kx * delta, Ky * delta, nval, delta)
+        errs.append(np.abs(sla.logm(M) / delta ** 2 - G).max())
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.9 < r < 4.1 for r in ratios), ratios
+    assert errs[-1] < 1e-3 * np.abs(G).max()
+
+
+# --------------------------------------------------------------------------------------
+# free-space propagation (closed form: rigid translation at c = 1)
+def _centroid(e_x):
+    x = np.arange(e_x.size)
+    return float((x * e_x).sum() / e_x.sum())
+
+
+def test_vacuum_packet_moves_one_way_at_the_lattice_group_velocity():
+    nx, ny, delta, steps = 512, 1, 0.25, 600
+    lam, sigma, x0 = 16.0, 12.0, 100.0
+    n = np.ones((ny, nx))
+    q = oracle.packet(n, x0, 0.0, sigma, lam)
+    assert np.array_equal(q[4], -q[2])                      # one-way pairing for +x
+    e0 = oracle.energy(q)
+    oracle.advance(q, n, delta, steps)
+    e_x = (q ** 2).sum(axis=(0, 1))
+    # group velocity (cells per step) of the carrier from the exact symbol
+    k0, dk = 2 * np.pi / lam, 1e-4
+
+    def phase(k):
+        w = np.linalg.eigvals(symbol.step(k, 0.0, 1.0, delta))
+        return np.sort(np.abs(np.angle(w)))[-1]
+    vg = (phase(k0 + dk) - phase(k0 - dk)) / (2 * dk)
+    assert 0.9 * delta < vg < delta                         # ~ delta cos(k0)
+    shift = _centroid(e_x) - x0
+    assert abs(shift / (steps * vg) - 1) < 5e-3
+    back = e_x[: int(x0)].sum() / e_x.sum()                 # nothing moves towards -x
+    assert back < 1e-6
+    assert abs(e_x.sum() / e0 - 1) < 5e-12     # rounding of cos, sin only
+
+
+def _gauss_packet_phys(x, x0, sigma, lam):
+    return np.exp(-((x - x0) ** 2) / (2 * sigma ** 2)) * np.cos(2 * np.pi * (x - x0) / lam)
+
+
+def test_vacuum_translation_error_falls_at_second_order():
+    # Fixed physical problem on [0, 1): delta = 1 / N, steps = T / delta^2; the exact
+    # solution is the initial packet translated by T (c = 1).
+    T, x0, sigma, lam = 0.25, 0.3, 0.06, 0.15
+    errs = []
+    for N in (32, 64, 128, 256):
+        delta = 1.0 / N
+        x = np.arange(N) * delta
+        n = np.ones((1, N))
+        q = np.zeros((6, 1, N))
+        q[2, 0] = _gauss_packet_phys(x, x0, sigma, lam)
+        q[4, 0] = -q[2, 0]
+        oracle.advance(q, n, delta, int(round(T / delta ** 2)))
+        exact = _gauss_packet_phys(x, x0 + T, sigma, lam)
+        errs.append(np.linalg.norm(q[2, 0] - exact) / np.linalg.norm(exact))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert ratios[-1] > 3.7 and ratios[-2] > 3.3, (errs, ratios)
+
+
+# --------------------------------------------------------------------------------------
+# second-order convergence to the continuum equations in an inhomogeneous medium
+def _slab_phys(x, xa, xb, n_in, w):
+    return 1.0 + (n_in - 1.0) * 0.5 * (np.tanh((x - xa) / w) - np.tanh((x - xb) / w))
+
+
+def _run_slab(N, vmode, T):
+    delta = 1.0 / N
+    x = np.arange(N) * delta
+    n = _slab_phys(x, 0.45, 0.85, 2.0, 0.03)[None, :].copy()
+    q = np.zeros((6, 1, N))
+    q[2, 0] = n[0] * _gauss_packet_phys(x, 0.25, 0.06, 0.15)
+    q[4, 0] = -q[2, 0]
+    oracle.advance(q, n, delta, int(round(T / delta ** 2)), vmode)
+    return q
+
+
+@pytest.fixture(scope="module")
+def slab_reference():
+    T, Nref = 0.25, 2048
+    x = np.arange(Nref) / Nref
+    n = _slab_phys(x, 0.45, 0.85, 2.0, 0.03)[None, :].copy()
+    q = np.zeros((6, 1, Nref))
+    q[2, 0] = n[0] * _gauss_packet_phys(x, 0.25, 0.06, 0.15)
+    q[4, 0] = -q[2, 0]
+    return T, Nref, spectral.solve(q, n, 1.0, 1.0 / Nref, T)
+
+
+def _slab_errors(vmode, ref):
+    T, Nref, qref = ref
+    errs = []
+    for N in (64, 128, 256):
+        q = _run_slab(N, vmode, T)
+        r = qref[:, :, :: Nref // N][2:5]
+        errs.append(np.linalg.norm(q[2:5] - r) / np.linalg.norm(r))
+    return errs
+
+
+def test_skew_half_converges_at_second_order_through_a_dielectric_slab(slab_reference):
+    errs = _slab_errors(oracle.V_SKEW_HALF, slab_reference)
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert ratios[-1] > 3.6 and ratios[-2] > 2.5, (errs, ratios)
+    assert errs[-1] < 0.15
+
+
+def test_printed_potentials_do_not_converge(slab_reference):
+    # Recorded reading: with the potentials as printed (V_PAPER) the error stalls.
+    errs = _slab_errors(oracle.V_PAPER, slab_reference)
+    assert errs[-1] > 0.3 and errs[-2] / errs[-1] < 2.0, errs
+
+
+def test_skew_half_converges_in_2d_around_an_ellipse():
+    T, Nref = 0.06, 256
+    L = 1.0
+
+    def index(N):
+        c = (np.arange(N) + 0.0) / N
+        X, Y = np.meshgrid(c, c)
+        xp, yp = X - 0.5, Y - 0.5
+        rho2 = (xp / 0.2) ** 2 + (yp / 0.12) ** 2
+        return 1.0 + 0.5 * (1.0 - np.tanh((rho2 - 1.0) / 0.35))
+
+    def init(N, n):
+        c = np.arange(N) / N
+        X, _ = np.meshgrid(c, c)
+        q = np.zeros((6, N, N))
+        q[2] = n * _gauss_packet_phys(X, 0.3, 0.05, 0.12)
+        q[4] = -q[2]
+        return q
+
+    nref = index(Nref)
+    qref = spectral.solve(init(Nref, nref), nref, L, L, T)
+    errs = []
+    for N in (32, 64, 128):
+        n = index(N)
+        q = init(N, n)
+        oracle.advance(q, n, L / N, int(round(T * N * N)))
+        r = qref[:, :: Nref // N, :: Nref // N][2:5]
+        errs.append(np.linalg.norm(q[2:5] - r) / np.linalg.norm(r))
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert ratios[-1] > 3.3, (errs, ratios)
+
+
+# --------------------------------------------------------------------------------------
+# normal-incidence Fresnel reflectance (textbook special case)
+def _fresnel_run(vmode, width=0.5, lam=32.0, n2=2.0):
+    nx, delta = 1024, 0.5
+    x = np.arange(nx, dtype=float)
+    n = (1.0 + (n2 - 1.0) * 0.5 * (np.tanh((x - 512) / width) - np.tanh((x - 1000) / width)))
+    n = n[None, :].copy()
+    q = oracle.packet(n, 300.0, 0.0, 1.5 * lam, lam)
+    e0 = oracle.energy(q)
+    oracle.advance(q, n, delta, 900, vmode)
+    e_x = (q ** 2).sum(axis=(0, 1))
+    refl = e_x[:512].sum() / e0
+    trans = e_x[512:1000].sum() / e0
+    return refl, trans
+
+
+def test_normal_incidence_reflectance_is_fresnel():
+    r, t = _fresnel_run(oracle.V_SKEW_HALF)
+    r_exact = ((2.0 - 1.0) / (2.0 + 1.0)) ** 2                 # 1/9
+    assert abs(r / r_exact - 1) < 0.06, r
+    assert abs(r + t - 1) < 1e-6
+    # without the potentials the gradient terms of Eqs. (2d4)-(2d5) are half missing and
+    # almost nothing reflects; the printed potentials create energy (R + T far above 1)
+    r0, _ = _fresnel_run(oracle.V_NONE)
+    assert r0 < 0.05 * r_exact
+    rp, tp = _fresnel_run(oracle.V_PAPER)
+    assert rp + tp > 1.5
