@@ -1,0 +1,161 @@
+/*
+ * qla.h - C ABI of the MI355X (gfx950) qubit lattice algorithm (QLA) library for
+ * the 2D Maxwell equations in an isotropic inhomogeneous dielectric n(x, y).
+ *
+ * Method: Soe, Ram, Koukoutsis, Vahala, Vahala & Hizanidis, "Quantum Computing
+ * Framework for Transient Scattering of Electromagnetic Waves by Dielectric
+ * Structures". One time step is Eq. (2e14): Q(t + dt) = V_y V_x U_y U_x Q(t),
+ * with the collide-stream sequences U_x (Eq. 2e6) and U_y (Eq. 2e9) built from
+ * the collisions C_x (Eq. 2e3), C_y (Eq. 2e8) and the streaming operators of
+ * Eq. (2e5), and the refractive-index potentials V_x, V_y (Eqs. 2e11-2e13).
+ *
+ * State. The qubit vector is Q = (n Ex, n Ey, n Ez, Bx, By, Bz) = (q0..q5)
+ * (Eq. 3b3, c = 1, t -> ct). This library evolves the E_z polarisation: the
+ * triple (q2, q3, q4) = (n Ez, Bx, By), which the operators of Eq. (2e14) never
+ * couple to (q0, q1, q5); those stay zero for an E_z packet. Every field array
+ * that crosses this ABI is a set of 3 planes ordered (q2, q3, q4) - or
+ * (Ez, Bx, By) for physical readout - each plane row-major [y][x] with x
+ * fastest, nx * ny doubles, planes contiguous one after another.
+ *
+ * Lattice. nx * ny sites, periodic in x and y, spacing delta (physical units);
+ * one step advances time by delta^2 (Section IV, "diffusion ordering"), so light
+ * in vacuum crosses delta cells per step. Collision angle theta = delta / (4 n)
+ * (Eq. 2e4); potential angles beta = delta^2 (dn/dx) / n^2 (Eq. 2e13) with
+ * centred differences of the sampled n.
+ *
+ * Ownership. A context owns all device memory it allocates; host arrays passed
+ * in are copied and remain owned by the caller; device pointers passed in
+ * (the *_device calls) are read or written on the context's stream and remain
+ * owned by the caller.
+ *
+ * Errors. Every call returns a qla_status. Nothing throws across the ABI. On an
+ * error the context's state is unchanged, except QLA_EDEVICE, after which the
+ * context should be destroyed. qla_last_error() gives a message for the last
+ * failing call on the calling thread.
+ *
+ * Streams. Work is enqueued on the context's HIP stream (given at creation, or a
+ * library-owned stream). qla_advance, qla_init_packet, qla_set_index_device,
+ * qla_get_fields_device and qla_energy_device are asynchronous; the calls that
+ * return host data synchronise the stream. One context must not be used from
+ * two threads at once.
+ */
+#ifndef QLA_H
+#define QLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qla_ctx qla_ctx;
+
+typedef enum {
+    QLA_OK = 0,
+    QLA_EINVAL = -1,   /* bad argument (size, pointer, value); nothing was changed */
+    QLA_ENOMEM = -2,   /* device or host allocation failed */
+    QLA_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed */
+    QLA_ESTATE = -4    /* call out of order (e.g. advance before the index is set) */
+} qla_status;
+
+typedef enum {
+    QLA_F64 = 0,  /* amplitudes stored and stepped in FP64 */
+    QLA_F32 = 1   /* amplitudes stored and stepped in FP32; energy always in FP64 */
+} qla_precision;
+
+/* Potential operators V_x, V_y of Eq. (2e14). */
+typedef enum {
+    /* Default. Unitary half-angle rotations V_x = C_x(theta2 -> -beta2/2),
+     * V_y = C_y(theta2 -> -beta3/2): with site-dependent collision angles the
+     * unitary U_x, U_y recover the symmetrised operator (1/2)[(1/n)d + d(1/n)];
+     * these rotations add the skew remainder that yields Eqs. (2d3)-(2d5)
+     * exactly to second order, and conserve the energy of Eq. (A13). */
+    QLA_V_SKEW_HALF = 0,
+    /* Eqs. (2e11)-(2e12) as printed, with V_y's q3 row read as
+     * (0, 0, sin b3, cos b3, 0, 0) so that V_y = I when n is uniform. Not
+     * unitary; kept for comparison. */
+    QLA_V_PAPER = 1,
+    /* Potentials off: the homogeneous-medium scheme of Eq. (2e10). */
+    QLA_V_NONE = 2
+} qla_potential;
+
+/* Gaussian-envelope plane-wave packet in E_z (Section V, initial conditions):
+ * Ez0 = amp * exp(-r^2 / (2 sigma^2)) * cos(2 pi s / lambda), where s is the
+ * minimum-image displacement from (x0, y0) (cells) projected on the direction of
+ * travel phi (radians, 0 = +x) and r = s if planar != 0 (uniform across the
+ * direction of travel, the paper's 1D packet), else the full minimum-image
+ * distance. The paired magnetic field is that of a wave travelling one way along
+ * phi in a uniform medium: q2 = n Ez0, q3 = q2 sin(phi), q4 = -q2 cos(phi). */
+typedef struct {
+    double x0, y0, sigma, lambda, phi, amp;
+    int planar;
+} qla_packet;
+
+/* Create a context for an nx-by-ny periodic lattice with spacing delta.
+ * nx, ny >= 8 (the step reads 4 neighbours on each side), nx * ny < 2^31,
+ * delta > 0 and finite. hip_stream: a hipStream_t to enqueue on, or NULL for a
+ * library-owned stream. Allocates the amplitude planes (two buffers), the index
+ * planes and small scratch; the state starts at zero with no index set. */
+qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
+                      qla_potential potential, void *hip_stream, qla_ctx **out);
+
+/* Set n(x, y) from a host array of ny rows of nx doubles, row stride ld >= nx
+ * (elements). Computes the coefficients of Eqs. (2e4) and (2e13) in FP64 on the
+ * GPU and checks them: every n must be finite and > 0, and the collision and
+ * potential rotation angles must not exceed 0.5 rad (QLA_EINVAL otherwise).
+ * Synchronises. Resets the step counter; the amplitudes are kept. */
+qla_status qla_set_index(qla_ctx *ctx, const double *n_host, size_t ld);
+
+/* As qla_set_index, from device memory (ny rows of nx doubles, stride ld). */
+qla_status qla_set_index_device(qla_ctx *ctx, const double *n_device, size_t ld);
+
+/* Fill the amplitudes with the packet of qla_packet on the current n
+ * (QLA_ESTATE if no index is set). Resets the step counter. Asynchronous. */
+qla_status qla_init_packet(qla_ctx *ctx, const qla_packet *packet);
+
+/* Replace the amplitudes by 3 host planes (q2, q3, q4) in FP64 (rounded to FP32
+ * in QLA_F32 mode): checkpoint restore. Resets the step counter to `step`. */
+qla_status qla_set_fields(qla_ctx *ctx, const double *q_host, int64_t step);
+
+/* Advance k >= 0 full steps of Eq. (2e14). Asynchronous. */
+qla_status qla_advance(qla_ctx *ctx, int64_t k);
+
+/* Copy the state to 3 host planes in FP64: (q2, q3, q4) if physical == 0,
+ * else (Ez, Bx, By) = (q2 / n, q3, q4). Synchronises. */
+qla_status qla_get_fields(qla_ctx *ctx, double *out_host, int physical);
+
+/* As qla_get_fields into 3 device planes (3 * nx * ny doubles). Asynchronous. */
+qla_status qla_get_fields_device(qla_ctx *ctx, double *out_device, int physical);
+
+/* Energy of Eq. (A13): the sum over sites of q2^2 + q3^2 + q4^2, accumulated in
+ * FP64 in a fixed order (bitwise reproducible). Synchronises. */
+qla_status qla_energy(qla_ctx *ctx, double *energy);
+
+/* As qla_energy, written to one device double. Asynchronous. */
+qla_status qla_energy_device(qla_ctx *ctx, double *energy_device);
+
+/* Per-site FP64 coefficients the step uses, copied to host arrays of nx * ny
+ * (any pointer may be NULL): theta = delta / (4 n) (Eq. 2e4) and
+ * beta_x, beta_y = delta^2 (dn/dx, dn/dy) / n^2 (Eq. 2e13), centred differences.
+ * Synchronises. QLA_ESTATE if no index is set. */
+qla_status qla_get_coefficients(qla_ctx *ctx, double *theta, double *beta_x, double *beta_y);
+
+/* Number of steps taken since the last reset. */
+qla_status qla_step_count(const qla_ctx *ctx, int64_t *steps);
+
+/* Tuning of the step kernel: output rows per wavefront segment (multiple of 8,
+ * >= 8, or 0 for the default). */
+qla_status qla_set_tuning(qla_ctx *ctx, int rows_per_segment);
+
+/* Release every resource of the context (NULL is accepted). Synchronises. */
+qla_status qla_destroy(qla_ctx *ctx);
+
+const char *qla_strerror(qla_status status);
+const char *qla_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QLA_H */

@@ -1,0 +1,383 @@
+// C ABI of the QLA library (declared in include/qla.h): context lifetime, argument
+// checks, device memory and the order of kernel launches on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+
+#include "qla.h"
+#include "qla_internal.h"
+
+struct qla_ctx {
+  int nx = 0, ny = 0;
+  double delta = 0.0;
+  bool fp32 = false;
+  int vmode = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* q[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  int cur = 0;
+  double* n64 = nullptr;
+  float* n32 = nullptr;
+  double* staging = nullptr;  // 3 * nx * ny doubles
+  double* partials = nullptr;
+  double* energy_dev = nullptr;
+  unsigned long long* stats = nullptr;
+  int64_t steps = 0;
+  bool have_index = false;
+  int angle_class = 0;
+  int rows_per_seg = 120;
+  size_t count() const { return static_cast<size_t>(nx) * static_cast<size_t>(ny); }
+  size_t elem() const { return fp32 ? sizeof(float) : sizeof(double); }
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qla_status fail(qla_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+qla_status hip_fail(hipError_t e, const char* what) {
+  return fail(QLA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QLA_HIP(call)                               \
+  do {                                              \
+    const hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+// Makes the context's device current for the duration of a call.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    ok_ = hipGetDevice(&prev_) == hipSuccess;
+    if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int now = prev_;
+    if (hipGetDevice(&now) == hipSuccess && now != prev_) (void)hipSetDevice(prev_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = 0;
+  bool ok_ = false;
+};
+
+void release(qla_ctx* c) {
+  for (auto& buf : c->q)
+    for (auto& p : buf)
+      if (p) (void)hipFree(p);
+  if (c->n64) (void)hipFree(c->n64);
+  if (c->n32) (void)hipFree(c->n32);
+  if (c->staging) (void)hipFree(c->staging);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->energy_dev) (void)hipFree(c->energy_dev);
+  if (c->stats) (void)hipFree(c->stats);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+qla_status alloc(void** p, size_t bytes, const char* what) {
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(QLA_ENOMEM, std::string("hipMalloc(") + what + "): " + hipGetErrorString(e));
+  }
+  return QLA_OK;
+}
+
+// Validates the index held in the scratch planes (raw input already copied there
+// or readable at src) and installs it.
+qla_status install_index(qla_ctx* c, const double* src, size_t ld) {
+  const size_t N = c->count();
+  double* n_new = c->staging + N;
+  float* n32_new = c->fp32 ? reinterpret_cast<float*>(c->staging + 2 * N) : nullptr;
+  const unsigned long long init[3] = {0ull, 0x7FF0000000000000ull, 0ull};  // 0, +inf, 0
+  QLA_HIP(hipMemcpyAsync(c->stats, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+  QLA_HIP(qla::launch_index_prepare(src, ld, c->nx, c->ny, c->delta, n_new, n32_new, c->stats,
+                                    c->stream));
+  unsigned long long got[3];
+  QLA_HIP(hipMemcpyAsync(got, c->stats, sizeof(got), hipMemcpyDeviceToHost, c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  if (got[0] != 0)
+    return fail(QLA_EINVAL, "refractive index: " + std::to_string(got[0]) +
+                                " entries are not finite or not > 0");
+  double nmin, hb;
+  std::memcpy(&nmin, &got[1], sizeof(double));
+  std::memcpy(&hb, &got[2], sizeof(double));
+  const double theta = c->delta / (4.0 * nmin);
+  int cls;
+  if (theta <= 1.0 / 16.0 && hb <= 1.0 / 16.0) {
+    cls = 0;
+  } else if (theta <= 0.5 && hb <= 0.5) {
+    cls = 1;
+  } else {
+    return fail(QLA_EINVAL, "lattice angles too large: max collision angle delta/(4n) = " +
+                                std::to_string(theta) + ", max potential half-angle = " +
+                                std::to_string(hb) + " (both must be <= 0.5 rad)");
+  }
+  QLA_HIP(hipMemcpyAsync(c->n64, n_new, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (c->fp32)
+    QLA_HIP(hipMemcpyAsync(c->n32, n32_new, N * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  c->angle_class = cls;
+  c->have_index = true;
+  c->steps = 0;
+  return QLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qla_strerror(qla_status s) {
+  switch (s) {
+    case QLA_OK: return "success";
+    case QLA_EINVAL: return "invalid argument";
+    case QLA_ENOMEM: return "out of memory";
+    case QLA_EDEVICE: return "HIP device error";
+    case QLA_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* qla_last_error(void) { return g_last_error.c_str(); }
+
+qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
+                      qla_potential potential, void* hip_stream, qla_ctx** out) {
+  if (!out) return fail(QLA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nx < 8 || ny < 8) return fail(QLA_EINVAL, "nx and ny must be >= 8");
+  if (static_cast<long long>(nx) * ny >= (1ll << 31))
+    return fail(QLA_EINVAL, "nx * ny must be < 2^31");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(QLA_EINVAL, "delta must be > 0");
+  if (precision != QLA_F64 && precision != QLA_F32) return fail(QLA_EINVAL, "bad precision");
+  if (potential != QLA_V_SKEW_HALF && potential != QLA_V_PAPER && potential != QLA_V_NONE)
+    return fail(QLA_EINVAL, "bad potential mode");
+  qla_ctx* c = new (std::nothrow) qla_ctx;
+  if (!c) return fail(QLA_ENOMEM, "host allocation");
+  c->nx = nx;
+  c->ny = ny;
+  c->delta = delta;
+  c->fp32 = precision == QLA_F32;
+  c->vmode = static_cast<int>(potential);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    c->own_stream = true;
+  }
+  const size_t N = c->count();
+  qla_status st = QLA_OK;
+  for (int b = 0; b < 2 && st == QLA_OK; ++b)
+    for (int k = 0; k < 3 && st == QLA_OK; ++k) st = alloc(&c->q[b][k], N * c->elem(), "amplitudes");
+  if (st == QLA_OK) st = alloc(reinterpret_cast<void**>(&c->n64), N * sizeof(double), "index");
+  if (st == QLA_OK && c->fp32)
+    st = alloc(reinterpret_cast<void**>(&c->n32), N * sizeof(float), "index fp32");
+  if (st == QLA_OK)
+    st = alloc(reinterpret_cast<void**>(&c->staging), 3 * N * sizeof(double), "staging");
+  if (st == QLA_OK)
+    st = alloc(reinterpret_cast<void**>(&c->partials), qla::kEnergyPartials * sizeof(double),
+               "partials");
+  if (st == QLA_OK) st = alloc(reinterpret_cast<void**>(&c->energy_dev), sizeof(double), "energy");
+  if (st == QLA_OK)
+    st = alloc(reinterpret_cast<void**>(&c->stats), 4 * sizeof(unsigned long long), "stats");
+  if (st == QLA_OK) {
+    for (int k = 0; k < 3 && st == QLA_OK; ++k) {
+      e = hipMemsetAsync(c->q[0][k], 0, N * c->elem(), c->stream);
+      if (e != hipSuccess) st = hip_fail(e, "hipMemsetAsync");
+    }
+    if (st == QLA_OK) {
+      e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+  }
+  if (st != QLA_OK) {
+    release(c);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return QLA_OK;
+}
+
+qla_status qla_destroy(qla_ctx* c) {
+  if (!c) return QLA_OK;
+  DeviceGuard g(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  release(c);
+  delete c;
+  return QLA_OK;
+}
+
+qla_status qla_set_index(qla_ctx* c, const double* n_host, size_t ld) {
+  if (!c || !n_host) return fail(QLA_EINVAL, "NULL argument");
+  if (ld < static_cast<size_t>(c->nx)) return fail(QLA_EINVAL, "ld < nx");
+  DeviceGuard g(c->device);
+  if (!g.ok()) return fail(QLA_EDEVICE, "cannot select the context's device");
+  // raw rows into the first staging plane (packed), then validate from there
+  QLA_HIP(hipMemcpy2DAsync(c->staging, c->nx * sizeof(double), n_host, ld * sizeof(double),
+                           c->nx * sizeof(double), c->ny, hipMemcpyHostToDevice, c->stream));
+  return install_index(c, c->staging, c->nx);
+}
+
+qla_status qla_set_index_device(qla_ctx* c, const double* n_device, size_t ld) {
+  if (!c || !n_device) return fail(QLA_EINVAL, "NULL argument");
+  if (ld < static_cast<size_t>(c->nx)) return fail(QLA_EINVAL, "ld < nx");
+  DeviceGuard g(c->device);
+  if (!g.ok()) return fail(QLA_EDEVICE, "cannot select the context's device");
+  return install_index(c, n_device, ld);
+}
+
+qla_status qla_init_packet(qla_ctx* c, const qla_packet* p) {
+  if (!c || !p) return fail(QLA_EINVAL, "NULL argument");
+  if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
+  if (!(p->sigma > 0.0) || !(p->lambda > 0.0) || !std::isfinite(p->x0) || !std::isfinite(p->y0) ||
+      !std::isfinite(p->phi) || !std::isfinite(p->amp) || !std::isfinite(p->sigma) ||
+      !std::isfinite(p->lambda))
+    return fail(QLA_EINVAL, "packet: sigma and lambda must be > 0 and all fields finite");
+  DeviceGuard g(c->device);
+  qla::PacketArgs a{p->x0, p->y0, p->sigma, p->lambda, p->phi, p->amp, p->planar};
+  QLA_HIP(qla::launch_packet(c->n64, c->nx, c->ny, a, c->fp32, c->q[c->cur][0], c->q[c->cur][1],
+                             c->q[c->cur][2], c->stream));
+  c->steps = 0;
+  return QLA_OK;
+}
+
+qla_status qla_set_fields(qla_ctx* c, const double* q_host, int64_t step) {
+  if (!c || !q_host) return fail(QLA_EINVAL, "NULL argument");
+  if (step < 0) return fail(QLA_EINVAL, "step < 0");
+  DeviceGuard g(c->device);
+  const size_t N = c->count();
+  QLA_HIP(hipMemcpyAsync(c->staging, q_host, 3 * N * sizeof(double), hipMemcpyHostToDevice,
+                         c->stream));
+  QLA_HIP(qla::launch_from_f64(c->staging, N, c->fp32, c->q[c->cur][0], c->q[c->cur][1],
+                               c->q[c->cur][2], c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  c->steps = step;
+  return QLA_OK;
+}
+
+qla_status qla_advance(qla_ctx* c, int64_t k) {
+  if (!c) return fail(QLA_EINVAL, "NULL context");
+  if (k < 0) return fail(QLA_EINVAL, "k < 0");
+  if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
+  DeviceGuard g(c->device);
+  qla::StepLaunch L{};
+  L.n = c->fp32 ? static_cast<const void*>(c->n32) : static_cast<const void*>(c->n64);
+  L.nx = c->nx;
+  L.ny = c->ny;
+  L.rows_per_seg = c->rows_per_seg;
+  L.delta = c->delta;
+  L.fp32 = c->fp32;
+  L.vmode = c->vmode;
+  L.angle_class = c->angle_class;
+  for (int64_t s = 0; s < k; ++s) {
+    for (int j = 0; j < 3; ++j) {
+      L.in[j] = c->q[c->cur][j];
+      L.out[j] = c->q[c->cur ^ 1][j];
+    }
+    QLA_HIP(qla::launch_step(L, c->stream));
+    c->cur ^= 1;
+    ++c->steps;
+  }
+  return QLA_OK;
+}
+
+qla_status qla_get_fields_device(qla_ctx* c, double* out, int physical) {
+  if (!c || !out) return fail(QLA_EINVAL, "NULL argument");
+  if (physical && !c->have_index) return fail(QLA_ESTATE, "physical readout needs the index");
+  DeviceGuard g(c->device);
+  QLA_HIP(qla::launch_readout(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->n64,
+                              c->count(), c->fp32, physical, out, c->stream));
+  return QLA_OK;
+}
+
+qla_status qla_get_fields(qla_ctx* c, double* out_host, int physical) {
+  if (!c || !out_host) return fail(QLA_EINVAL, "NULL argument");
+  if (physical && !c->have_index) return fail(QLA_ESTATE, "physical readout needs the index");
+  DeviceGuard g(c->device);
+  QLA_HIP(qla::launch_readout(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->n64,
+                              c->count(), c->fp32, physical, c->staging, c->stream));
+  QLA_HIP(hipMemcpyAsync(out_host, c->staging, 3 * c->count() * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  return QLA_OK;
+}
+
+qla_status qla_energy_device(qla_ctx* c, double* energy_device) {
+  if (!c || !energy_device) return fail(QLA_EINVAL, "NULL argument");
+  DeviceGuard g(c->device);
+  QLA_HIP(qla::launch_energy(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->count(),
+                             c->fp32, c->partials, energy_device, c->stream));
+  return QLA_OK;
+}
+
+qla_status qla_energy(qla_ctx* c, double* energy) {
+  if (!c || !energy) return fail(QLA_EINVAL, "NULL argument");
+  DeviceGuard g(c->device);
+  QLA_HIP(qla::launch_energy(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->count(),
+                             c->fp32, c->partials, c->energy_dev, c->stream));
+  QLA_HIP(hipMemcpyAsync(energy, c->energy_dev, sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  return QLA_OK;
+}
+
+qla_status qla_get_coefficients(qla_ctx* c, double* theta, double* beta_x, double* beta_y) {
+  if (!c) return fail(QLA_EINVAL, "NULL context");
+  if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
+  DeviceGuard g(c->device);
+  const size_t N = c->count();
+  double* s = c->staging;
+  QLA_HIP(qla::launch_coefficients(c->n64, c->nx, c->ny, c->delta, s, s + N, s + 2 * N,
+                                   c->stream));
+  double* dst[3] = {theta, beta_x, beta_y};
+  for (int k = 0; k < 3; ++k)
+    if (dst[k])
+      QLA_HIP(hipMemcpyAsync(dst[k], s + k * N, N * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  return QLA_OK;
+}
+
+qla_status qla_step_count(const qla_ctx* c, int64_t* steps) {
+  if (!c || !steps) return fail(QLA_EINVAL, "NULL argument");
+  *steps = c->steps;
+  return QLA_OK;
+}
+
+qla_status qla_set_tuning(qla_ctx* c, int rows_per_segment) {
+  if (!c) return fail(QLA_EINVAL, "NULL context");
+  const int gran = qla::step_rows_granularity();
+  if (rows_per_segment == 0) {
+    c->rows_per_seg = 120;
+    return QLA_OK;
+  }
+  if (rows_per_segment < gran || rows_per_segment % gran != 0)
+    return fail(QLA_EINVAL, "rows_per_segment must be a positive multiple of " +
+                                std::to_string(gran));
+  c->rows_per_seg = rows_per_segment;
+  return QLA_OK;
+}
+
+}  // extern "C"

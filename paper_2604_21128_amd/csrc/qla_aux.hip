@@ -1,0 +1,307 @@
+// Set-up, diagnostic and readout kernels around the fused step: index preparation
+// and checks, the per-site coefficients of Eqs. (2e4) and (2e13), the initial
+// packet, the energy of Eq. (A13) and field readout.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "qla_device.h"
+#include "qla_internal.h"
+
+namespace qla {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ unsigned long long bits(double v) {
+  return __builtin_bit_cast(unsigned long long, v);
+}
+
+// Reduce within the block; for non-negative doubles, the order of the bit patterns
+// as unsigned integers is the order of the values.
+template <typename Op>
+__device__ unsigned long long block_reduce_u64(unsigned long long v, Op op,
+                                               unsigned long long* lds) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = op(v, o);
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) lds[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < static_cast<int>(blockDim.x >> 6); ++i) v = op(v, lds[i]);
+  }
+  return v;
+}
+
+struct MinOp {
+  __device__ unsigned long long operator()(unsigned long long a, unsigned long long b) const {
+    return a < b ? a : b;
+  }
+};
+struct MaxOp {
+  __device__ unsigned long long operator()(unsigned long long a, unsigned long long b) const {
+    return a > b ? a : b;
+  }
+};
+struct AddOp {
+  __device__ unsigned long long operator()(unsigned long long a, unsigned long long b) const {
+    return a + b;
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void index_copy_kernel(const double* __restrict__ src,
+                                                            size_t ld, int nx, int ny,
+                                                            double* __restrict__ n64,
+                                                            float* __restrict__ n32,
+                                                            unsigned long long* stats) {
+  __shared__ unsigned long long lds[kBlock / 64];
+  const size_t count = static_cast<size_t>(nx) * ny;
+  unsigned long long bad = 0, nmin = bits(INFINITY);
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    const size_t y = i / nx, x = i - y * nx;
+    const double v = src[y * ld + x];
+    n64[i] = v;
+    if (n32) n32[i] = static_cast<float>(v);
+    if (!(v > 0.0) || !isfinite(v)) {
+      ++bad;
+    } else if (bits(v) < nmin) {
+      nmin = bits(v);
+    }
+  }
+  bad = block_reduce_u64(bad, AddOp{}, lds);
+  __syncthreads();
+  nmin = block_reduce_u64(nmin, MinOp{}, lds);
+  if (threadIdx.x == 0) {
+    if (bad) atomicAdd(&stats[0], bad);
+    atomicMin(&stats[1], nmin);
+  }
+}
+
+// beta/2 along x and y exactly as the step computes it.
+__device__ __forceinline__ void half_betas(const double* __restrict__ n, int nx, int ny, int x,
+                                           int y, double d4, double& hbx, double& hby,
+                                           double& m) {
+  const size_t row = static_cast<size_t>(y) * nx;
+  const int xl = x == 0 ? nx - 1 : x - 1, xr = x + 1 == nx ? 0 : x + 1;
+  const int yl = y == 0 ? ny - 1 : y - 1, yr = y + 1 == ny ? 0 : y + 1;
+  m = recip(n[row + x]);
+  const double dm = d4 * m * m;
+  hbx = (n[row + xr] - n[row + xl]) * dm;
+  hby = (n[static_cast<size_t>(yr) * nx + x] - n[static_cast<size_t>(yl) * nx + x]) * dm;
+}
+
+__global__ __launch_bounds__(kBlock) void index_beta_max_kernel(const double* __restrict__ n64,
+                                                                int nx, int ny, double d4,
+                                                                unsigned long long* stats) {
+  __shared__ unsigned long long lds[kBlock / 64];
+  const size_t count = static_cast<size_t>(nx) * ny;
+  unsigned long long mx = 0;
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
+    double hbx, hby, m;
+    half_betas(n64, nx, ny, x, y, d4, hbx, hby, m);
+    const double a = fmax(fabs(hbx), fabs(hby));
+    const unsigned long long b = isfinite(a) ? bits(a) : bits(INFINITY);
+    mx = b > mx ? b : mx;
+  }
+  mx = block_reduce_u64(mx, MaxOp{}, lds);
+  if (threadIdx.x == 0) atomicMax(&stats[2], mx);
+}
+
+__global__ __launch_bounds__(kBlock) void coefficients_kernel(const double* __restrict__ n64,
+                                                              int nx, int ny, double d4,
+                                                              double* theta, double* bx,
+                                                              double* by) {
+  const size_t count = static_cast<size_t>(nx) * ny;
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
+    double hbx, hby, m;
+    half_betas(n64, nx, ny, x, y, d4, hbx, hby, m);
+    if (theta) theta[i] = d4 * m;
+    if (bx) bx[i] = hbx + hbx;
+    if (by) by[i] = hby + hby;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void packet_kernel(const double* __restrict__ n64, int nx,
+                                                        int ny, PacketArgs p, T* q2, T* q3,
+                                                        T* q4) {
+  const size_t count = static_cast<size_t>(nx) * ny;
+  const double kx = cos(p.phi), ky = sin(p.phi);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
+    double dx = x - p.x0, dy = y - p.y0;
+    dx -= nx * floor(dx / nx + 0.5);
+    dy -= ny * floor(dy / ny + 0.5);
+    const double s = dx * kx + dy * ky;
+    const double r2 = p.planar ? s * s : dx * dx + dy * dy;
+    const double ez = p.amp * exp(-r2 / (2.0 * p.sigma * p.sigma)) * cos(two_pi * s / p.lambda);
+    const double a = n64[i] * ez;
+    q2[i] = static_cast<T>(a);
+    q3[i] = static_cast<T>(a * ky);
+    q4[i] = static_cast<T>(-a * kx);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void energy_partial_kernel(const T* __restrict__ q2,
+                                                                const T* __restrict__ q3,
+                                                                const T* __restrict__ q4,
+                                                                size_t count, double* partials) {
+  __shared__ double lds[kBlock];
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    const double a = q2[i], b = q3[i], c = q4[i];
+    acc = fma(a, a, acc);
+    acc = fma(b, b, acc);
+    acc = fma(c, c, acc);
+  }
+  lds[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = lds[0];
+}
+
+__global__ __launch_bounds__(kEnergyPartials) void energy_final_kernel(const double* partials,
+                                                                       double* out) {
+  __shared__ double lds[kEnergyPartials];
+  lds[threadIdx.x] = partials[threadIdx.x];
+  __syncthreads();
+  for (int s = kEnergyPartials / 2; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = lds[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void readout_kernel(const T* __restrict__ q2,
+                                                         const T* __restrict__ q3,
+                                                         const T* __restrict__ q4,
+                                                         const double* __restrict__ n64,
+                                                         size_t count, int physical,
+                                                         double* __restrict__ out) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    const double a = q2[i];
+    out[i] = physical ? a / n64[i] : a;
+    out[count + i] = q3[i];
+    out[2 * count + i] = q4[i];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void from_f64_kernel(const double* __restrict__ src,
+                                                          size_t count, T* q2, T* q3, T* q4) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    q2[i] = static_cast<T>(src[i]);
+    q3[i] = static_cast<T>(src[count + i]);
+    q4[i] = static_cast<T>(src[2 * count + i]);
+  }
+}
+
+unsigned grid_for(size_t count) {
+  const size_t blocks = (count + kBlock - 1) / kBlock;
+  return static_cast<unsigned>(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
+}
+
+}  // namespace
+
+hipError_t launch_index_prepare(const double* src, size_t ld, int nx, int ny, double delta,
+                                double* n64, float* n32, unsigned long long* stats,
+                                hipStream_t stream) {
+  const size_t count = static_cast<size_t>(nx) * ny;
+  hipLaunchKernelGGL(index_copy_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, src, ld,
+                     nx, ny, n64, n32, stats);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(index_beta_max_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64,
+                     nx, ny, 0.25 * delta, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_coefficients(const double* n64, int nx, int ny, double delta, double* theta,
+                               double* beta_x, double* beta_y, hipStream_t stream) {
+  const size_t count = static_cast<size_t>(nx) * ny;
+  hipLaunchKernelGGL(coefficients_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64, nx,
+                     ny, 0.25 * delta, theta, beta_x, beta_y);
+  return hipGetLastError();
+}
+
+hipError_t launch_packet(const double* n64, int nx, int ny, const PacketArgs& p, bool fp32,
+                         void* q2, void* q3, void* q4, hipStream_t stream) {
+  const size_t count = static_cast<size_t>(nx) * ny;
+  if (fp32) {
+    hipLaunchKernelGGL(packet_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64,
+                       nx, ny, p, static_cast<float*>(q2), static_cast<float*>(q3),
+                       static_cast<float*>(q4));
+  } else {
+    hipLaunchKernelGGL(packet_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64,
+                       nx, ny, p, static_cast<double*>(q2), static_cast<double*>(q3),
+                       static_cast<double*>(q4));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const void* q2, const void* q3, const void* q4, size_t count, bool fp32,
+                         double* partials, double* out, hipStream_t stream) {
+  if (fp32) {
+    hipLaunchKernelGGL(energy_partial_kernel<float>, dim3(kEnergyPartials), dim3(kBlock), 0,
+                       stream, static_cast<const float*>(q2), static_cast<const float*>(q3),
+                       static_cast<const float*>(q4), count, partials);
+  } else {
+    hipLaunchKernelGGL(energy_partial_kernel<double>, dim3(kEnergyPartials), dim3(kBlock), 0,
+                       stream, static_cast<const double*>(q2), static_cast<const double*>(q3),
+                       static_cast<const double*>(q4), count, partials);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kEnergyPartials), 0, stream, partials,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_readout(const void* q2, const void* q3, const void* q4, const double* n64,
+                          size_t count, bool fp32, int physical, double* out,
+                          hipStream_t stream) {
+  if (fp32) {
+    hipLaunchKernelGGL(readout_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
+                       static_cast<const float*>(q2), static_cast<const float*>(q3),
+                       static_cast<const float*>(q4), n64, count, physical, out);
+  } else {
+    hipLaunchKernelGGL(readout_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
+                       static_cast<const double*>(q2), static_cast<const double*>(q3),
+                       static_cast<const double*>(q4), n64, count, physical, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_from_f64(const double* src, size_t count, bool fp32, void* q2, void* q3,
+                           void* q4, hipStream_t stream) {
+  if (fp32) {
+    hipLaunchKernelGGL(from_f64_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
+                       src, count, static_cast<float*>(q2), static_cast<float*>(q3),
+                       static_cast<float*>(q4));
+  } else {
+    hipLaunchKernelGGL(from_f64_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
+                       src, count, static_cast<double*>(q2), static_cast<double*>(q3),
+                       static_cast<double*>(q4));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qla

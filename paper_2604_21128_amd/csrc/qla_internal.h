@@ -1,0 +1,62 @@
+// Internal interface between the C ABI (qla_api.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qla {
+
+enum VMode : int { kVSkewHalf = 0, kVPaper = 1, kVNone = 2 };
+
+// One fused step (qla_step.hip): three amplitude planes in, three out, n in the
+// stepping precision; all planes nx * ny, row pitch nx.
+struct StepLaunch {
+  const void* in[3];
+  void* out[3];
+  const void* n;
+  int nx, ny;
+  int rows_per_seg;
+  double delta;
+  bool fp32;
+  int vmode;
+  int angle_class;
+};
+hipError_t launch_step(const StepLaunch& L, hipStream_t stream);
+int step_rows_granularity();
+
+// Index preparation (qla_aux.hip): copy n (row pitch ld) into the packed FP64
+// plane n64 (and its FP32 rounding n32 when non-null), and accumulate into
+// stats[0] the number of entries that are not finite or not > 0, into stats[1]
+// the bit pattern of the smallest n and into stats[2] the bit pattern of the
+// largest |beta/2| over both axes. stats must be preset to {0, +inf, 0}.
+hipError_t launch_index_prepare(const double* src, size_t ld, int nx, int ny, double delta,
+                                double* n64, float* n32, unsigned long long* stats,
+                                hipStream_t stream);
+
+// theta = delta / (4 n), beta_x, beta_y = delta^2 (dn/dx, dn/dy) / n^2 (FP64).
+hipError_t launch_coefficients(const double* n64, int nx, int ny, double delta, double* theta,
+                               double* beta_x, double* beta_y, hipStream_t stream);
+
+struct PacketArgs {
+  double x0, y0, sigma, lambda, phi, amp;
+  int planar;
+};
+hipError_t launch_packet(const double* n64, int nx, int ny, const PacketArgs& p, bool fp32,
+                         void* q2, void* q3, void* q4, hipStream_t stream);
+
+// Sum of squares of three planes of `count` elements, FP64, fixed order.
+constexpr int kEnergyPartials = 1024;
+hipError_t launch_energy(const void* q2, const void* q3, const void* q4, size_t count, bool fp32,
+                         double* partials, double* out, hipStream_t stream);
+
+// Three planes to FP64 (q2, q3, q4), or (q2 / n, q3, q4) when physical.
+hipError_t launch_readout(const void* q2, const void* q3, const void* q4, const double* n64,
+                          size_t count, bool fp32, int physical, double* out, hipStream_t stream);
+
+// FP64 staging (3 consecutive planes) to the three amplitude planes.
+hipError_t launch_from_f64(const double* src, size_t count, bool fp32, void* q2, void* q3,
+                           void* q4, hipStream_t stream);
+
+}  // namespace qla

@@ -1,0 +1,251 @@
+"""Thin ctypes binding of libqla.so (the C ABI declared in include/qla.h).
+
+Argument marshalling only: every step of the QLA path runs in the library's HIP
+kernels. Functions keep the C names; a non-zero status raises QlaError carrying
+qla_last_error(). Host arrays are numpy float64; device arrays may be anything
+exposing a device pointer (torch tensors via .data_ptr()).
+
+Importing this module loads the built library and fails loudly if it is missing:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqla.so")
+
+QLA_OK, QLA_EINVAL, QLA_ENOMEM, QLA_EDEVICE, QLA_ESTATE = 0, -1, -2, -3, -4
+QLA_F64, QLA_F32 = 0, 1
+QLA_V_SKEW_HALF, QLA_V_PAPER, QLA_V_NONE = 0, 1, 2
+
+# Every symbol include/qla.h declares.
+EXPORTED = (
+    "qla_create", "qla_set_index", "qla_set_index_device", "qla_init_packet",
+    "qla_set_fields", "qla_advance", "qla_get_fields", "qla_get_fields_device",
+    "qla_energy", "qla_energy_device", "qla_get_coefficients", "qla_step_count",
+    "qla_set_tuning", "qla_destroy", "qla_strerror", "qla_last_error",
+)
+
+
+class QlaError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where} failed with status {status}: {message}")
+        self.status = status
+
+
+class qla_packet(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("phi", ctypes.c_double), ("amp", ctypes.c_double),
+                ("planar", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libqla.so and declare every prototype. Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2604_21128_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+    st = ctypes.c_int
+    proto = {
+        "qla_create": (st, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                            ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "qla_set_index": (st, [vp, dp, ctypes.c_size_t]),
+        "qla_set_index_device": (st, [vp, vp, ctypes.c_size_t]),
+        "qla_init_packet": (st, [vp, ctypes.POINTER(qla_packet)]),
+        "qla_set_fields": (st, [vp, dp, i64]),
+        "qla_advance": (st, [vp, i64]),
+        "qla_get_fields": (st, [vp, dp, ctypes.c_int]),
+        "qla_get_fields_device": (st, [vp, vp, ctypes.c_int]),
+        "qla_energy": (st, [vp, dp]),
+        "qla_energy_device": (st, [vp, vp]),
+        "qla_get_coefficients": (st, [vp, dp, dp, dp]),
+        "qla_step_count": (st, [vp, ctypes.POINTER(i64)]),
+        "qla_set_tuning": (st, [vp, ctypes.c_int]),
+        "qla_destroy": (st, [vp]),
+        "qla_strerror": (ctypes.c_char_p, [st]),
+        "qla_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in proto.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != QLA_OK:
+        msg = load().qla_last_error().decode(errors="replace")
+        raise QlaError(status, where, msg)
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _devptr(x) -> int:
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    return int(x)
+
+
+def _host_planes(a: np.ndarray, count: int, name: str) -> np.ndarray:
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+            and a.size == count):
+        raise ValueError(f"{name} must be a C-contiguous float64 array of {count} elements")
+    return a
+
+
+def qla_create(nx: int, ny: int, delta: float, precision: int = QLA_F64,
+               potential: int = QLA_V_SKEW_HALF, hip_stream: Optional[int] = None) -> int:
+    """Returns the context handle (an integer address)."""
+    out = ctypes.c_void_p()
+    _check(load().qla_create(int(nx), int(ny), float(delta), int(precision), int(potential),
+                             ctypes.c_void_p(hip_stream) if hip_stream else None,
+                             ctypes.byref(out)), "qla_create")
+    return int(out.value)
+
+
+def qla_destroy(ctx: int) -> None:
+    _check(load().qla_destroy(ctypes.c_void_p(ctx)), "qla_destroy")
+
+
+def qla_set_index(ctx: int, n: np.ndarray) -> None:
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    if n.ndim != 2:
+        raise ValueError("n must be [ny, nx]")
+    _check(load().qla_set_index(ctypes.c_void_p(ctx), _dptr(n), n.shape[1]), "qla_set_index")
+
+
+def qla_set_index_device(ctx: int, n_device, ld: int) -> None:
+    _check(load().qla_set_index_device(ctypes.c_void_p(ctx), ctypes.c_void_p(_devptr(n_device)),
+                                       int(ld)), "qla_set_index_device")
+
+
+def qla_init_packet(ctx: int, x0: float, y0: float, sigma: float, lam: float, phi: float = 0.0,
+                    amp: float = 1.0, planar: bool = True) -> None:
+    p = qla_packet(float(x0), float(y0), float(sigma), float(lam), float(phi), float(amp),
+                   int(bool(planar)))
+    _check(load().qla_init_packet(ctypes.c_void_p(ctx), ctypes.byref(p)), "qla_init_packet")
+
+
+def qla_set_fields(ctx: int, q: np.ndarray, step: int = 0) -> None:
+    """q: float64 [3, ny, nx] planes (q2, q3, q4)."""
+    q = _host_planes(q, q.size, "q")
+    _check(load().qla_set_fields(ctypes.c_void_p(ctx), _dptr(q), int(step)), "qla_set_fields")
+
+
+def qla_advance(ctx: int, k: int) -> None:
+    _check(load().qla_advance(ctypes.c_void_p(ctx), int(k)), "qla_advance")
+
+
+def qla_get_fields(ctx: int, nx: int, ny: int, physical: bool = False) -> np.ndarray:
+    out = np.empty((3, ny, nx), dtype=np.float64)
+    _check(load().qla_get_fields(ctypes.c_void_p(ctx), _dptr(out), int(bool(physical))),
+           "qla_get_fields")
+    return out
+
+
+def qla_get_fields_device(ctx: int, out_device, physical: bool = False) -> None:
+    _check(load().qla_get_fields_device(ctypes.c_void_p(ctx), ctypes.c_void_p(_devptr(out_device)),
+                                        int(bool(physical))), "qla_get_fields_device")
+
+
+def qla_energy(ctx: int) -> float:
+    e = ctypes.c_double()
+    _check(load().qla_energy(ctypes.c_void_p(ctx), ctypes.byref(e)), "qla_energy")
+    return float(e.value)
+
+
+def qla_energy_device(ctx: int, out_device) -> None:
+    _check(load().qla_energy_device(ctypes.c_void_p(ctx), ctypes.c_void_p(_devptr(out_device))),
+           "qla_energy_device")
+
+
+def qla_get_coefficients(ctx: int, nx: int, ny: int):
+    th, bx, by = (np.empty((ny, nx), dtype=np.float64) for _ in range(3))
+    _check(load().qla_get_coefficients(ctypes.c_void_p(ctx), _dptr(th), _dptr(bx), _dptr(by)),
+           "qla_get_coefficients")
+    return th, bx, by
+
+
+def qla_step_count(ctx: int) -> int:
+    v = ctypes.c_int64()
+    _check(load().qla_step_count(ctypes.c_void_p(ctx), ctypes.byref(v)), "qla_step_count")
+    return int(v.value)
+
+
+def qla_set_tuning(ctx: int, rows_per_segment: int) -> None:
+    _check(load().qla_set_tuning(ctypes.c_void_p(ctx), int(rows_per_segment)), "qla_set_tuning")
+
+
+def qla_strerror(status: int) -> str:
+    return load().qla_strerror(int(status)).decode()
+
+
+def qla_last_error() -> str:
+    return load().qla_last_error().decode(errors="replace")
+
+
+class Lattice:
+    """Owns one context; a convenience wrapper over the functions above."""
+
+    def __init__(self, nx: int, ny: int, delta: float, precision: int = QLA_F64,
+                 potential: int = QLA_V_SKEW_HALF, hip_stream: Optional[int] = None):
+        self.nx, self.ny = int(nx), int(ny)
+        self.ctx = qla_create(nx, ny, delta, precision, potential, hip_stream)
+
+    def close(self):
+        if self.ctx:
+            qla_destroy(self.ctx)
+            self.ctx = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_index(self, n):
+        qla_set_index(self.ctx, n)
+
+    def init_packet(self, p):
+        qla_init_packet(self.ctx, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
+
+    def advance(self, k: int):
+        qla_advance(self.ctx, k)
+
+    def fields(self, physical: bool = False) -> np.ndarray:
+        return qla_get_fields(self.ctx, self.nx, self.ny, physical)
+
+    def set_fields(self, q, step: int = 0):
+        qla_set_fields(self.ctx, np.ascontiguousarray(q, dtype=np.float64), step)
+
+    def energy(self) -> float:
+        return qla_energy(self.ctx)
+
+    def coefficients(self):
+        return qla_get_coefficients(self.ctx, self.nx, self.ny)
+
+    @property
+    def steps(self) -> int:
+        return qla_step_count(self.ctx)

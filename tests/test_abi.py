@@ -1,0 +1,70 @@
+"""The C ABI library loads and exports every symbol include/qla.h declares (no GPU
+needed); argument checks that return before any device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qla.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qla_[a-z_]+)\s*\(", text)))
+
+
+def _lib():
+    from paper_2604_21128_amd import qla
+    if not os.path.exists(qla.LIB_PATH):
+        pytest.fail("libqla.so is not built (run `python -m paper_2604_21128_amd.build`)")
+    return qla, qla.load()
+
+
+def test_header_declares_the_documented_calls():
+    names = _declared()
+    for must in ("qla_create", "qla_set_index", "qla_init_packet", "qla_advance",
+                 "qla_get_fields", "qla_energy", "qla_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    qla, lib = _lib()
+    declared = _declared()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(qla.EXPORTED) == declared
+
+
+def test_status_strings():
+    qla, _ = _lib()
+    assert qla.qla_strerror(qla.QLA_OK) == "success"
+    assert qla.qla_strerror(qla.QLA_EINVAL) == "invalid argument"
+    assert qla.qla_strerror(qla.QLA_ESTATE) == "call out of order"
+
+
+@pytest.mark.parametrize("nx,ny,delta,prec,pot", [
+    (4, 64, 0.25, 0, 0),       # lattice too small for the 4-cell neighbourhood
+    (64, 7, 0.25, 0, 0),
+    (64, 64, 0.0, 0, 0),       # delta must be > 0
+    (64, 64, float("nan"), 0, 0),
+    (64, 64, 0.25, 7, 0),      # bad precision
+    (64, 64, 0.25, 0, 9),      # bad potential mode
+    (65536, 65536, 0.25, 0, 0),  # nx * ny >= 2^31
+])
+def test_create_rejects_bad_arguments_before_touching_the_device(nx, ny, delta, prec, pot):
+    qla, lib = _lib()
+    out = ctypes.c_void_p(1234)
+    st = lib.qla_create(nx, ny, delta, prec, pot, None, ctypes.byref(out))
+    assert st == qla.QLA_EINVAL
+    assert out.value is None
+    assert qla.qla_last_error()
+
+
+def test_null_context_is_rejected():
+    qla, lib = _lib()
+    assert lib.qla_advance(None, 1) == qla.QLA_EINVAL
+    assert lib.qla_energy(None, None) == qla.QLA_EINVAL
+    assert lib.qla_destroy(None) == qla.QLA_OK

@@ -1,0 +1,287 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: relative L2 <= 1e-12 for FP64 amplitudes and <= 1e-5 for FP32
+amplitudes against the FP64 oracle; coefficients and the initial packet to a few
+ulps. Full-size lattices are checked on windows whose centre the oracle computes
+exactly: after s steps an amplitude depends only on inputs within 4 s cells along
+each axis (U_x and U_y each reach 4 cells, the potentials 1 for n), so the oracle
+run on a periodic window is exact more than 4 s + 1 cells inside its edges.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}   # by precision code: QLA_F64, QLA_F32
+
+
+@pytest.fixture(scope="module")
+def qla():
+    from paper_2604_21128_amd import qla as q
+    q.load()
+    return q
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _oracle_state(n, q3):
+    q = np.zeros((6,) + n.shape)
+    q[2:5] = q3
+    return q
+
+
+def _random_fields(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((3,) + shape)
+
+
+def _random_index(ny, nx, seed, lo=1.0, hi=3.0):
+    rng = np.random.default_rng(seed)
+    base = rng.uniform(lo, hi)
+    bump = rng.uniform(-0.5, 0.5, size=(ny, nx))
+    return np.clip(base + bump, lo, hi)
+
+
+# ---------------------------------------------------------------------------------------
+# a1 coefficients, a2 packet, a6 energy, a7 readout
+def test_coefficients_match_oracle(qla):
+    w = workloads.parity_small()
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    with qla.Lattice(w.nx, w.ny, w.delta) as lat:
+        lat.set_index(n)
+        th, bx, by = lat.coefficients()
+    oth, obx, oby = oracle.coefficients(n, w.delta)
+    np.testing.assert_allclose(th, oth, rtol=4e-16, atol=0)
+    scale = max(np.abs(obx).max(), np.abs(oby).max())
+    assert np.abs(bx - obx).max() <= 1e-15 * scale
+    assert np.abs(by - oby).max() <= 1e-15 * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_packet_matches_oracle(qla, prec):
+    w = workloads.parity_small()
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    with qla.Lattice(w.nx, w.ny, w.delta, precision=prec) as lat:
+        lat.set_index(n)
+        for p in (w.packet, workloads.Packet(x0=30.5, y0=200.0, sigma=9.0, lam=12.0, phi=0.7,
+                                               amp=0.5, planar=False)):
+            lat.init_packet(p)
+            got = lat.fields()
+            want = oracle.packet_from(n, p)[2:5]
+            tol = 1e-15 if prec == 0 else 1e-7
+            assert np.abs(got - want).max() <= tol * np.abs(want).max()
+            phys = lat.fields(physical=True)
+            ez, bxf, byf = oracle.physical_fields(oracle.packet_from(n, p), n)
+            assert np.abs(phys[0] - ez).max() <= 4 * tol * np.abs(ez).max()
+            np.testing.assert_array_equal(phys[1:], got[1:])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_energy_matches_oracle(qla, prec):
+    ny, nx = 77, 131
+    q = _random_fields((ny, nx), 11)
+    with qla.Lattice(nx, ny, 0.25, precision=prec) as lat:
+        lat.set_index(np.full((ny, nx), 1.5))
+        lat.set_fields(q)
+        e = lat.energy()
+        stored = lat.fields()
+    want = oracle.energy(_oracle_state(np.ones((ny, nx)), stored))
+    assert abs(e / want - 1) < 1e-14
+
+
+# ---------------------------------------------------------------------------------------
+# the full step (a3 U_x, a4 U_y, a5 V_x, V_y)
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("vmode", [0, 1, 2])
+def test_parity_small_workload(qla, prec, vmode):
+    """256^2 ellipse, +x packet, 200 steps (the small parity workload), each potential mode."""
+    w = workloads.parity_small()
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    q0 = oracle.packet_from(n, w.packet)
+    want = oracle.advance(q0.copy(), n, w.delta, w.steps, vmode)
+    with qla.Lattice(w.nx, w.ny, w.delta, precision=prec, potential=vmode) as lat:
+        lat.set_index(n)
+        lat.init_packet(w.packet)
+        lat.advance(w.steps)
+        got = lat.fields()
+        assert lat.steps == w.steps
+    err = rel_l2(got, want[2:5])
+    print(f"prec={prec} vmode={vmode} rel_l2={err:.3e}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("nx,ny,steps,rows", [
+    (8, 8, 5, 0),          # smallest lattice: one wave covers the row 8 times over
+    (57, 121, 7, 0),       # one column past a strip, one row past a segment
+    (131, 77, 9, 8),       # ragged, smallest segment
+    (200, 9, 6, 16),       # short and wide
+    (9, 300, 6, 40),       # tall and narrow
+    (112, 240, 4, 120),    # exact multiples of the strip and segment
+])
+def test_parity_ragged_random(qla, prec, nx, ny, steps, rows):
+    n = _random_index(ny, nx, seed=nx * 1000 + ny)
+    q = _random_fields((ny, nx), seed=ny)
+    for vmode in (0, 1):
+        want = oracle.advance(_oracle_state(n, q), n, 0.4, steps, vmode)[2:5]
+        with qla.Lattice(nx, ny, 0.4, precision=prec, potential=vmode) as lat:
+            qla.qla_set_tuning(lat.ctx, rows)
+            lat.set_index(n)
+            lat.set_fields(q)
+            lat.advance(steps)
+            got = lat.fields()
+        err = rel_l2(got, want)
+        print(f"{nx}x{ny} steps={steps} rows={rows} prec={prec} vmode={vmode} rel_l2={err:.3e}")
+        assert err <= TOL[prec]
+
+
+def test_parity_large_angles(qla):
+    """delta = 1.6: collision angles up to 0.4 rad and large potential angles (the
+    long-series kernel variant)."""
+    ny, nx = 40, 70
+    n = 1.0 + 0.5 * (1 + np.sin(2 * np.pi * np.arange(nx) / nx))[None, :] \
+        * (1 + np.cos(2 * np.pi * np.arange(ny) / ny))[:, None] / 2
+    q = _random_fields((ny, nx), seed=5)
+    for vmode in (0, 1):
+        want = oracle.advance(_oracle_state(n, q), n, 1.6, 12, vmode)[2:5]
+        with qla.Lattice(nx, ny, 1.6, potential=vmode) as lat:
+            lat.set_index(n)
+            lat.set_fields(q)
+            lat.advance(12)
+            got = lat.fields()
+        assert rel_l2(got, want) <= 1e-12
+
+
+# ---------------------------------------------------------------------------------------
+# full-size lattice, sampled windows
+def _window_parity(qla, w, prec, steps, centres, seed):
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    q = _random_fields((w.ny, w.nx), seed=seed)
+    with qla.Lattice(w.nx, w.ny, w.delta, precision=prec) as lat:
+        lat.set_index(n)
+        lat.set_fields(q)
+        lat.advance(steps)
+        got = lat.fields()
+    margin = 4 * steps + 2
+    half = margin + 12
+    worst = 0.0
+    for cx, cy in centres:
+        ys = np.arange(cy - half, cy + half + 1) % w.ny
+        xs = np.arange(cx - half, cx + half + 1) % w.nx
+        nw = np.ascontiguousarray(n[np.ix_(ys, xs)])
+        qw = np.ascontiguousarray(q[:, ys][:, :, xs])
+        out = oracle.advance(_oracle_state(nw, qw), nw, w.delta, steps)[2:5]
+        inner = slice(margin, 2 * half + 1 - margin)
+        want = out[:, inner, inner]
+        g = got[:, ys[inner]][:, :, xs[inner]]
+        err = rel_l2(g, want)
+        print(f"window centre=({cx},{cy}) prec={prec} rel_l2={err:.3e}")
+        worst = max(worst, err)
+    return worst
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_parity_full_size_4096_windows(qla, prec):
+    w = workloads.plain_4096()
+    e = w.ellipse
+    centres = [(int(e.xc - e.a), int(e.yc)),          # left vertex: strong x gradient
+               (int(e.xc), int(e.yc + e.b)),          # top co-vertex: strong y gradient
+               (int(e.xc + 0.7 * e.a), int(e.yc - 0.7 * e.b)),
+               (0, 0),                                # periodic corner
+               (w.nx - 1, 1234)]
+    assert _window_parity(qla, w, prec, 20, centres, seed=42) <= TOL[prec]
+
+
+# ---------------------------------------------------------------------------------------
+# state handling
+def test_checkpoint_restore_continues_bitwise(qla):
+    w = workloads.parity_small()
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    for prec in (0, 1):
+        with qla.Lattice(w.nx, w.ny, w.delta, precision=prec) as a:
+            a.set_index(n)
+            a.init_packet(w.packet)
+            a.advance(30)
+            mid = a.fields()
+            a.advance(25)
+            ref = a.fields()
+        with qla.Lattice(w.nx, w.ny, w.delta, precision=prec) as b:
+            b.set_index(n)
+            b.set_fields(mid, step=30)
+            b.advance(25)
+            assert b.steps == 55
+            np.testing.assert_array_equal(b.fields(), ref)
+
+
+def test_runs_are_deterministic_and_tiling_independent(qla):
+    w = workloads.parity_small()
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    outs, energies = [], []
+    for rows in (0, 8, 64, 0):
+        with qla.Lattice(w.nx, w.ny, w.delta) as lat:
+            qla.qla_set_tuning(lat.ctx, rows)
+            lat.set_index(n)
+            lat.init_packet(w.packet)
+            lat.advance(40)
+            outs.append(lat.fields())
+            energies.append(lat.energy())
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    assert len(set(energies)) == 1
+
+
+def test_zero_steps_is_identity(qla):
+    q = _random_fields((16, 24), seed=3)
+    with qla.Lattice(24, 16, 0.25) as lat:
+        lat.set_index(np.full((16, 24), 2.0))
+        lat.set_fields(q)
+        lat.advance(0)
+        np.testing.assert_array_equal(lat.fields(), q)
+
+
+def test_energy_conserved_over_a_long_run(qla):
+    """SKEW_HALF is unitary: FP64 energy drift stays at rounding level, and the
+    three-shear rotations keep FP32 drift small (no systematic growth)."""
+    w = workloads.parity_small()
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+        with qla.Lattice(w.nx, w.ny, w.delta, precision=prec) as lat:
+            lat.set_index(n)
+            lat.init_packet(w.packet)
+            e0 = lat.energy()
+            lat.advance(4000)
+            drift = lat.energy() / e0 - 1
+        print(f"prec={prec} energy drift over 4000 steps: {drift:.3e}")
+        assert abs(drift) < tol
+
+
+# ---------------------------------------------------------------------------------------
+# errors forced from the host
+def test_error_paths(qla):
+    with qla.Lattice(16, 16, 0.25) as lat:
+        with pytest.raises(qla.QlaError) as e:
+            lat.advance(1)                                   # no index yet
+        assert e.value.status == qla.QLA_ESTATE
+        bad = np.full((16, 16), 1.5)
+        bad[3, 4] = 0.0
+        with pytest.raises(qla.QlaError) as e:
+            lat.set_index(bad)
+        assert e.value.status == qla.QLA_EINVAL
+        bad[3, 4] = np.nan
+        with pytest.raises(qla.QlaError):
+            lat.set_index(bad)
+        with pytest.raises(qla.QlaError) as e:
+            qla.qla_set_tuning(lat.ctx, 12)                  # not a multiple of 8
+        assert e.value.status == qla.QLA_EINVAL
+        with pytest.raises(qla.QlaError):
+            lat.advance(-1)
+    with qla.Lattice(16, 16, 3.0) as lat:                    # delta/(4n) = 0.75 rad
+        with pytest.raises(qla.QlaError) as e:
+            lat.set_index(np.ones((16, 16)))
+        assert e.value.status == qla.QLA_EINVAL
+        assert "angle" in qla.qla_last_error()
