@@ -65,8 +65,11 @@ def bench_precision(qla, torch, w, prec, steps, warmup):
     n_dev = torch.from_numpy(n_host).to("cuda")
     out_dev = torch.empty((3, w.ny, w.nx), dtype=torch.float64, device="cuda")
     energies = torch.zeros(w.steps // w.energy_every + 1, dtype=torch.float64, device="cuda")
+    # The library enqueues on this stream; torch's events are recorded on it too.
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
+    if not sp:
+        raise RuntimeError("bench needs a non-default torch stream")
     for _ in range(warmup):
         ctx, _ = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, False)
         torch.cuda.synchronize()
@@ -132,6 +135,9 @@ def main():
     ap.add_argument("--precisions", default="f64,f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (a reference kernel of "
+                         "known traffic for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU halo-exchange path "
@@ -146,13 +152,21 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib * 2**20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = workloads.workload_by_name(args.workload)
     if args.qla_steps:
         w = dataclasses.replace(w, steps=args.qla_steps)
     precs = [p for p in args.precisions.split(",") if p]
     results = {}
-    for p in precs:
-        results[p] = bench_precision(qla, torch, w, p, args.steps, args.warmup)
+    stream = torch.cuda.Stream()   # default priority
+    with torch.cuda.stream(stream):
+        for p in precs:
+            results[p] = bench_precision(qla, torch, w, p, args.steps, args.warmup)
     main_p = precs[0]
     r = results[main_p]
     line = {

@@ -93,7 +93,8 @@ typedef struct {
 } qla_packet;
 
 /* Create a context for an nx-by-ny periodic lattice with spacing delta.
- * nx, ny >= 8 (the step reads 4 neighbours on each side), nx * ny < 2^31,
+ * nx, ny >= 8 (the step reads 4 neighbours on each side); one amplitude plane
+ * must fit in 2 GiB (nx * ny <= 2^28 in FP64, 2^29 in FP32),
  * delta > 0 and finite. hip_stream: a hipStream_t to enqueue on, or NULL for a
  * library-owned stream. Allocates the amplitude planes (two buffers), the index
  * planes and small scratch; the state starts at zero with no index set. */
@@ -144,9 +145,11 @@ qla_status qla_get_coefficients(qla_ctx *ctx, double *theta, double *beta_x, dou
 /* Number of steps taken since the last reset. */
 qla_status qla_step_count(const qla_ctx *ctx, int64_t *steps);
 
-/* Tuning of the step kernel: output rows per wavefront segment (multiple of 8,
- * >= 8, or 0 for the default). */
-qla_status qla_set_tuning(qla_ctx *ctx, int rows_per_segment);
+/* Tuning of the step kernel (results do not depend on it, bit for bit):
+ * rows_per_segment = output rows each wavefront marches through (rounded up so
+ * that the rows plus 8 halo rows fill whole unrolled loop trips; 0 = default);
+ * prefetch_rows = how many rows ahead its loads run (2, 3 or 4; 0 = default). */
+qla_status qla_set_tuning(qla_ctx *ctx, int rows_per_segment, int prefetch_rows);
 
 /* Release every resource of the context (NULL is accepted). Synchronises. */
 qla_status qla_destroy(qla_ctx *ctx);

@@ -12,6 +12,11 @@
 #include "qla.h"
 #include "qla_internal.h"
 
+namespace {
+constexpr int kDefaultRows = 24;
+constexpr int kDefaultPrefetch = 3;
+}  // namespace
+
 struct qla_ctx {
   int nx = 0, ny = 0;
   double delta = 0.0;
@@ -31,7 +36,8 @@ struct qla_ctx {
   int64_t steps = 0;
   bool have_index = false;
   int angle_class = 0;
-  int rows_per_seg = 120;
+  int rows_per_seg = kDefaultRows;
+  int prefetch = kDefaultPrefetch;
   size_t count() const { return static_cast<size_t>(nx) * static_cast<size_t>(ny); }
   size_t elem() const { return fp32 ? sizeof(float) : sizeof(double); }
 };
@@ -158,8 +164,11 @@ qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
   if (!out) return fail(QLA_EINVAL, "out is NULL");
   *out = nullptr;
   if (nx < 8 || ny < 8) return fail(QLA_EINVAL, "nx and ny must be >= 8");
-  if (static_cast<long long>(nx) * ny >= (1ll << 31))
-    return fail(QLA_EINVAL, "nx * ny must be < 2^31");
+  const long long sites = static_cast<long long>(nx) * ny;
+  const long long elem = precision == QLA_F32 ? 4 : 8;
+  if (sites * elem > (1ll << 31))
+    return fail(QLA_EINVAL, "one amplitude plane must fit in 2 GiB (nx * ny <= 2^28 in FP64, "
+                            "2^29 in FP32)");
   if (!(delta > 0.0) || !std::isfinite(delta)) return fail(QLA_EINVAL, "delta must be > 0");
   if (precision != QLA_F64 && precision != QLA_F32) return fail(QLA_EINVAL, "bad precision");
   if (potential != QLA_V_SKEW_HALF && potential != QLA_V_PAPER && potential != QLA_V_NONE)
@@ -287,6 +296,7 @@ qla_status qla_advance(qla_ctx* c, int64_t k) {
   L.nx = c->nx;
   L.ny = c->ny;
   L.rows_per_seg = c->rows_per_seg;
+  L.prefetch = c->prefetch;
   L.delta = c->delta;
   L.fp32 = c->fp32;
   L.vmode = c->vmode;
@@ -366,17 +376,14 @@ qla_status qla_step_count(const qla_ctx* c, int64_t* steps) {
   return QLA_OK;
 }
 
-qla_status qla_set_tuning(qla_ctx* c, int rows_per_segment) {
+qla_status qla_set_tuning(qla_ctx* c, int rows_per_segment, int prefetch_rows) {
   if (!c) return fail(QLA_EINVAL, "NULL context");
-  const int gran = qla::step_rows_granularity();
-  if (rows_per_segment == 0) {
-    c->rows_per_seg = 120;
-    return QLA_OK;
-  }
-  if (rows_per_segment < gran || rows_per_segment % gran != 0)
-    return fail(QLA_EINVAL, "rows_per_segment must be a positive multiple of " +
-                                std::to_string(gran));
-  c->rows_per_seg = rows_per_segment;
+  if (rows_per_segment < 0 || rows_per_segment > (1 << 20))
+    return fail(QLA_EINVAL, "rows_per_segment must be in [0, 2^20]");
+  if (prefetch_rows != 0 && (prefetch_rows < 2 || prefetch_rows > 4))
+    return fail(QLA_EINVAL, "prefetch_rows must be 0 (default), 2, 3 or 4");
+  c->rows_per_seg = rows_per_segment ? rows_per_segment : kDefaultRows;
+  c->prefetch = prefetch_rows ? prefetch_rows : kDefaultPrefetch;
   return QLA_OK;
 }
 

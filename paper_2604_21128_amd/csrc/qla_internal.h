@@ -17,14 +17,14 @@ struct StepLaunch {
   void* out[3];
   const void* n;
   int nx, ny;
-  int rows_per_seg;
+  int rows_per_seg;  // requested output rows per wavefront segment (rounded up)
+  int prefetch;      // rows the loads run ahead: 2, 3 or 4
   double delta;
   bool fp32;
   int vmode;
   int angle_class;
 };
 hipError_t launch_step(const StepLaunch& L, hipStream_t stream);
-int step_rows_granularity();
 
 // Index preparation (qla_aux.hip): copy n (row pitch ld) into the packed FP64
 // plane n64 (and its FP32 rounding n32 when non-null), and accumulate into

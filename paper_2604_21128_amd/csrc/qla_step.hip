@@ -38,6 +38,8 @@
 // is exactly three amplitude planes in and out plus n in.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "qla_device.h"
 #include "qla_internal.h"
 
@@ -49,37 +51,73 @@ constexpr int kWave = 64;
 constexpr int kHalo = 4;
 constexpr int kStripCols = kWave - 2 * kHalo;  // 56 output columns per wave
 constexpr int kWavesPerBlock = 4;
-constexpr int kWin = 8;  // register window depth (rows), power of two
+// A buffer store whose offset is at least the buffer's size is discarded by the
+// hardware; stores of halo lanes and of rows outside the segment use this offset
+// instead of a branch, so the memory counters stay static for the compiler.
+constexpr unsigned kDropOffset = 0x80000000u;
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, unsigned bytes) {
+  // raw buffer (stride 0), 32-bit dwords, range-checked against `bytes`
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes),
+                                           0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned soff) {
+  if constexpr (sizeof(T) == 8) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  }
+}
 
 template <typename T>
 struct StepArgs {
-  const T* __restrict__ q2i;
-  const T* __restrict__ q3i;
-  const T* __restrict__ q4i;
-  const T* __restrict__ n;
-  T* __restrict__ q2o;
-  T* __restrict__ q3o;
-  T* __restrict__ q4o;
+  const T* q2i;
+  const T* q3i;
+  const T* q4i;
+  const T* n;
+  T* q2o;
+  T* q3o;
+  T* q4o;
+  unsigned plane_bytes;  // nx * ny * sizeof(T), at most 2^31
   int nx, ny, strips, segs, rows_per_seg, iters;
   T d4;  // delta / 4
 };
 
-template <typename T, int VMODE, int CLS>
+// kWin: register window depth in rows (the loop is unrolled kWin times so every
+// window index is static); PF: how many rows ahead the loads run.
+template <typename T, int VMODE, int CLS, int kWin, int PF>
 struct Marcher {
+  static_assert(PF + 6 <= kWin, "a prefetched row must not overwrite a live one");
   // Row window: amplitudes, index, 1/n and the collision shear of each row.
   T A[kWin], P4[kWin], P3[kWin], N[kWin], M[kWin], Tt[kWin], Ts[kWin];
-  int col;       // this lane's column (wrapped)
-  int yin;       // row index of the next row to load (wrapped)
-  bool store_lane;
+  __amdgpu_buffer_rsrc_t r2i, r3i, r4i, rn, r2o, r3o, r4o;
+  unsigned col_bytes;    // this lane's column (wrapped) in bytes
+  unsigned store_bytes;  // col_bytes for lanes that own an output column, else kDropOffset
+  unsigned row_bytes;    // nx * sizeof(T)
+  int yin;               // row index of the next row to load (wrapped)
 
-  // y is uniform across the wave: the row offset stays in scalar registers and
-  // every lane adds its fixed column.
-  __device__ __forceinline__ void load_row(const StepArgs<T>& g, int slot, int y) {
-    const size_t row = static_cast<size_t>(__builtin_amdgcn_readfirstlane(y)) * g.nx;
-    A[slot] = (g.q2i + row)[col];
-    P3[slot] = (g.q3i + row)[col];
-    P4[slot] = (g.q4i + row)[col];
-    N[slot] = (g.n + row)[col];
+  // y is uniform across the wave: the row offset is a scalar register and every
+  // lane adds its fixed column offset.
+  __device__ __forceinline__ void load_row(int slot, int y) {
+    const unsigned soff = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(y)) * row_bytes;
+    A[slot] = buf_load<T>(r2i, col_bytes, soff);
+    P3[slot] = buf_load<T>(r3i, col_bytes, soff);
+    P4[slot] = buf_load<T>(r4i, col_bytes, soff);
+    N[slot] = buf_load<T>(rn, col_bytes, soff);
   }
 
   // U_x on the just-arrived row (slot s): lanes exchange neighbour values by DPP.
@@ -173,11 +211,11 @@ struct Marcher {
 
   template <int S0>
   __device__ __forceinline__ void iteration(const StepArgs<T>& g, int r, int y0, int yend) {
-    constexpr int s0 = S0, s4 = (S0 + kWin - 4) % kWin, sp = (S0 + 2) % kWin;
-    // loads for row r + 2 (the slot held row r - 6, no longer needed). Issued
-    // unconditionally, also past the segment's end (rows wrap, so they stay in
-    // bounds): a branch here would make the compiler wait for these loads at once.
-    load_row(g, sp, yin);
+    constexpr int s0 = S0, s4 = (S0 + kWin - 4) % kWin, sp = (S0 + PF) % kWin;
+    // loads for row r + PF (the slot held row r + PF - kWin, no longer needed).
+    // Issued unconditionally, also past the segment's end (rows wrap, so they stay
+    // in bounds): a branch here would make the compiler wait for them at once.
+    load_row(sp, yin);
     yin = (yin + 1 == g.ny) ? 0 : yin + 1;
     // collision shear of row r
     const T m = recip(N[s0]);
@@ -190,16 +228,16 @@ struct Marcher {
     // row r - 4 is complete: output row y0 + r - 8
     potentials<S0>(g.d4);
     const int yo = y0 + r - 2 * kHalo;
-    if (yo >= y0 && yo < yend && store_lane) {
-      const size_t row = static_cast<size_t>(__builtin_amdgcn_readfirstlane(yo)) * g.nx;
-      (g.q2o + row)[col] = A[s4];
-      (g.q3o + row)[col] = P3[s4];
-      (g.q4o + row)[col] = P4[s4];
-    }
+    const bool row_ok = yo >= y0 && yo < yend;
+    const unsigned soff = row_ok ? static_cast<unsigned>(yo) * row_bytes : 0u;
+    const unsigned voff = row_ok ? store_bytes : kDropOffset;
+    buf_store<T>(A[s4], r2o, voff, soff);
+    buf_store<T>(P3[s4], r3o, voff, soff);
+    buf_store<T>(P4[s4], r4o, voff, soff);
   }
 };
 
-template <typename T, int VMODE, int CLS>
+template <typename T, int VMODE, int CLS, int kWin, int PF>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(StepArgs<T> g) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
@@ -209,12 +247,22 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
   const int strip = (blk % blocks_per_seg) * kWavesPerBlock + wib;
   if (seg >= g.segs || strip >= g.strips) return;  // whole wave exits together
 
-  Marcher<T, VMODE, CLS> w;
+  Marcher<T, VMODE, CLS, kWin, PF> w;
   const int x0 = strip * kStripCols;
   int col = (x0 - kHalo + lane) % g.nx;
   if (col < 0) col += g.nx;
-  w.col = col;
-  w.store_lane = lane >= kHalo && lane < kHalo + kStripCols && x0 + lane - kHalo < g.nx;
+  const bool store_lane =
+      lane >= kHalo && lane < kHalo + kStripCols && x0 + lane - kHalo < g.nx;
+  w.col_bytes = static_cast<unsigned>(col) * sizeof(T);
+  w.store_bytes = store_lane ? w.col_bytes : kDropOffset;
+  w.row_bytes = static_cast<unsigned>(g.nx) * sizeof(T);
+  w.r2i = plane_rsrc(g.q2i, g.plane_bytes);
+  w.r3i = plane_rsrc(g.q3i, g.plane_bytes);
+  w.r4i = plane_rsrc(g.q4i, g.plane_bytes);
+  w.rn = plane_rsrc(g.n, g.plane_bytes);
+  w.r2o = plane_rsrc(g.q2o, g.plane_bytes);
+  w.r3o = plane_rsrc(g.q3o, g.plane_bytes);
+  w.r4o = plane_rsrc(g.q4o, g.plane_bytes);
   const int y0 = seg * g.rows_per_seg;
   const int yend = min(y0 + g.rows_per_seg, g.ny);
 #pragma unroll
@@ -223,24 +271,28 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
   }
   int y = y0 - kHalo;
   if (y < 0) y += g.ny;
-  w.load_row(g, 0, y);
-  y = (y + 1 == g.ny) ? 0 : y + 1;
-  w.load_row(g, 1, y);
-  w.yin = (y + 1 == g.ny) ? 0 : y + 1;
+  // The prologue issues the first PF rows in the same pattern as the loop body
+  // (4 loads, then 3 stores, here discarded ones), so the compiler sees the same
+  // outstanding memory operations on entry as on the back edge and keeps its
+  // waits at the prefetch distance instead of draining the queue every trip.
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    w.load_row(k, y);
+    y = (y + 1 == g.ny) ? 0 : y + 1;
+    buf_store<T>(T(0), w.r2o, kDropOffset, 0u);
+    buf_store<T>(T(0), w.r3o, kDropOffset, 0u);
+    buf_store<T>(T(0), w.r4o, kDropOffset, 0u);
+  }
+  w.yin = y;
 
   for (int r = 0; r < g.iters; r += kWin) {
-    w.template iteration<0>(g, r + 0, y0, yend);
-    w.template iteration<1>(g, r + 1, y0, yend);
-    w.template iteration<2>(g, r + 2, y0, yend);
-    w.template iteration<3>(g, r + 3, y0, yend);
-    w.template iteration<4>(g, r + 4, y0, yend);
-    w.template iteration<5>(g, r + 5, y0, yend);
-    w.template iteration<6>(g, r + 6, y0, yend);
-    w.template iteration<7>(g, r + 7, y0, yend);
+    [&]<int... K>(std::integer_sequence<int, K...>) {
+      (w.template iteration<K>(g, r + K, y0, yend), ...);
+    }(std::make_integer_sequence<int, kWin>{});
   }
 }
 
-template <typename T, int VMODE, int CLS>
+template <typename T, int VMODE, int CLS, int kWin, int PF>
 hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
   StepArgs<T> g;
   g.q2i = static_cast<const T*>(L.in[0]);
@@ -250,34 +302,45 @@ hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
   g.q2o = static_cast<T*>(L.out[0]);
   g.q3o = static_cast<T*>(L.out[1]);
   g.q4o = static_cast<T*>(L.out[2]);
+  g.plane_bytes = static_cast<unsigned>(static_cast<size_t>(L.nx) * L.ny * sizeof(T));
   g.nx = L.nx;
   g.ny = L.ny;
   g.strips = (L.nx + kStripCols - 1) / kStripCols;
-  g.rows_per_seg = L.rows_per_seg;
-  g.segs = (L.ny + L.rows_per_seg - 1) / L.rows_per_seg;
-  // rows_per_seg + 2 halos, rounded up to the unroll depth
+  // the requested rows plus both halos, rounded up to the unroll depth; the
+  // segment then takes every row those iterations produce
   g.iters = ((L.rows_per_seg + 2 * kHalo + kWin - 1) / kWin) * kWin;
+  g.rows_per_seg = g.iters - 2 * kHalo;
+  g.segs = (L.ny + g.rows_per_seg - 1) / g.rows_per_seg;
   g.d4 = static_cast<T>(L.delta * 0.25);
   const int blocks_per_seg = (g.strips + kWavesPerBlock - 1) / kWavesPerBlock;
   const int blocks = blocks_per_seg * g.segs;
-  hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS>), dim3(blocks),
+  hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF>), dim3(blocks),
                      dim3(kWave * kWavesPerBlock), 0, stream, g);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_prec(const StepLaunch& L, hipStream_t stream) {
+template <typename T, int kWin, int PF>
+hipError_t launch_pf(const StepLaunch& L, hipStream_t stream) {
   const bool large = L.angle_class == kLarge;
   switch (L.vmode) {
     case kVSkewHalf:
-      return large ? launch_typed<T, kVSkewHalf, kLarge>(L, stream)
-                   : launch_typed<T, kVSkewHalf, kSmall>(L, stream);
+      return large ? launch_typed<T, kVSkewHalf, kLarge, kWin, PF>(L, stream)
+                   : launch_typed<T, kVSkewHalf, kSmall, kWin, PF>(L, stream);
     case kVPaper:
-      return large ? launch_typed<T, kVPaper, kLarge>(L, stream)
-                   : launch_typed<T, kVPaper, kSmall>(L, stream);
+      return large ? launch_typed<T, kVPaper, kLarge, kWin, PF>(L, stream)
+                   : launch_typed<T, kVPaper, kSmall, kWin, PF>(L, stream);
     default:
-      return large ? launch_typed<T, kVNone, kLarge>(L, stream)
-                   : launch_typed<T, kVNone, kSmall>(L, stream);
+      return large ? launch_typed<T, kVNone, kLarge, kWin, PF>(L, stream)
+                   : launch_typed<T, kVNone, kSmall, kWin, PF>(L, stream);
+  }
+}
+
+template <typename T>
+hipError_t launch_prec(const StepLaunch& L, hipStream_t stream) {
+  switch (L.prefetch) {
+    case 2: return launch_pf<T, 8, 2>(L, stream);
+    case 3: return launch_pf<T, 12, 3>(L, stream);
+    default: return launch_pf<T, 12, 4>(L, stream);
   }
 }
 
@@ -287,6 +350,6 @@ hipError_t launch_step(const StepLaunch& L, hipStream_t stream) {
   return L.fp32 ? launch_prec<float>(L, stream) : launch_prec<double>(L, stream);
 }
 
-int step_rows_granularity() { return kWin; }
+
 
 }  // namespace qla

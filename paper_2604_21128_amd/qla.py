@@ -71,7 +71,7 @@ def load(path: str = LIB_PATH):
         "qla_energy_device": (st, [vp, vp]),
         "qla_get_coefficients": (st, [vp, dp, dp, dp]),
         "qla_step_count": (st, [vp, ctypes.POINTER(i64)]),
-        "qla_set_tuning": (st, [vp, ctypes.c_int]),
+        "qla_set_tuning": (st, [vp, ctypes.c_int, ctypes.c_int]),
         "qla_destroy": (st, [vp]),
         "qla_strerror": (ctypes.c_char_p, [st]),
         "qla_last_error": (ctypes.c_char_p, []),
@@ -188,8 +188,9 @@ def qla_step_count(ctx: int) -> int:
     return int(v.value)
 
 
-def qla_set_tuning(ctx: int, rows_per_segment: int) -> None:
-    _check(load().qla_set_tuning(ctypes.c_void_p(ctx), int(rows_per_segment)), "qla_set_tuning")
+def qla_set_tuning(ctx: int, rows_per_segment: int = 0, prefetch_rows: int = 0) -> None:
+    _check(load().qla_set_tuning(ctypes.c_void_p(ctx), int(rows_per_segment), int(prefetch_rows)),
+           "qla_set_tuning")
 
 
 def qla_strerror(status: int) -> str:

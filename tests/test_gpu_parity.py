@@ -91,7 +91,7 @@ def test_energy_matches_oracle(qla, prec):
         e = lat.energy()
         stored = lat.fields()
     want = oracle.energy(_oracle_state(np.ones((ny, nx)), stored))
-    assert abs(e / want - 1) < 1e-14
+    assert abs(e / want - 1) < 1e-12    # summation order differs from the oracle's
 
 
 # ---------------------------------------------------------------------------------------
@@ -118,11 +118,11 @@ def test_parity_small_workload(qla, prec, vmode):
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("nx,ny,steps,rows", [
     (8, 8, 5, 0),          # smallest lattice: one wave covers the row 8 times over
-    (57, 121, 7, 0),       # one column past a strip, one row past a segment
-    (131, 77, 9, 8),       # ragged, smallest segment
+    (57, 121, 7, 0),       # one column past a strip, ragged rows
+    (131, 77, 9, 1),       # ragged, smallest segment
     (200, 9, 6, 16),       # short and wide
     (9, 300, 6, 40),       # tall and narrow
-    (112, 240, 4, 120),    # exact multiples of the strip and segment
+    (112, 240, 4, 120),    # exact multiples of the strip
 ])
 def test_parity_ragged_random(qla, prec, nx, ny, steps, rows):
     n = _random_index(ny, nx, seed=nx * 1000 + ny)
@@ -222,9 +222,9 @@ def test_runs_are_deterministic_and_tiling_independent(qla):
     w = workloads.parity_small()
     n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
     outs, energies = [], []
-    for rows in (0, 8, 64, 0):
+    for rows, pf in ((0, 0), (8, 2), (64, 3), (1, 4), (100, 2), (0, 0)):
         with qla.Lattice(w.nx, w.ny, w.delta) as lat:
-            qla.qla_set_tuning(lat.ctx, rows)
+            qla.qla_set_tuning(lat.ctx, rows, pf)
             lat.set_index(n)
             lat.init_packet(w.packet)
             lat.advance(40)
@@ -276,7 +276,7 @@ def test_error_paths(qla):
         with pytest.raises(qla.QlaError):
             lat.set_index(bad)
         with pytest.raises(qla.QlaError) as e:
-            qla.qla_set_tuning(lat.ctx, 12)                  # not a multiple of 8
+            qla.qla_set_tuning(lat.ctx, 24, 7)               # unsupported prefetch depth
         assert e.value.status == qla.QLA_EINVAL
         with pytest.raises(qla.QlaError):
             lat.advance(-1)
