@@ -31,11 +31,17 @@ BYTES_PER_SITE = {"f64": 56, "f32": 28}
 METRIC = "lattice-site updates/s (GLUPS) + HBM GB/s; batched/surrogate instances/s at error"
 
 
-def run_job(qla, torch, w, n_dev, prec_code, out_dev, energies, stream_ptr, record_kernel):
-    """The whole job once; returns (ctx, list of (start, end) events around advances)."""
+def run_job(qla, torch, w, n_dev, prec_code, out_dev, energies, stream_ptr, record_kernel,
+            tuning=None):
+    """The whole job once; returns (ctx, list of (start, end) events around advances).
+    With tuning=None the context autotunes (untimed warm-up only)."""
     ctx = qla.qla_create(w.nx, w.ny, w.delta, prec_code, qla.QLA_V_SKEW_HALF, stream_ptr)
     try:
         qla.qla_set_index_device(ctx, n_dev, w.nx)
+        if tuning is None:
+            qla.qla_autotune(ctx)
+        else:
+            qla.qla_set_tuning(ctx, *tuning)
         p = w.packet
         qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
         pairs = []
@@ -58,7 +64,7 @@ def run_job(qla, torch, w, n_dev, prec_code, out_dev, energies, stream_ptr, reco
     return ctx, pairs
 
 
-def bench_precision(qla, torch, w, prec, steps, warmup):
+def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None):
     code = qla.QLA_F64 if prec == "f64" else qla.QLA_F32
     import workloads
     n_host = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
@@ -70,9 +76,12 @@ def bench_precision(qla, torch, w, prec, steps, warmup):
     sp = stream.cuda_stream
     if not sp:
         raise RuntimeError("bench needs a non-default torch stream")
-    for _ in range(warmup):
-        ctx, _ = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, False)
+    tuning = tuple(forced_tuning) if forced_tuning else None
+    for _ in range(max(1, warmup)):
+        ctx, _ = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, False, tuning)
         torch.cuda.synchronize()
+        if tuning is None:
+            tuning = qla.qla_get_tuning(ctx)
         qla.qla_destroy(ctx)
     times, kernel_ms, drift = [], [], []
     for _ in range(steps):
@@ -81,7 +90,7 @@ def bench_precision(qla, torch, w, prec, steps, warmup):
         t1 = torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
         t0.record()
-        ctx, pairs = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, True)
+        ctx, pairs = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, True, tuning)
         t1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
@@ -96,17 +105,148 @@ def bench_precision(qla, torch, w, prec, steps, warmup):
               file=sys.stderr, flush=True)
     t = max(times)
     sites = w.nx * w.ny * w.steps
-    k_s = sum(kernel_ms) / len(kernel_ms) / 1e3
-    achieved = BYTES_PER_SITE[prec] * w.nx * w.ny / k_s / 1e9
+    k_s = sum(kernel_ms) / len(kernel_ms) / 1e3          # seconds per QLA step
+    rows, pf, fused = tuning
+    launch_s = k_s * fused                               # one launch applies `fused` steps
+    algorithmic = BYTES_PER_SITE[prec] * w.nx * w.ny * fused
+    achieved = algorithmic / launch_s / 1e9
+    traffic = measured_traffic(w, prec, tuning)
     return {
         "glups": sites / t / 1e9,
         "seconds": t,
         "kernel_us": k_s * 1e6,
         "kernel_glups": w.nx * w.ny / k_s / 1e9,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": (round(traffic / launch_s / 1e9, 1) if traffic else None)},
+        "launch": {"steps_per_launch": fused, "rows_per_segment": rows, "prefetch_rows": pf,
+                   "launch_us": round(launch_s * 1e6, 2),
+                   "algorithmic_bytes_per_launch": algorithmic,
+                   "hbm_bytes_per_launch": traffic},
         "energy_max_rel_drift": max(drift),
     }
+
+
+STEP_SOURCES = ("paper_2604_21128_amd/csrc/qla_step.hip", "paper_2604_21128_amd/csrc/qla_device.h")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "qla_step_ez_4096_ellipse.json")
+
+
+def step_kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(w, prec, tuning):
+    """HBM bytes per launch of the step kernel from the committed counter summary,
+    or None if the kernel source or its tuning changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256") != step_kernel_sha() or rec.get("workload") != w.name:
+        return None
+    r = rec.get(prec)
+    if not r or tuple(r.get("tuning", ())) != tuple(tuning):
+        return None
+    return r["hbm_bytes_per_launch"]
+
+
+def recorded_tuning(w):
+    """The tuning under which the committed counters were taken, if the step kernel is
+    unchanged since (it was the autotuner's choice then); else {} and the run autotunes."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    if rec.get("kernel_sha256") != step_kernel_sha() or rec.get("workload") != w.name:
+        return {}
+    return {p: rec[p]["tuning"] for p in ("f64", "f32") if p in rec}
+
+
+def summarize_counters(fetch_dir, write_dir, trace_dir, tuning_json):
+    """Turn rocprofv3 outputs (one FETCH_SIZE run, one WRITE_SIZE run, one kernel trace)
+    into profiles/qla_step_ez_4096_ellipse.{md,json}. The FETCH_SIZE and WRITE_SIZE
+    values of every kernel are scaled by what the counters read for the 1 GiB reference
+    copy in the same run."""
+    import collections
+    import csv
+    import glob
+    def load(d, ctr):
+        out = collections.defaultdict(list)
+        for fn in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for r in csv.DictReader(open(fn)):
+                if r["Counter_Name"] == ctr:
+                    out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return out
+    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    ref = "__amd_rocclr_copyBuffer"
+    kib = 1048576.0
+    fcopy = max(fe[ref]); wcopy = max(wr[ref])
+    fs, ws = kib / fcopy, kib / wcopy
+    tuning = json.loads(tuning_json)
+    w = __import__("workloads").plain_4096()
+    n = w.nx * w.ny
+    rec = {"workload": w.name, "kernel_sha256": step_kernel_sha(), "fetch_scale": fs,
+           "write_scale": ws}
+    lines = [f"# qla_step_ez_kernel on the {w.nx}x{w.ny} ellipse workload (MI355X, gfx950)", "",
+             "Commands (from /tmp with TMPDIR=/tmp; R = repository root; tuning fixed to the "
+             "autotuned values below):", "", "```"]
+    lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_trace "
+              f"-o trace -- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 2000 "
+              f"--no-cpu-baseline",
+              f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof_fetch -o fetch "
+              f"-- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 100 --no-cpu-baseline "
+              f"--copy-probe-mib 1024",
+              f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof_write -o write "
+              f"-- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 100 --no-cpu-baseline "
+              f"--copy-probe-mib 1024",
+              f"python3 $R/bench.py --summarize-counters $R/gpurun_out/prof_fetch "
+              f"$R/gpurun_out/prof_write $R/gpurun_out/prof_trace '<tuning json>'", "```", ""]
+    lines += ["## Kernel trace (--stats)", "", "| kernel | calls | average (us) | min (us) | max (us) |",
+              "|---|---|---|---|---|"]
+    avg_ns = {}
+    for fn in glob.glob(os.path.join(trace_dir, "*kernel_stats.csv")):
+        for r in csv.DictReader(open(fn)):
+            name = r["Name"].replace("(anonymous namespace)::", "")
+            short = name.split("(qla::")[0].split("(double")[0].split("(float")[0]
+            avg_ns[name] = float(r["AverageNs"])
+            lines.append(f"| `{short[:80]}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
+                         f"{float(r['MinNs'])/1e3:.1f} | {float(r['MaxNs'])/1e3:.1f} |")
+    lines += ["", "## HBM traffic per dispatch (hardware counters, KiB)", "",
+              f"Reference: a 1 GiB device copy (`{ref}`, 1048576 KiB read and written) reads "
+              f"FETCH_SIZE = {fcopy:.1f} and WRITE_SIZE = {wcopy:.1f}; scale factors "
+              f"{fs:.4f} (fetch) and {ws:.4f} (write).", "",
+              "| kernel | steps/launch | FETCH raw | WRITE raw | read scaled | write scaled | "
+              "algorithmic read | algorithmic write | traffic / algorithmic |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    for k in fe:
+        if "qla_step_ez_kernel" not in k:
+            continue
+        prec = "f64" if "<double" in k else "f32"
+        e = 8 if prec == "f64" else 4
+        t = tuning[prec]
+        fused = int(t[2])
+        fr = sum(fe[k]) / len(fe[k]); wv = sum(wr[k]) / len(wr[k])
+        ar, aw = 4 * n * e / 1024, 3 * n * e / 1024
+        hbm = (fr * fs + wv * ws) * 1024
+        rec[prec] = {"tuning": t, "hbm_bytes_per_launch": hbm,
+                     "algorithmic_bytes_per_launch": 7 * n * e * fused}
+        lines.append(f"| step {prec} | {fused} | {fr:.0f} | {wv:.0f} | {fr*fs:.0f} | {wv*ws:.0f} | "
+                     f"{ar:.0f} | {aw:.0f} | {(fr*fs+wv*ws)/(ar+aw):.3f} |")
+    lines += ["", "Algorithmic bytes per launch count every step the launch applies (56 B per site "
+              "update in FP64, 28 B in FP32); the read and write columns are per launch.", ""]
+    base = os.path.join(ROOT, "profiles", "qla_step_ez_4096_ellipse")
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(lines))
+    with open(base + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    print("\n".join(lines))
 
 
 def cpu_baseline(w, sample_steps):
@@ -135,10 +275,17 @@ def main():
     ap.add_argument("--precisions", default="f64,f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR",
+                                                               "TRACE_DIR", "TUNING_JSON"))
+    ap.add_argument("--tuning-json", default="",
+                    help='fixed tuning instead of autotuning, e.g. {"f64": [176, 3, 2]}')
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (a reference kernel of "
                          "known traffic for hardware counters)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU halo-exchange path "
               "is not part of it (run with --gpus 1)", file=sys.stderr)
@@ -165,8 +312,9 @@ def main():
     results = {}
     stream = torch.cuda.Stream()   # default priority
     with torch.cuda.stream(stream):
+        forced = json.loads(args.tuning_json) if args.tuning_json else recorded_tuning(w)
         for p in precs:
-            results[p] = bench_precision(qla, torch, w, p, args.steps, args.warmup)
+            results[p] = bench_precision(qla, torch, w, p, args.steps, args.warmup, forced.get(p))
     main_p = precs[0]
     r = results[main_p]
     line = {
@@ -186,6 +334,7 @@ def main():
                    "energy_every": w.energy_every, "delta": w.delta, "potential": "skew_half",
                    "ellipse": dataclasses.asdict(w.ellipse), "packet": dataclasses.asdict(w.packet)},
         "roofline": r["roofline"],
+        "launch": r["launch"],
         "step_kernel_us": round(r["kernel_us"], 2),
         "step_kernel_glups": round(r["kernel_glups"], 2),
         "energy_max_rel_drift": r["energy_max_rel_drift"],
@@ -194,6 +343,7 @@ def main():
         rp = results[p]
         line[p] = {"value": round(rp["glups"], 3), "unit": "GLUPS",
                    "ms_per_step": round(rp["seconds"] * 1e3, 3), "roofline": rp["roofline"],
+                   "launch": rp["launch"],
                    "step_kernel_us": round(rp["kernel_us"], 2),
                    "energy_max_rel_drift": rp["energy_max_rel_drift"]}
     if not args.no_cpu_baseline:

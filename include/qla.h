@@ -147,9 +147,24 @@ qla_status qla_step_count(const qla_ctx *ctx, int64_t *steps);
 
 /* Tuning of the step kernel (results do not depend on it, bit for bit):
  * rows_per_segment = output rows each wavefront marches through (rounded up so
- * that the rows plus 8 halo rows fill whole unrolled loop trips; 0 = default);
- * prefetch_rows = how many rows ahead its loads run (2, 3 or 4; 0 = default). */
-qla_status qla_set_tuning(qla_ctx *ctx, int rows_per_segment, int prefetch_rows);
+ * that the rows plus the halo rows fill whole unrolled loop trips; 0 = default);
+ * prefetch_rows = how many rows ahead its loads run (2 or 3; 0 = default);
+ * steps_per_pass = steps of Eq. (2e14) applied per pass over HBM (1 or 2,
+ * temporal blocking; 0 = default). */
+qla_status qla_set_tuning(qla_ctx *ctx, int rows_per_segment, int prefetch_rows,
+                          int steps_per_pass);
+
+/* Pick the tuning of the step kernel for this context's lattice by timing
+ * candidate segment heights, prefetch depths and steps per pass on it (tens of
+ * milliseconds). The state and step counter are saved and restored, so results
+ * are unaffected; the chosen values are kept and returned through the non-NULL
+ * pointers. Synchronises. QLA_ESTATE if no index is set. */
+qla_status qla_autotune(qla_ctx *ctx, int *rows_per_segment, int *prefetch_rows,
+                        int *steps_per_pass);
+
+/* The tuning currently in use (see qla_set_tuning). */
+qla_status qla_get_tuning(const qla_ctx *ctx, int *rows_per_segment, int *prefetch_rows,
+                          int *steps_per_pass);
 
 /* Release every resource of the context (NULL is accepted). Synchronises. */
 qla_status qla_destroy(qla_ctx *ctx);

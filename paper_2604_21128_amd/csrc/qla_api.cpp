@@ -15,6 +15,7 @@
 namespace {
 constexpr int kDefaultRows = 24;
 constexpr int kDefaultPrefetch = 3;
+constexpr int kDefaultFused = 2;
 }  // namespace
 
 struct qla_ctx {
@@ -38,6 +39,7 @@ struct qla_ctx {
   int angle_class = 0;
   int rows_per_seg = kDefaultRows;
   int prefetch = kDefaultPrefetch;
+  int fused = kDefaultFused;
   size_t count() const { return static_cast<size_t>(nx) * static_cast<size_t>(ny); }
   size_t elem() const { return fp32 ? sizeof(float) : sizeof(double); }
 };
@@ -286,30 +288,123 @@ qla_status qla_set_fields(qla_ctx* c, const double* q_host, int64_t step) {
   return QLA_OK;
 }
 
-qla_status qla_advance(qla_ctx* c, int64_t k) {
-  if (!c) return fail(QLA_EINVAL, "NULL context");
-  if (k < 0) return fail(QLA_EINVAL, "k < 0");
-  if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
-  DeviceGuard g(c->device);
+namespace {
+
+// Enqueue k steps on the context's stream with the given tuning (no checks).
+qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused) {
   qla::StepLaunch L{};
   L.n = c->fp32 ? static_cast<const void*>(c->n32) : static_cast<const void*>(c->n64);
   L.nx = c->nx;
   L.ny = c->ny;
-  L.rows_per_seg = c->rows_per_seg;
-  L.prefetch = c->prefetch;
+  L.rows_per_seg = rows;
+  L.prefetch = prefetch;
   L.delta = c->delta;
   L.fp32 = c->fp32;
   L.vmode = c->vmode;
   L.angle_class = c->angle_class;
-  for (int64_t s = 0; s < k; ++s) {
+  // passes of `fused` steps, then single steps for the remainder
+  int64_t done = 0;
+  while (done < k) {
+    L.fused_steps = (k - done >= fused) ? fused : 1;
     for (int j = 0; j < 3; ++j) {
       L.in[j] = c->q[c->cur][j];
       L.out[j] = c->q[c->cur ^ 1][j];
     }
     QLA_HIP(qla::launch_step(L, c->stream));
     c->cur ^= 1;
-    ++c->steps;
+    c->steps += L.fused_steps;
+    done += L.fused_steps;
   }
+  return QLA_OK;
+}
+
+}  // namespace
+
+qla_status qla_advance(qla_ctx* c, int64_t k) {
+  if (!c) return fail(QLA_EINVAL, "NULL context");
+  if (k < 0) return fail(QLA_EINVAL, "k < 0");
+  if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
+  DeviceGuard g(c->device);
+  return enqueue_steps(c, k, c->rows_per_seg, c->prefetch, c->fused);
+}
+
+qla_status qla_autotune(qla_ctx* c, int* rows_out, int* prefetch_out, int* steps_per_pass_out) {
+  if (!c) return fail(QLA_EINVAL, "NULL context");
+  if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
+  DeviceGuard g(c->device);
+  const size_t bytes = 3 * c->count() * c->elem();
+  // keep the state: the trial launches overwrite both amplitude buffers
+  char* save = reinterpret_cast<char*>(c->staging);
+  for (int j = 0; j < 3; ++j)
+    QLA_HIP(hipMemcpyAsync(save + j * c->count() * c->elem(), c->q[c->cur][j],
+                           c->count() * c->elem(), hipMemcpyDeviceToDevice, c->stream));
+  (void)bytes;
+  const int64_t steps_saved = c->steps;
+  const int cur_saved = c->cur;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  QLA_HIP(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(he, "hipEventCreate");
+  }
+  static const int kRows[] = {24, 40, 56, 80, 112, 144, 176, 240, 320, 480, 720};
+  static const int kPrefetch[] = {2, 3};
+  static const int kFused[] = {1, 2};
+  double best = 1e300;
+  int brows = c->rows_per_seg, bpf = c->prefetch, bfused = c->fused;
+  qla_status st = QLA_OK;
+  for (int fused : kFused) {
+    for (int pf : kPrefetch) {
+      for (int rows : kRows) {
+        if (rows > c->ny + 8 && rows != kRows[0]) continue;
+        // one warm-up pass, then enough steps for a stable time
+        st = enqueue_steps(c, fused, rows, pf, fused);
+        if (st != QLA_OK) break;
+        const int64_t trial = 8 * fused;
+        he = hipEventRecord(e0, c->stream);
+        if (he == hipSuccess) st = enqueue_steps(c, trial, rows, pf, fused);
+        if (he == hipSuccess && st == QLA_OK) he = hipEventRecord(e1, c->stream);
+        if (he == hipSuccess && st == QLA_OK) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess && st == QLA_OK) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) st = hip_fail(he, "autotune timing");
+        if (st != QLA_OK) break;
+        const double per_step = ms / static_cast<double>(trial);
+        if (per_step < best) {
+          best = per_step;
+          brows = rows;
+          bpf = pf;
+          bfused = fused;
+        }
+      }
+      if (st != QLA_OK) break;
+    }
+    if (st != QLA_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->cur = cur_saved;
+  c->steps = steps_saved;
+  for (int j = 0; j < 3; ++j)
+    QLA_HIP(hipMemcpyAsync(c->q[c->cur][j], save + j * c->count() * c->elem(),
+                           c->count() * c->elem(), hipMemcpyDeviceToDevice, c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  if (st != QLA_OK) return st;
+  c->rows_per_seg = brows;
+  c->prefetch = bpf;
+  c->fused = bfused;
+  if (rows_out) *rows_out = brows;
+  if (prefetch_out) *prefetch_out = bpf;
+  if (steps_per_pass_out) *steps_per_pass_out = bfused;
+  return QLA_OK;
+}
+
+qla_status qla_get_tuning(const qla_ctx* c, int* rows, int* prefetch, int* steps_per_pass) {
+  if (!c) return fail(QLA_EINVAL, "NULL context");
+  if (rows) *rows = c->rows_per_seg;
+  if (prefetch) *prefetch = c->prefetch;
+  if (steps_per_pass) *steps_per_pass = c->fused;
   return QLA_OK;
 }
 
@@ -376,14 +471,18 @@ qla_status qla_step_count(const qla_ctx* c, int64_t* steps) {
   return QLA_OK;
 }
 
-qla_status qla_set_tuning(qla_ctx* c, int rows_per_segment, int prefetch_rows) {
+qla_status qla_set_tuning(qla_ctx* c, int rows_per_segment, int prefetch_rows,
+                          int steps_per_pass) {
   if (!c) return fail(QLA_EINVAL, "NULL context");
   if (rows_per_segment < 0 || rows_per_segment > (1 << 20))
     return fail(QLA_EINVAL, "rows_per_segment must be in [0, 2^20]");
-  if (prefetch_rows != 0 && (prefetch_rows < 2 || prefetch_rows > 4))
-    return fail(QLA_EINVAL, "prefetch_rows must be 0 (default), 2, 3 or 4");
+  if (prefetch_rows != 0 && prefetch_rows != 2 && prefetch_rows != 3)
+    return fail(QLA_EINVAL, "prefetch_rows must be 0 (default), 2 or 3");
+  if (steps_per_pass < 0 || steps_per_pass > 2)
+    return fail(QLA_EINVAL, "steps_per_pass must be 0 (default), 1 or 2");
   c->rows_per_seg = rows_per_segment ? rows_per_segment : kDefaultRows;
   c->prefetch = prefetch_rows ? prefetch_rows : kDefaultPrefetch;
+  c->fused = steps_per_pass ? steps_per_pass : kDefaultFused;
   return QLA_OK;
 }
 

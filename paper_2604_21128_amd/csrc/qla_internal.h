@@ -18,7 +18,8 @@ struct StepLaunch {
   const void* n;
   int nx, ny;
   int rows_per_seg;  // requested output rows per wavefront segment (rounded up)
-  int prefetch;      // rows the loads run ahead: 2, 3 or 4
+  int prefetch;      // rows the loads run ahead: 2 or 3
+  int fused_steps;   // steps applied per pass: 1 or 2
   double delta;
   bool fp32;
   int vmode;

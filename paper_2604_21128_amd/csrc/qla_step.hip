@@ -31,9 +31,10 @@
 //   - U_y runs down the rows inside each lane as a software pipeline: when row r
 //     arrives, set 1 finishes row r-1, set 2 row r-2, set 3 row r-3 and set 4 row
 //     r-4, which then gets V_x, V_y and is stored.
-// The rows of the window live in registers, indexed modulo 8 with the loop
-// unrolled 8 times so every index is static; loads run 2 rows ahead. The segment
-// starts 4 rows early and ends 4 rows late (vertical halo). Rotations use the
+// The rows of the window live in registers, indexed modulo the window depth with
+// the loop unrolled that many times so every index is static; loads run 2-3 rows
+// ahead. The segment starts 4 rows early and ends 4 rows late (vertical halo).
+// One pass can also apply two steps (temporal blocking, see Marcher). Rotations use the
 // three-shear form (qla_device.h); angles come from n on the fly, so HBM traffic
 // is exactly three amplitude planes in and out plus n in.
 #include <hip/hip_runtime.h>
@@ -48,8 +49,6 @@ namespace qla {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kHalo = 4;
-constexpr int kStripCols = kWave - 2 * kHalo;  // 56 output columns per wave
 constexpr int kWavesPerBlock = 4;
 // A buffer store whose offset is at least the buffer's size is discarded by the
 // hardware; stores of halo lanes and of rows outside the segment use this offset
@@ -62,6 +61,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, unsi
   // raw buffer (stride 0), 32-bit dwords, range-checked against `bytes`
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes),
                                            0x00020000);
+}
+
+__device__ __forceinline__ unsigned long long bits_of(double v) {
+  return __builtin_bit_cast(unsigned long long, v);
+}
+__device__ __forceinline__ unsigned long long bits_of(float v) {
+  return __builtin_bit_cast(unsigned int, v);
+}
+// The bit pattern of lane 0's value, in scalar registers.
+__device__ __forceinline__ unsigned long long lane0_bits(double v) {
+  const unsigned long long b = bits_of(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(b));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(b >> 32));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long lane0_bits(float v) {
+  return __builtin_amdgcn_readfirstlane(__builtin_bit_cast(unsigned, v));
 }
 
 template <typename T>
@@ -98,34 +114,60 @@ struct StepArgs {
 };
 
 // kWin: register window depth in rows (the loop is unrolled kWin times so every
-// window index is static); PF: how many rows ahead the loads run.
-template <typename T, int VMODE, int CLS, int kWin, int PF>
+// window index is static); PF: how many rows ahead the loads run; TS: how many
+// steps one pass applies (temporal blocking).
+//
+// With TS steps per pass, stage k (k = 0 .. TS-1) applies step k + 1. Stage 0
+// receives the freshly loaded row r; stage k receives row r - 4k, the row stage
+// k-1 completed in the same iteration, and completes row r - 4k - 4. The stages
+// share one window: a row keeps its slot from its load until its store. Each
+// stage widens the dependence by 4 cells in x and y, so a pass has 4 TS halo
+// columns on each side of the strip and 4 TS halo rows at each end of a segment.
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
 struct Marcher {
-  static_assert(PF + 6 <= kWin, "a prefetched row must not overwrite a live one");
+  static_assert(PF + 4 * TS + 2 <= kWin, "a prefetched row must not overwrite a live one");
   // Row window: amplitudes, index, 1/n and the collision shear of each row.
   T A[kWin], P4[kWin], P3[kWin], N[kWin], M[kWin], Tt[kWin], Ts[kWin];
+  // Per-row wave-uniform facts, one bit per slot in scalar registers: umask bit s
+  // says all 64 lanes of the row in slot s hold the same n; emask bit s says so
+  // and that this n equals the previous row's (also uniform) n. In a uniform row
+  // the neighbours' collision angles equal the lane's own; where a row and its
+  // two vertical neighbours hold one common n every potential angle is exactly 0
+  // (V = I).
+  unsigned umask, emask;
+  unsigned long long nb_prev;  // n's bit pattern in lane 0 of the previous row
   __amdgpu_buffer_rsrc_t r2i, r3i, r4i, rn, r2o, r3o, r4o;
   unsigned col_bytes;    // this lane's column (wrapped) in bytes
   unsigned store_bytes;  // col_bytes for lanes that own an output column, else kDropOffset
   unsigned row_bytes;    // nx * sizeof(T)
   int yin;               // row index of the next row to load (wrapped)
 
+  static constexpr int slot(int s, int back) { return ((s - back) % kWin + kWin) % kWin; }
+
   // y is uniform across the wave: the row offset is a scalar register and every
   // lane adds its fixed column offset.
-  __device__ __forceinline__ void load_row(int slot, int y) {
+  __device__ __forceinline__ void load_row(int s, int y) {
     const unsigned soff = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(y)) * row_bytes;
-    A[slot] = buf_load<T>(r2i, col_bytes, soff);
-    P3[slot] = buf_load<T>(r3i, col_bytes, soff);
-    P4[slot] = buf_load<T>(r4i, col_bytes, soff);
-    N[slot] = buf_load<T>(rn, col_bytes, soff);
+    A[s] = buf_load<T>(r2i, col_bytes, soff);
+    P3[s] = buf_load<T>(r3i, col_bytes, soff);
+    P4[s] = buf_load<T>(r4i, col_bytes, soff);
+    N[s] = buf_load<T>(rn, col_bytes, soff);
   }
 
-  // U_x on the just-arrived row (slot s): lanes exchange neighbour values by DPP.
+  // U_x on one row (slot s): lanes exchange neighbour values by DPP. In a
+  // uniform row the neighbours' shears are the lane's own and are not exchanged
+  // (the two versions differ only in the end lanes, which are halo).
   __device__ __forceinline__ void ux(int s) {
+    if (umask & (1u << s)) {
+      ux_with(s, Tt[s], Ts[s], Tt[s], Ts[s]);
+    } else {
+      ux_with(s, from_left(Tt[s]), from_left(Ts[s]), from_right(Tt[s]), from_right(Ts[s]));
+    }
+  }
+
+  __device__ __forceinline__ void ux_with(int s, T tl, T sl, T tr, T sr) {
     T a = A[s], p = P4[s];
     const T t0 = Tt[s], s0 = Ts[s];
-    const T tl = from_left(t0), sl = from_left(s0);
-    const T tr = from_right(t0), sr = from_right(s0);
     // set 1: C^T on site; C(th_i) on (a_i, p_{i-1})
     rotate(a, p, -t0, -s0);
     {
@@ -162,83 +204,108 @@ struct Marcher {
     P4[s] = p;
   }
 
-  // U_y pipeline after row r (slot s0) arrived; C_y = R(-th), C_y^T = R(+th).
-  template <int S0>
+  // U_y pipeline of one stage after its row a (slot SA) arrived; C_y = R(-th),
+  // C_y^T = R(+th).
+  template <int SA>
   __device__ __forceinline__ void uy() {
-    constexpr int s0 = S0, s1 = (S0 + kWin - 1) % kWin, s2 = (S0 + kWin - 2) % kWin;
-    constexpr int s3 = (S0 + kWin - 3) % kWin, s4 = (S0 + kWin - 4) % kWin;
-    // set 1 on row r: on-site C_y^T, then (a_r, p_{r-1}) with C_y(th_r)
+    constexpr int s0 = SA, s1 = slot(SA, 1), s2 = slot(SA, 2), s3 = slot(SA, 3),
+                  s4 = slot(SA, 4);
+    // set 1 on row a: on-site C_y^T, then (a_a, p_{a-1}) with C_y(th_a)
     rotate(A[s0], P3[s0], Tt[s0], Ts[s0]);
     rotate(A[s0], P3[s1], -Tt[s0], -Ts[s0]);
-    // set 2 on row r-1: on-site C_y^T, then (a_{r-1}, p_{r-2}) with C_y(th_{r-2})
+    // set 2 on row a-1: on-site C_y^T, then (a_{a-1}, p_{a-2}) with C_y(th_{a-2})
     rotate(A[s1], P3[s1], Tt[s1], Ts[s1]);
     rotate(A[s1], P3[s2], -Tt[s2], -Ts[s2]);
-    // set 3 on row r-2: on-site C_y, then (a_{r-3}, p_{r-2}) with C_y^T(th_{r-3})
+    // set 3 on row a-2: on-site C_y, then (a_{a-3}, p_{a-2}) with C_y^T(th_{a-3})
     rotate(A[s2], P3[s2], -Tt[s2], -Ts[s2]);
     rotate(A[s3], P3[s2], Tt[s3], Ts[s3]);
-    // set 4 on row r-3: on-site C_y, then (a_{r-4}, p_{r-3}) with C_y^T(th_{r-3})
+    // set 4 on row a-3: on-site C_y, then (a_{a-4}, p_{a-3}) with C_y^T(th_{a-3})
     rotate(A[s3], P3[s3], -Tt[s3], -Ts[s3]);
     rotate(A[s4], P3[s3], Tt[s3], Ts[s3]);
   }
 
-  // V_x, V_y on the completed row r-4.
-  template <int S0>
+  // V_x, V_y on the row a - 4 that the stage just completed (slot SC).
+  template <int SC>
   __device__ __forceinline__ void potentials(T d4) {
     if constexpr (VMODE == kVNone) {
       return;
     } else {
-      constexpr int s3 = (S0 + kWin - 3) % kWin, s4 = (S0 + kWin - 4) % kWin;
-      constexpr int s5 = (S0 + kWin - 5) % kWin;
-      const T m = M[s4];
+      constexpr int sc = SC, sup = slot(SC, -1), sdn = slot(SC, 1);
+      if ((emask & (1u << sc)) && (emask & (1u << sup))) return;
+      const T m = M[sc];
       const T dm = d4 * m * m;
-      const T nl = from_left(N[s4]), nr = from_right(N[s4]);
+      const T nl = from_left(N[sc]), nr = from_right(N[sc]);
       const T hbx = (nr - nl) * dm;          // beta_x / 2
-      const T hby = (N[s3] - N[s5]) * dm;    // beta_y / 2
+      const T hby = (N[sup] - N[sdn]) * dm;  // beta_y / 2
       if constexpr (VMODE == kVSkewHalf) {
         const Shear<T> vx = shear_of<T, CLS>(hbx);
-        rotate(A[s4], P4[s4], -vx.t, -vx.s);
+        rotate(A[sc], P4[sc], -vx.t, -vx.s);
         const Shear<T> vy = shear_of<T, CLS>(hby);
-        rotate(A[s4], P3[s4], vy.t, vy.s);
+        rotate(A[sc], P3[sc], vy.t, vy.s);
       } else {
         const T bx = hbx + hbx, by = hby + hby;
         const T sbx = sin_series<T, CLS>(bx), cbx = cos_series<T, CLS>(bx);
-        P4[s4] = fma(-sbx, A[s4], cbx * P4[s4]);
+        P4[sc] = fma(-sbx, A[sc], cbx * P4[sc]);
         const T sby = sin_series<T, CLS>(by), cby = cos_series<T, CLS>(by);
-        P3[s4] = fma(sby, A[s4], cby * P3[s4]);
+        P3[sc] = fma(sby, A[sc], cby * P3[sc]);
       }
     }
   }
 
+  template <int S0, int K>
+  __device__ __forceinline__ void stage(T d4) {
+    constexpr int sa = slot(S0, 4 * K);  // row arriving at this stage
+    ux(sa);
+    uy<sa>();
+    potentials<slot(sa, 4)>(d4);
+  }
+
   template <int S0>
   __device__ __forceinline__ void iteration(const StepArgs<T>& g, int r, int y0, int yend) {
-    constexpr int s0 = S0, s4 = (S0 + kWin - 4) % kWin, sp = (S0 + PF) % kWin;
+    constexpr int sp = slot(S0, -PF), sout = slot(S0, 4 * TS);
     // loads for row r + PF (the slot held row r + PF - kWin, no longer needed).
     // Issued unconditionally, also past the segment's end (rows wrap, so they stay
     // in bounds): a branch here would make the compiler wait for them at once.
     load_row(sp, yin);
     yin = (yin + 1 == g.ny) ? 0 : yin + 1;
-    // collision shear of row r
-    const T m = recip(N[s0]);
-    M[s0] = m;
-    const Shear<T> c = shear_of<T, CLS>(g.d4 * m);
-    Tt[s0] = c.t;
-    Ts[s0] = c.s;
-    ux(s0);
-    uy<S0>();
-    // row r - 4 is complete: output row y0 + r - 8
-    potentials<S0>(g.d4);
-    const int yo = y0 + r - 2 * kHalo;
+    // Is row r uniform? Then, if row r - 1 was uniform with the same n, its
+    // collision shear and 1/n are reused; otherwise they are computed.
+    constexpr int sprev = slot(S0, 1);
+    const unsigned long long nb = lane0_bits(N[S0]);
+    const bool uni = __builtin_amdgcn_ballot_w64(bits_of(N[S0]) != nb) == 0;
+    const bool same = uni && (umask & (1u << sprev)) && nb == nb_prev;
+    umask = (umask & ~(1u << S0)) | (uni ? 1u << S0 : 0u);
+    emask = (emask & ~(1u << S0)) | (same ? 1u << S0 : 0u);
+    nb_prev = nb;
+    if (same) {
+      M[S0] = M[sprev];
+      Tt[S0] = Tt[sprev];
+      Ts[S0] = Ts[sprev];
+    } else {
+      const T m = recip(N[S0]);
+      M[S0] = m;
+      const Shear<T> c = shear_of<T, CLS>(g.d4 * m);
+      Tt[S0] = c.t;
+      Ts[S0] = c.s;
+    }
+    [&]<int... K>(std::integer_sequence<int, K...>) {
+      (stage<S0, K>(g.d4), ...);
+    }(std::make_integer_sequence<int, TS>{});
+    // row r - 4 TS has had all TS steps: output row y0 + r - 8 TS
+    const int yo = y0 + r - 8 * TS;
     const bool row_ok = yo >= y0 && yo < yend;
     const unsigned soff = row_ok ? static_cast<unsigned>(yo) * row_bytes : 0u;
     const unsigned voff = row_ok ? store_bytes : kDropOffset;
-    buf_store<T>(A[s4], r2o, voff, soff);
-    buf_store<T>(P3[s4], r3o, voff, soff);
-    buf_store<T>(P4[s4], r4o, voff, soff);
+    buf_store<T>(A[sout], r2o, voff, soff);
+    buf_store<T>(P3[sout], r3o, voff, soff);
+    buf_store<T>(P4[sout], r4o, voff, soff);
   }
 };
 
-template <typename T, int VMODE, int CLS, int kWin, int PF>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(StepArgs<T> g) {
+  constexpr int halo = 4 * TS;
+  constexpr int strip_cols = kWave - 2 * halo;
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
   const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
@@ -247,12 +314,11 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
   const int strip = (blk % blocks_per_seg) * kWavesPerBlock + wib;
   if (seg >= g.segs || strip >= g.strips) return;  // whole wave exits together
 
-  Marcher<T, VMODE, CLS, kWin, PF> w;
-  const int x0 = strip * kStripCols;
-  int col = (x0 - kHalo + lane) % g.nx;
+  Marcher<T, VMODE, CLS, kWin, PF, TS> w;
+  const int x0 = strip * strip_cols;
+  int col = (x0 - halo + lane) % g.nx;
   if (col < 0) col += g.nx;
-  const bool store_lane =
-      lane >= kHalo && lane < kHalo + kStripCols && x0 + lane - kHalo < g.nx;
+  const bool store_lane = lane >= halo && lane < halo + strip_cols && x0 + lane - halo < g.nx;
   w.col_bytes = static_cast<unsigned>(col) * sizeof(T);
   w.store_bytes = store_lane ? w.col_bytes : kDropOffset;
   w.row_bytes = static_cast<unsigned>(g.nx) * sizeof(T);
@@ -269,7 +335,10 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
   for (int k = 0; k < kWin; ++k) {
     w.A[k] = w.P4[k] = w.P3[k] = w.N[k] = w.M[k] = w.Tt[k] = w.Ts[k] = T(0);
   }
-  int y = y0 - kHalo;
+  w.umask = 0;
+  w.emask = 0;
+  w.nb_prev = 0;
+  int y = (y0 - halo) % g.ny;
   if (y < 0) y += g.ny;
   // The prologue issues the first PF rows in the same pattern as the loop body
   // (4 loads, then 3 stores, here discarded ones), so the compiler sees the same
@@ -292,8 +361,10 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
   }
 }
 
-template <typename T, int VMODE, int CLS, int kWin, int PF>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
 hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
+  constexpr int halo = 4 * TS;
+  constexpr int strip_cols = kWave - 2 * halo;
   StepArgs<T> g;
   g.q2i = static_cast<const T*>(L.in[0]);
   g.q3i = static_cast<const T*>(L.in[1]);
@@ -305,43 +376,44 @@ hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
   g.plane_bytes = static_cast<unsigned>(static_cast<size_t>(L.nx) * L.ny * sizeof(T));
   g.nx = L.nx;
   g.ny = L.ny;
-  g.strips = (L.nx + kStripCols - 1) / kStripCols;
+  g.strips = (L.nx + strip_cols - 1) / strip_cols;
   // the requested rows plus both halos, rounded up to the unroll depth; the
   // segment then takes every row those iterations produce
-  g.iters = ((L.rows_per_seg + 2 * kHalo + kWin - 1) / kWin) * kWin;
-  g.rows_per_seg = g.iters - 2 * kHalo;
+  g.iters = ((L.rows_per_seg + 2 * halo + kWin - 1) / kWin) * kWin;
+  g.rows_per_seg = g.iters - 2 * halo;
   g.segs = (L.ny + g.rows_per_seg - 1) / g.rows_per_seg;
   g.d4 = static_cast<T>(L.delta * 0.25);
   const int blocks_per_seg = (g.strips + kWavesPerBlock - 1) / kWavesPerBlock;
   const int blocks = blocks_per_seg * g.segs;
-  hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF>), dim3(blocks),
+  hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF, TS>), dim3(blocks),
                      dim3(kWave * kWavesPerBlock), 0, stream, g);
   return hipGetLastError();
 }
 
-template <typename T, int kWin, int PF>
+template <typename T, int kWin, int PF, int TS>
 hipError_t launch_pf(const StepLaunch& L, hipStream_t stream) {
   const bool large = L.angle_class == kLarge;
   switch (L.vmode) {
     case kVSkewHalf:
-      return large ? launch_typed<T, kVSkewHalf, kLarge, kWin, PF>(L, stream)
-                   : launch_typed<T, kVSkewHalf, kSmall, kWin, PF>(L, stream);
+      return large ? launch_typed<T, kVSkewHalf, kLarge, kWin, PF, TS>(L, stream)
+                   : launch_typed<T, kVSkewHalf, kSmall, kWin, PF, TS>(L, stream);
     case kVPaper:
-      return large ? launch_typed<T, kVPaper, kLarge, kWin, PF>(L, stream)
-                   : launch_typed<T, kVPaper, kSmall, kWin, PF>(L, stream);
+      return large ? launch_typed<T, kVPaper, kLarge, kWin, PF, TS>(L, stream)
+                   : launch_typed<T, kVPaper, kSmall, kWin, PF, TS>(L, stream);
     default:
-      return large ? launch_typed<T, kVNone, kLarge, kWin, PF>(L, stream)
-                   : launch_typed<T, kVNone, kSmall, kWin, PF>(L, stream);
+      return large ? launch_typed<T, kVNone, kLarge, kWin, PF, TS>(L, stream)
+                   : launch_typed<T, kVNone, kSmall, kWin, PF, TS>(L, stream);
   }
 }
 
+// Window depth: the smallest that keeps every live row (PF + 4 TS + 2 rows).
 template <typename T>
 hipError_t launch_prec(const StepLaunch& L, hipStream_t stream) {
-  switch (L.prefetch) {
-    case 2: return launch_pf<T, 8, 2>(L, stream);
-    case 3: return launch_pf<T, 12, 3>(L, stream);
-    default: return launch_pf<T, 12, 4>(L, stream);
+  if (L.fused_steps == 2) {
+    return L.prefetch == 2 ? launch_pf<T, 12, 2, 2>(L, stream)
+                           : launch_pf<T, 13, 3, 2>(L, stream);
   }
+  return L.prefetch == 2 ? launch_pf<T, 8, 2, 1>(L, stream) : launch_pf<T, 9, 3, 1>(L, stream);
 }
 
 }  // namespace

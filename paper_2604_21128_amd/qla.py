@@ -28,7 +28,8 @@ EXPORTED = (
     "qla_create", "qla_set_index", "qla_set_index_device", "qla_init_packet",
     "qla_set_fields", "qla_advance", "qla_get_fields", "qla_get_fields_device",
     "qla_energy", "qla_energy_device", "qla_get_coefficients", "qla_step_count",
-    "qla_set_tuning", "qla_destroy", "qla_strerror", "qla_last_error",
+    "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_destroy", "qla_strerror",
+    "qla_last_error",
 )
 
 
@@ -71,7 +72,11 @@ def load(path: str = LIB_PATH):
         "qla_energy_device": (st, [vp, vp]),
         "qla_get_coefficients": (st, [vp, dp, dp, dp]),
         "qla_step_count": (st, [vp, ctypes.POINTER(i64)]),
-        "qla_set_tuning": (st, [vp, ctypes.c_int, ctypes.c_int]),
+        "qla_set_tuning": (st, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "qla_autotune": (st, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_int)]),
+        "qla_get_tuning": (st, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]),
         "qla_destroy": (st, [vp]),
         "qla_strerror": (ctypes.c_char_p, [st]),
         "qla_last_error": (ctypes.c_char_p, []),
@@ -188,9 +193,25 @@ def qla_step_count(ctx: int) -> int:
     return int(v.value)
 
 
-def qla_set_tuning(ctx: int, rows_per_segment: int = 0, prefetch_rows: int = 0) -> None:
-    _check(load().qla_set_tuning(ctypes.c_void_p(ctx), int(rows_per_segment), int(prefetch_rows)),
-           "qla_set_tuning")
+def qla_set_tuning(ctx: int, rows_per_segment: int = 0, prefetch_rows: int = 0,
+                   steps_per_pass: int = 0) -> None:
+    _check(load().qla_set_tuning(ctypes.c_void_p(ctx), int(rows_per_segment), int(prefetch_rows),
+                                 int(steps_per_pass)), "qla_set_tuning")
+
+
+def qla_autotune(ctx: int):
+    """Returns the chosen (rows_per_segment, prefetch_rows, steps_per_pass)."""
+    r, p, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().qla_autotune(ctypes.c_void_p(ctx), ctypes.byref(r), ctypes.byref(p),
+                               ctypes.byref(t)), "qla_autotune")
+    return r.value, p.value, t.value
+
+
+def qla_get_tuning(ctx: int):
+    r, p, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().qla_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(r), ctypes.byref(p),
+                                 ctypes.byref(t)), "qla_get_tuning")
+    return r.value, p.value, t.value
 
 
 def qla_strerror(status: int) -> str:

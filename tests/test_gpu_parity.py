@@ -115,6 +115,7 @@ def test_parity_small_workload(qla, prec, vmode):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("fused", [1, 2])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("nx,ny,steps,rows", [
     (8, 8, 5, 0),          # smallest lattice: one wave covers the row 8 times over
@@ -124,13 +125,13 @@ def test_parity_small_workload(qla, prec, vmode):
     (9, 300, 6, 40),       # tall and narrow
     (112, 240, 4, 120),    # exact multiples of the strip
 ])
-def test_parity_ragged_random(qla, prec, nx, ny, steps, rows):
+def test_parity_ragged_random(qla, prec, nx, ny, steps, rows, fused):
     n = _random_index(ny, nx, seed=nx * 1000 + ny)
     q = _random_fields((ny, nx), seed=ny)
     for vmode in (0, 1):
         want = oracle.advance(_oracle_state(n, q), n, 0.4, steps, vmode)[2:5]
         with qla.Lattice(nx, ny, 0.4, precision=prec, potential=vmode) as lat:
-            qla.qla_set_tuning(lat.ctx, rows)
+            qla.qla_set_tuning(lat.ctx, rows, 0, fused)
             lat.set_index(n)
             lat.set_fields(q)
             lat.advance(steps)
@@ -219,12 +220,15 @@ def test_checkpoint_restore_continues_bitwise(qla):
 
 
 def test_runs_are_deterministic_and_tiling_independent(qla):
+    """Segment height, prefetch depth and steps per pass (1 or 2) change only the order
+    in which sites are visited, never a site's arithmetic: results are bitwise equal."""
     w = workloads.parity_small()
     n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
     outs, energies = [], []
-    for rows, pf in ((0, 0), (8, 2), (64, 3), (1, 4), (100, 2), (0, 0)):
+    for rows, pf, ts in ((0, 0, 0), (8, 2, 1), (64, 3, 2), (1, 3, 1), (100, 2, 2), (1, 2, 2),
+                         (0, 0, 1)):
         with qla.Lattice(w.nx, w.ny, w.delta) as lat:
-            qla.qla_set_tuning(lat.ctx, rows, pf)
+            qla.qla_set_tuning(lat.ctx, rows, pf, ts)
             lat.set_index(n)
             lat.init_packet(w.packet)
             lat.advance(40)
@@ -276,8 +280,10 @@ def test_error_paths(qla):
         with pytest.raises(qla.QlaError):
             lat.set_index(bad)
         with pytest.raises(qla.QlaError) as e:
-            qla.qla_set_tuning(lat.ctx, 24, 7)               # unsupported prefetch depth
+            qla.qla_set_tuning(lat.ctx, 24, 7, 0)            # unsupported prefetch depth
         assert e.value.status == qla.QLA_EINVAL
+        with pytest.raises(qla.QlaError):
+            qla.qla_set_tuning(lat.ctx, 24, 0, 3)            # unsupported steps per pass
         with pytest.raises(qla.QlaError):
             lat.advance(-1)
     with qla.Lattice(16, 16, 3.0) as lat:                    # delta/(4n) = 0.75 rad
@@ -285,3 +291,25 @@ def test_error_paths(qla):
             lat.set_index(np.ones((16, 16)))
         assert e.value.status == qla.QLA_EINVAL
         assert "angle" in qla.qla_last_error()
+
+
+def test_autotune_keeps_state_and_results(qla):
+    w = workloads.parity_small()
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    with qla.Lattice(w.nx, w.ny, w.delta) as ref:
+        ref.set_index(n)
+        ref.init_packet(w.packet)
+        ref.advance(30)
+        want = ref.fields()
+    with qla.Lattice(w.nx, w.ny, w.delta) as lat:
+        lat.set_index(n)
+        lat.init_packet(w.packet)
+        lat.advance(10)
+        before = lat.fields()
+        rows, pf, ts = qla.qla_autotune(lat.ctx)
+        assert (rows, pf, ts) == qla.qla_get_tuning(lat.ctx)
+        assert pf in (2, 3) and ts in (1, 2) and rows >= 1
+        assert lat.steps == 10
+        np.testing.assert_array_equal(lat.fields(), before)
+        lat.advance(20)
+        np.testing.assert_array_equal(lat.fields(), want)
