@@ -249,6 +249,56 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, tuning_json):
     print("\n".join(lines))
 
 
+def precision_study(qla, torch, w, snapshot_every):
+    """Run the workload in FP64 and FP32 side by side; at every snapshot compare the
+    FP32 fields with the FP64 ones (relative L2 over the three planes) and record both
+    energy drifts. Norms are diagnostics computed on the device."""
+    import workloads
+    n_dev = torch.from_numpy(workloads.ellipse_index(w.nx, w.ny, w.ellipse)).to("cuda")
+    sp = torch.cuda.current_stream().cuda_stream
+    ctxs = {}
+    for prec, code in (("f64", qla.QLA_F64), ("f32", qla.QLA_F32)):
+        c = qla.qla_create(w.nx, w.ny, w.delta, code, qla.QLA_V_SKEW_HALF, sp)
+        qla.qla_set_index_device(c, n_dev, w.nx)
+        tun = recorded_tuning(workloads.plain_4096()).get(prec)
+        if tun:
+            qla.qla_set_tuning(c, *tun)
+        else:
+            qla.qla_autotune(c)
+        p = w.packet
+        qla.qla_init_packet(c, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
+        ctxs[prec] = c
+    f64 = torch.empty((3, w.ny, w.nx), dtype=torch.float64, device="cuda")
+    f32 = torch.empty_like(f64)
+    e0 = {k: qla.qla_energy(c) for k, c in ctxs.items()}
+    snaps = []
+    t_run = {"f64": 0.0, "f32": 0.0}
+    for step in range(snapshot_every, w.steps + 1, snapshot_every):
+        for prec, c in ctxs.items():
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            qla.qla_advance(c, snapshot_every)
+            b.record()
+            torch.cuda.synchronize()
+            t_run[prec] += a.elapsed_time(b) / 1e3
+        qla.qla_get_fields_device(ctxs["f64"], f64, 0)
+        qla.qla_get_fields_device(ctxs["f32"], f32, 0)
+        torch.cuda.synchronize()
+        err = float(torch.linalg.vector_norm(f32 - f64) / torch.linalg.vector_norm(f64))
+        ed = {k: qla.qla_energy(c) / e0[k] - 1 for k, c in ctxs.items()}
+        snaps.append({"step": step, "field_rel_l2_f32_vs_f64": err,
+                      "energy_drift_f64": ed["f64"], "energy_drift_f32": ed["f32"]})
+        print(f"[study] step {step}: f32 vs f64 rel L2 {err:.3e}, drift f64 {ed['f64']:.2e} "
+              f"f32 {ed['f32']:.2e}", file=sys.stderr, flush=True)
+    for c in ctxs.values():
+        qla.qla_destroy(c)
+    sites = w.nx * w.ny * w.steps
+    return {"workload": w.name, "nx": w.nx, "ny": w.ny, "qla_steps": w.steps,
+            "snapshot_every": snapshot_every,
+            "glups": {k: sites / v / 1e9 for k, v in t_run.items()},
+            "seconds": t_run, "snapshots": snaps}
+
+
 def cpu_baseline(w, sample_steps):
     import numpy as np
     import oracle
@@ -277,6 +327,10 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR",
                                                                "TRACE_DIR", "TUNING_JSON"))
+    ap.add_argument("--precision-study", action="store_true",
+                    help="FP32 against FP64 on the 8192^2 bubble workload (field L2, energy drift "
+                         "per snapshot); prints its own JSON line")
+    ap.add_argument("--snapshot-every", type=int, default=1000)
     ap.add_argument("--tuning-json", default="",
                     help='fixed tuning instead of autotuning, e.g. {"f64": [176, 3, 2]}')
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -305,6 +359,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.precision_study:
+        w = workloads.bubble_8192()
+        if args.qla_steps:
+            w = dataclasses.replace(w, steps=args.qla_steps)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out = precision_study(qla, torch, w, args.snapshot_every)
+        print(json.dumps(out), flush=True)
+        return
     w = workloads.workload_by_name(args.workload)
     if args.qla_steps:
         w = dataclasses.replace(w, steps=args.qla_steps)
