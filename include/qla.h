@@ -169,6 +169,47 @@ qla_status qla_get_tuning(const qla_ctx *ctx, int *rows_per_segment, int *prefet
 /* Release every resource of the context (NULL is accepted). Synchronises. */
 qla_status qla_destroy(qla_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent lattices (sizes, media and packets of their own)
+ * advanced together. Each pass (2 steps, or 1 if some step count is odd) is one
+ * persistent launch whose wavefronts stride over the tiles of every lattice still
+ * running; the whole run is captured once into a hipGraph.
+ * --------------------------------------------------------------------------- */
+typedef struct qla_batch qla_batch;
+
+/* Create `count` (1..4095) lattices nx[i] x ny[i] with spacing delta[i], all in one
+ * precision and potential mode, on one stream (NULL = library-owned). Each lattice
+ * is an ordinary context (see qla_batch_context). */
+qla_status qla_batch_create(int count, const int *nx, const int *ny, const double *delta,
+                            qla_precision precision, qla_potential potential,
+                            void *hip_stream, qla_batch **out);
+
+/* Borrow lattice i's context to set its index, packet or fields and to read its
+ * fields or energy with the single-lattice calls. It must not be destroyed and
+ * must not be advanced on its own while the batch has a plan. */
+qla_status qla_batch_context(qla_batch *batch, int i, qla_ctx **ctx);
+
+/* Plan a run in which lattice i advances steps[i] steps (every index must be set):
+ * autotune segment height, prefetch depth and steps per pass on the batch itself
+ * (the states are saved and restored), build the tile tables and capture the run
+ * (one persistent launch per pass) into a hipGraph. mode: 0 or 1 (one launch per
+ * pass); 2 (one cooperative launch per run) is rejected with QLA_EINVAL in this
+ * build. Synchronises. */
+qla_status qla_batch_plan(qla_batch *batch, const int64_t *steps, int mode);
+
+/* Replay the planned run (asynchronous). Runs can be repeated; each continues
+ * from the previous one's result. */
+qla_status qla_batch_run(qla_batch *batch);
+
+/* The plan's choices: tuning, mode (1), passes, and the lattice-site updates of
+ * one run. */
+qla_status qla_batch_plan_info(const qla_batch *batch, int *rows_per_segment,
+                               int *prefetch_rows, int *steps_per_pass, int *mode,
+                               int *passes, int64_t *site_updates);
+
+/* Release the batch and every lattice in it (NULL is accepted). Synchronises. */
+qla_status qla_batch_destroy(qla_batch *batch);
+
 const char *qla_strerror(qla_status status);
 const char *qla_last_error(void);
 

@@ -12,39 +12,9 @@
 #include "qla.h"
 #include "qla_internal.h"
 
-namespace {
-constexpr int kDefaultRows = 24;
-constexpr int kDefaultPrefetch = 3;
-constexpr int kDefaultFused = 2;
-}  // namespace
+#include "qla_ctx.h"
 
-struct qla_ctx {
-  int nx = 0, ny = 0;
-  double delta = 0.0;
-  bool fp32 = false;
-  int vmode = 0;
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  void* q[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-  int cur = 0;
-  double* n64 = nullptr;
-  float* n32 = nullptr;
-  double* staging = nullptr;  // 3 * nx * ny doubles
-  double* partials = nullptr;
-  double* energy_dev = nullptr;
-  unsigned long long* stats = nullptr;
-  int64_t steps = 0;
-  bool have_index = false;
-  int angle_class = 0;
-  int rows_per_seg = kDefaultRows;
-  int prefetch = kDefaultPrefetch;
-  int fused = kDefaultFused;
-  size_t count() const { return static_cast<size_t>(nx) * static_cast<size_t>(ny); }
-  size_t elem() const { return fp32 ? sizeof(float) : sizeof(double); }
-};
-
-namespace {
+namespace qla {
 
 thread_local std::string g_last_error;
 
@@ -57,29 +27,24 @@ qla_status hip_fail(hipError_t e, const char* what) {
   return fail(QLA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define QLA_HIP(call)                               \
-  do {                                              \
-    const hipError_t e_ = (call);                   \
-    if (e_ != hipSuccess) return hip_fail(e_, #call); \
-  } while (0)
+DeviceGuard::DeviceGuard(int dev) {
+  ok_ = hipGetDevice(&prev_) == hipSuccess;
+  if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+}
 
-// Makes the context's device current for the duration of a call.
-class DeviceGuard {
- public:
-  explicit DeviceGuard(int dev) {
-    ok_ = hipGetDevice(&prev_) == hipSuccess;
-    if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
-  }
-  ~DeviceGuard() {
-    int now = prev_;
-    if (hipGetDevice(&now) == hipSuccess && now != prev_) (void)hipSetDevice(prev_);
-  }
-  bool ok() const { return ok_; }
+DeviceGuard::~DeviceGuard() {
+  int now = prev_;
+  if (hipGetDevice(&now) == hipSuccess && now != prev_) (void)hipSetDevice(prev_);
+}
 
- private:
-  int prev_ = 0;
-  bool ok_ = false;
-};
+}  // namespace qla
+
+using qla::DeviceGuard;
+using qla::fail;
+using qla::hip_fail;
+using qla::g_last_error;
+
+namespace {
 
 void release(qla_ctx* c) {
   for (auto& buf : c->q)
@@ -145,6 +110,60 @@ qla_status install_index(qla_ctx* c, const double* src, size_t ld) {
 }
 
 }  // namespace
+
+namespace qla {
+
+// Enqueue k steps on the context's stream with the given tuning (no checks).
+qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused) {
+  qla::StepLaunch L{};
+  L.n = c->fp32 ? static_cast<const void*>(c->n32) : static_cast<const void*>(c->n64);
+  L.nx = c->nx;
+  L.ny = c->ny;
+  L.rows_per_seg = rows;
+  L.prefetch = prefetch;
+  L.delta = c->delta;
+  L.fp32 = c->fp32;
+  L.vmode = c->vmode;
+  L.angle_class = c->angle_class;
+  // passes of `fused` steps, then single steps for the remainder
+  int64_t done = 0;
+  while (done < k) {
+    L.fused_steps = (k - done >= fused) ? fused : 1;
+    for (int j = 0; j < 3; ++j) {
+      L.in[j] = c->q[c->cur][j];
+      L.out[j] = c->q[c->cur ^ 1][j];
+    }
+    QLA_HIP(qla::launch_step(L, c->stream));
+    c->cur ^= 1;
+    c->steps += L.fused_steps;
+    done += L.fused_steps;
+  }
+  return QLA_OK;
+}
+
+qla::StepLaunch step_launch_for(const qla_ctx* c, int rows, int prefetch, int fused, int dir) {
+  qla::StepLaunch L{};
+  L.n = c->fp32 ? static_cast<const void*>(c->n32) : static_cast<const void*>(c->n64);
+  L.nx = c->nx;
+  L.ny = c->ny;
+  L.rows_per_seg = rows;
+  L.prefetch = prefetch;
+  L.fused_steps = fused;
+  L.delta = c->delta;
+  L.fp32 = c->fp32;
+  L.vmode = c->vmode;
+  L.angle_class = c->angle_class;
+  const int from = c->cur ^ dir;
+  for (int j = 0; j < 3; ++j) {
+    L.in[j] = c->q[from][j];
+    L.out[j] = c->q[from ^ 1][j];
+  }
+  return L;
+}
+
+}  // namespace qla
+
+using qla::enqueue_steps;
 
 extern "C" {
 
@@ -233,6 +252,7 @@ qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
 
 qla_status qla_destroy(qla_ctx* c) {
   if (!c) return QLA_OK;
+  if (c->owned_by_batch) return fail(QLA_EINVAL, "this context belongs to a batch");
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   release(c);
@@ -288,37 +308,6 @@ qla_status qla_set_fields(qla_ctx* c, const double* q_host, int64_t step) {
   return QLA_OK;
 }
 
-namespace {
-
-// Enqueue k steps on the context's stream with the given tuning (no checks).
-qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused) {
-  qla::StepLaunch L{};
-  L.n = c->fp32 ? static_cast<const void*>(c->n32) : static_cast<const void*>(c->n64);
-  L.nx = c->nx;
-  L.ny = c->ny;
-  L.rows_per_seg = rows;
-  L.prefetch = prefetch;
-  L.delta = c->delta;
-  L.fp32 = c->fp32;
-  L.vmode = c->vmode;
-  L.angle_class = c->angle_class;
-  // passes of `fused` steps, then single steps for the remainder
-  int64_t done = 0;
-  while (done < k) {
-    L.fused_steps = (k - done >= fused) ? fused : 1;
-    for (int j = 0; j < 3; ++j) {
-      L.in[j] = c->q[c->cur][j];
-      L.out[j] = c->q[c->cur ^ 1][j];
-    }
-    QLA_HIP(qla::launch_step(L, c->stream));
-    c->cur ^= 1;
-    c->steps += L.fused_steps;
-    done += L.fused_steps;
-  }
-  return QLA_OK;
-}
-
-}  // namespace
 
 qla_status qla_advance(qla_ctx* c, int64_t k) {
   if (!c) return fail(QLA_EINVAL, "NULL context");
@@ -480,9 +469,9 @@ qla_status qla_set_tuning(qla_ctx* c, int rows_per_segment, int prefetch_rows,
     return fail(QLA_EINVAL, "prefetch_rows must be 0 (default), 2 or 3");
   if (steps_per_pass < 0 || steps_per_pass > 2)
     return fail(QLA_EINVAL, "steps_per_pass must be 0 (default), 1 or 2");
-  c->rows_per_seg = rows_per_segment ? rows_per_segment : kDefaultRows;
-  c->prefetch = prefetch_rows ? prefetch_rows : kDefaultPrefetch;
-  c->fused = steps_per_pass ? steps_per_pass : kDefaultFused;
+  c->rows_per_seg = rows_per_segment ? rows_per_segment : qla::kDefaultRows;
+  c->prefetch = prefetch_rows ? prefetch_rows : qla::kDefaultPrefetch;
+  c->fused = steps_per_pass ? steps_per_pass : qla::kDefaultFused;
   return QLA_OK;
 }
 

@@ -1,0 +1,77 @@
+// The state of one lattice (shared by the single-lattice and batched C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "qla.h"
+#include "qla_internal.h"
+
+namespace qla {
+constexpr int kDefaultRows = 24;
+constexpr int kDefaultPrefetch = 3;
+constexpr int kDefaultFused = 2;
+}  // namespace qla
+
+struct qla_ctx {
+  int nx = 0, ny = 0;
+  double delta = 0.0;
+  bool fp32 = false;
+  int vmode = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool owned_by_batch = false;
+  void* q[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  int cur = 0;
+  double* n64 = nullptr;
+  float* n32 = nullptr;
+  double* staging = nullptr;  // 3 * nx * ny doubles
+  double* partials = nullptr;
+  double* energy_dev = nullptr;
+  unsigned long long* stats = nullptr;
+  int64_t steps = 0;
+  bool have_index = false;
+  int angle_class = 0;
+  int rows_per_seg = qla::kDefaultRows;
+  int prefetch = qla::kDefaultPrefetch;
+  int fused = qla::kDefaultFused;
+  size_t count() const { return static_cast<size_t>(nx) * static_cast<size_t>(ny); }
+  size_t elem() const { return fp32 ? sizeof(float) : sizeof(double); }
+};
+
+namespace qla {
+
+extern thread_local std::string g_last_error;
+qla_status fail(qla_status s, const std::string& msg);
+qla_status hip_fail(hipError_t e, const char* what);
+
+#define QLA_HIP(call)                                         \
+  do {                                                        \
+    const hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::qla::hip_fail(e_, #call);  \
+  } while (0)
+
+// Makes a device current for the duration of a call.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = 0;
+  bool ok_ = false;
+};
+
+// Enqueue k steps of one context with the given tuning (no argument checks).
+qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused);
+
+// The step launch for one pass of context c: dir 0 reads the current buffer, dir 1
+// the other one.
+StepLaunch step_launch_for(const qla_ctx* c, int rows, int prefetch, int fused, int dir);
+
+}  // namespace qla

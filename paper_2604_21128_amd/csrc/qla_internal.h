@@ -27,6 +27,26 @@ struct StepLaunch {
 };
 hipError_t launch_step(const StepLaunch& L, hipStream_t stream);
 
+// Batched passes over many lattices (qla_step.hip, qla_batch_kernel). `args`
+// points to 2 StepArgs per instance (filled by fill_step_args), `items` to the
+// (instance << 20 | tile) list and `counts` to the number of items of each pass.
+struct BatchLaunch {
+  const void* args;
+  const unsigned* items;
+  const int* counts;
+  const int* parity;  // per instance: 1 if its buffers are swapped relative to args
+  int pass;      // the pass this launch runs
+  int blocks;    // grid size (batch_resident_blocks: every wave stays resident)
+  bool fp32;
+  int vmode, angle_class, prefetch, fused;
+};
+hipError_t launch_batch(const BatchLaunch& B, hipStream_t stream);
+hipError_t batch_resident_blocks(const BatchLaunch& B, int* blocks);
+size_t step_args_bytes(bool fp32);
+// The kernel's argument block for one pass of one lattice (in, out, n, sizes and the
+// tuning in L) written to host memory at dst; *tiles = wavefront tiles per pass.
+void fill_step_args(const StepLaunch& L, void* dst, int* tiles);
+
 // Index preparation (qla_aux.hip): copy n (row pitch ld) into the packed FP64
 // plane n64 (and its FP32 rounding n32 when non-null), and accumulate into
 // stats[0] the number of entries that are not finite or not > 0, into stats[1]

@@ -39,6 +39,7 @@
 // is exactly three amplitude planes in and out plus n in.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <utility>
 
 #include "qla_device.h"
@@ -302,18 +303,11 @@ struct Marcher {
   }
 };
 
+// One wavefront's work: the tile (strip, seg) of one pass over the lattice of g.
 template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(StepArgs<T> g) {
+__device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, int lane) {
   constexpr int halo = 4 * TS;
   constexpr int strip_cols = kWave - 2 * halo;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wib = threadIdx.x / kWave;
-  const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
-  const int blocks_per_seg = (g.strips + kWavesPerBlock - 1) / kWavesPerBlock;
-  const int seg = blk / blocks_per_seg;
-  const int strip = (blk % blocks_per_seg) * kWavesPerBlock + wib;
-  if (seg >= g.segs || strip >= g.strips) return;  // whole wave exits together
-
   Marcher<T, VMODE, CLS, kWin, PF, TS> w;
   const int x0 = strip * strip_cols;
   int col = (x0 - halo + lane) % g.nx;
@@ -362,7 +356,45 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
 }
 
 template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
-hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(StepArgs<T> g) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = threadIdx.x / kWave;
+  const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+  const int blocks_per_seg = (g.strips + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int seg = blk / blocks_per_seg;
+  const int strip = (blk % blocks_per_seg) * kWavesPerBlock + wib;
+  if (seg >= g.segs || strip >= g.strips) return;  // whole wave exits together
+  march<T, VMODE, CLS, kWin, PF, TS>(g, strip, seg, lane);
+}
+
+// Batched passes. `args` holds two entries per instance (parity 0: the buffer that
+// was current when the tables were built -> the other buffer; parity 1: back); pass p
+// of instance i uses parity (p + parity[i]) & 1, where parity[i] records whether a
+// previous run left instance i's buffers swapped. `items` lists (instance << 20 | tile)
+// for all instances, ordered by decreasing pass count, so the items of the
+// instances still running at pass p are the first counts[p] entries. The launch
+// runs pass p; each wave strides over its items (the grid is sized to what stays
+// resident, so the waves persist across items).
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_batch_kernel(
+    const StepArgs<T>* __restrict__ args, const unsigned* __restrict__ items,
+    const int* __restrict__ counts, const int* __restrict__ parity, int p) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = blockIdx.x * kWavesPerBlock + static_cast<int>(threadIdx.x / kWave);
+  const int waves = gridDim.x * kWavesPerBlock;
+  const int count = counts[p];
+  for (int it = wave; it < count; it += waves) {
+    const unsigned code = __builtin_amdgcn_readfirstlane(items[it]);
+    const int inst = static_cast<int>(code >> 20);
+    const int tile = static_cast<int>(code & 0xFFFFFu);
+    const int par = __builtin_amdgcn_readfirstlane(parity[inst]);
+    const StepArgs<T> g = args[2 * inst + ((p + par) & 1)];
+    march<T, VMODE, CLS, kWin, PF, TS>(g, tile % g.strips, tile / g.strips, lane);
+  }
+}
+
+template <typename T, int kWin, int TS>
+StepArgs<T> make_args(const StepLaunch& L) {
   constexpr int halo = 4 * TS;
   constexpr int strip_cols = kWave - 2 * halo;
   StepArgs<T> g;
@@ -383,6 +415,12 @@ hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
   g.rows_per_seg = g.iters - 2 * halo;
   g.segs = (L.ny + g.rows_per_seg - 1) / g.rows_per_seg;
   g.d4 = static_cast<T>(L.delta * 0.25);
+  return g;
+}
+
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
+hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
+  const StepArgs<T> g = make_args<T, kWin, TS>(L);
   const int blocks_per_seg = (g.strips + kWavesPerBlock - 1) / kWavesPerBlock;
   const int blocks = blocks_per_seg * g.segs;
   hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF, TS>), dim3(blocks),
@@ -390,30 +428,86 @@ hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <typename T, int kWin, int PF, int TS>
-hipError_t launch_pf(const StepLaunch& L, hipStream_t stream) {
-  const bool large = L.angle_class == kLarge;
-  switch (L.vmode) {
+// Calls f.template operator()<T, VMODE, CLS, kWin, PF, TS>() for the compiled variant
+// that matches the runtime choices. Window depth: the smallest that keeps every
+// live row (PF + 4 TS + 2 rows).
+template <typename T, int VMODE, int CLS, typename F>
+auto with_shape(int prefetch, int fused, F&& f) {
+  if (fused == 2) {
+    return prefetch == 2 ? f.template operator()<T, VMODE, CLS, 12, 2, 2>()
+                         : f.template operator()<T, VMODE, CLS, 13, 3, 2>();
+  }
+  return prefetch == 2 ? f.template operator()<T, VMODE, CLS, 8, 2, 1>()
+                       : f.template operator()<T, VMODE, CLS, 9, 3, 1>();
+}
+
+template <typename T, typename F>
+auto with_variant(int vmode, int angle_class, int prefetch, int fused, F&& f) {
+  const bool large = angle_class == kLarge;
+  switch (vmode) {
     case kVSkewHalf:
-      return large ? launch_typed<T, kVSkewHalf, kLarge, kWin, PF, TS>(L, stream)
-                   : launch_typed<T, kVSkewHalf, kSmall, kWin, PF, TS>(L, stream);
+      return large ? with_shape<T, kVSkewHalf, kLarge>(prefetch, fused, f)
+                   : with_shape<T, kVSkewHalf, kSmall>(prefetch, fused, f);
     case kVPaper:
-      return large ? launch_typed<T, kVPaper, kLarge, kWin, PF, TS>(L, stream)
-                   : launch_typed<T, kVPaper, kSmall, kWin, PF, TS>(L, stream);
+      return large ? with_shape<T, kVPaper, kLarge>(prefetch, fused, f)
+                   : with_shape<T, kVPaper, kSmall>(prefetch, fused, f);
     default:
-      return large ? launch_typed<T, kVNone, kLarge, kWin, PF, TS>(L, stream)
-                   : launch_typed<T, kVNone, kSmall, kWin, PF, TS>(L, stream);
+      return large ? with_shape<T, kVNone, kLarge>(prefetch, fused, f)
+                   : with_shape<T, kVNone, kSmall>(prefetch, fused, f);
   }
 }
 
-// Window depth: the smallest that keeps every live row (PF + 4 TS + 2 rows).
 template <typename T>
 hipError_t launch_prec(const StepLaunch& L, hipStream_t stream) {
-  if (L.fused_steps == 2) {
-    return L.prefetch == 2 ? launch_pf<T, 12, 2, 2>(L, stream)
-                           : launch_pf<T, 13, 3, 2>(L, stream);
-  }
-  return L.prefetch == 2 ? launch_pf<T, 8, 2, 1>(L, stream) : launch_pf<T, 9, 3, 1>(L, stream);
+  return with_variant<T>(L.vmode, L.angle_class, L.prefetch, L.fused_steps,
+                         [&]<typename U, int VM, int CL, int W, int PF, int TS>() {
+                           return launch_typed<U, VM, CL, W, PF, TS>(L, stream);
+                         });
+}
+
+template <typename T>
+hipError_t launch_batch_prec(const BatchLaunch& B, hipStream_t stream) {
+  return with_variant<T>(
+      B.vmode, B.angle_class, B.prefetch, B.fused,
+      [&]<typename U, int VM, int CL, int W, int PF, int TS>() -> hipError_t {
+        auto kern = qla_batch_kernel<U, VM, CL, W, PF, TS>;
+        const StepArgs<U>* args = static_cast<const StepArgs<U>*>(B.args);
+        const unsigned* items = B.items;
+        const int* counts = B.counts;
+        const int* parity = B.parity;
+        hipLaunchKernelGGL(kern, dim3(B.blocks), dim3(kWave * kWavesPerBlock), 0, stream, args,
+                           items, counts, parity, B.pass);
+        return hipGetLastError();
+      });
+}
+
+template <typename T>
+hipError_t batch_blocks_prec(const BatchLaunch& B, int* blocks) {
+  return with_variant<T>(
+      B.vmode, B.angle_class, B.prefetch, B.fused,
+      [&]<typename U, int VM, int CL, int W, int PF, int TS>() -> hipError_t {
+        int per_cu = 0, cus = 0, dev = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, qla_batch_kernel<U, VM, CL, W, PF, TS>, kWave * kWavesPerBlock, 0);
+        if (e != hipSuccess) return e;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        *blocks = per_cu * cus;
+        return hipSuccess;
+      });
+}
+
+template <typename T>
+void fill_args_prec(const StepLaunch& L, void* dst, int* tiles) {
+  with_variant<T>(L.vmode, L.angle_class, L.prefetch, L.fused_steps,
+                  [&]<typename U, int VM, int CL, int W, int PF, int TS>() {
+                    const StepArgs<U> g = make_args<U, W, TS>(L);
+                    std::memcpy(dst, &g, sizeof(g));
+                    *tiles = g.strips * g.segs;
+                    return 0;
+                  });
 }
 
 }  // namespace
@@ -422,6 +516,24 @@ hipError_t launch_step(const StepLaunch& L, hipStream_t stream) {
   return L.fp32 ? launch_prec<float>(L, stream) : launch_prec<double>(L, stream);
 }
 
+hipError_t launch_batch(const BatchLaunch& B, hipStream_t stream) {
+  return B.fp32 ? launch_batch_prec<float>(B, stream) : launch_batch_prec<double>(B, stream);
+}
 
+hipError_t batch_resident_blocks(const BatchLaunch& B, int* blocks) {
+  return B.fp32 ? batch_blocks_prec<float>(B, blocks) : batch_blocks_prec<double>(B, blocks);
+}
+
+size_t step_args_bytes(bool fp32) {
+  return fp32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
+}
+
+void fill_step_args(const StepLaunch& L, void* dst, int* tiles) {
+  if (L.fp32) {
+    fill_args_prec<float>(L, dst, tiles);
+  } else {
+    fill_args_prec<double>(L, dst, tiles);
+  }
+}
 
 }  // namespace qla

@@ -29,7 +29,8 @@ EXPORTED = (
     "qla_set_fields", "qla_advance", "qla_get_fields", "qla_get_fields_device",
     "qla_energy", "qla_energy_device", "qla_get_coefficients", "qla_step_count",
     "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_destroy", "qla_strerror",
-    "qla_last_error",
+    "qla_last_error", "qla_batch_create", "qla_batch_context", "qla_batch_plan", "qla_batch_run",
+    "qla_batch_plan_info", "qla_batch_destroy",
 )
 
 
@@ -78,6 +79,15 @@ def load(path: str = LIB_PATH):
         "qla_get_tuning": (st, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int)]),
         "qla_destroy": (st, [vp]),
+        "qla_batch_create": (st, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int), dp, ctypes.c_int, ctypes.c_int,
+                                  vp, ctypes.POINTER(vp)]),
+        "qla_batch_context": (st, [vp, ctypes.c_int, ctypes.POINTER(vp)]),
+        "qla_batch_plan": (st, [vp, ctypes.POINTER(i64), ctypes.c_int]),
+        "qla_batch_run": (st, [vp]),
+        "qla_batch_plan_info": (st, [vp] + [ctypes.POINTER(ctypes.c_int)] * 5
+                                + [ctypes.POINTER(i64)]),
+        "qla_batch_destroy": (st, [vp]),
         "qla_strerror": (ctypes.c_char_p, [st]),
         "qla_last_error": (ctypes.c_char_p, []),
     }
@@ -212,6 +222,49 @@ def qla_get_tuning(ctx: int):
     _check(load().qla_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(r), ctypes.byref(p),
                                  ctypes.byref(t)), "qla_get_tuning")
     return r.value, p.value, t.value
+
+
+def qla_batch_create(nx, ny, delta, precision: int = QLA_F32,
+                     potential: int = QLA_V_SKEW_HALF, hip_stream: Optional[int] = None) -> int:
+    count = len(nx)
+    ia = (ctypes.c_int * count)(*[int(v) for v in nx])
+    ib = (ctypes.c_int * count)(*[int(v) for v in ny])
+    da = (ctypes.c_double * count)(*[float(v) for v in delta])
+    out = ctypes.c_void_p()
+    _check(load().qla_batch_create(count, ia, ib, da, int(precision), int(potential),
+                                   ctypes.c_void_p(hip_stream) if hip_stream else None,
+                                   ctypes.byref(out)), "qla_batch_create")
+    return int(out.value)
+
+
+def qla_batch_context(batch: int, i: int) -> int:
+    out = ctypes.c_void_p()
+    _check(load().qla_batch_context(ctypes.c_void_p(batch), int(i), ctypes.byref(out)),
+           "qla_batch_context")
+    return int(out.value)
+
+
+def qla_batch_plan(batch: int, steps, mode: int = 0) -> None:
+    arr = (ctypes.c_int64 * len(steps))(*[int(v) for v in steps])
+    _check(load().qla_batch_plan(ctypes.c_void_p(batch), arr, int(mode)), "qla_batch_plan")
+
+
+def qla_batch_run(batch: int) -> None:
+    _check(load().qla_batch_run(ctypes.c_void_p(batch)), "qla_batch_run")
+
+
+def qla_batch_plan_info(batch: int) -> dict:
+    v = [ctypes.c_int() for _ in range(5)]
+    u = ctypes.c_int64()
+    _check(load().qla_batch_plan_info(ctypes.c_void_p(batch), *[ctypes.byref(x) for x in v],
+                                      ctypes.byref(u)), "qla_batch_plan_info")
+    return {"rows_per_segment": v[0].value, "prefetch_rows": v[1].value,
+            "steps_per_pass": v[2].value, "mode": v[3].value, "passes": v[4].value,
+            "site_updates": u.value}
+
+
+def qla_batch_destroy(batch: int) -> None:
+    _check(load().qla_batch_destroy(ctypes.c_void_p(batch)), "qla_batch_destroy")
 
 
 def qla_strerror(status: int) -> str:

@@ -1,0 +1,136 @@
+"""Batched QLA (qla_batch_*): many uneven lattices advanced by one captured run.
+
+Every lattice's result must equal, bit for bit, the single-lattice path on the same
+inputs (the batched kernel applies the same per-site arithmetic), and one lattice
+is also checked against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qla():
+    from paper_2604_21128_amd import qla as q
+    q.load()
+    return q
+
+
+SIZES = [(64, 64), (57, 90), (130, 40), (200, 200), (96, 128), (8, 8)]
+STEPS = [12, 20, 8, 16, 10, 6]
+
+
+def _instance(i, nx, ny):
+    rng = np.random.default_rng(100 + i)
+    e = workloads.Ellipse(nx / 2, ny / 2, rng.uniform(0.1, 0.3) * nx, rng.uniform(0.1, 0.3) * ny,
+                          rng.uniform(0, np.pi), rng.uniform(1.5, 3.0), 1.0, 3.0)
+    n = workloads.ellipse_index(nx, ny, e)
+    p = workloads.Packet(x0=rng.uniform(0, nx), y0=ny / 2, sigma=rng.uniform(3, 6),
+                         lam=rng.uniform(8, 16))
+    return n, p
+
+
+def _single(qla, n, p, steps, prec):
+    ny, nx = n.shape
+    with qla.Lattice(nx, ny, 0.25, precision=prec) as lat:
+        lat.set_index(n)
+        lat.init_packet(p)
+        lat.advance(steps)
+        return lat.fields()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("mode", [1, pytest.param(2, marks=pytest.mark.skip(
+    reason="one cooperative launch per run (grid barrier between passes) hung in FP32 on "
+           "the GPU; the cause is not shown, so the mode is switched off"))])
+def test_batch_matches_single_lattice_bitwise(qla, prec, mode):
+    b = qla.qla_batch_create([s[0] for s in SIZES], [s[1] for s in SIZES], [0.25] * len(SIZES),
+                             precision=prec)
+    try:
+        inputs = []
+        for i, (nx, ny) in enumerate(SIZES):
+            n, p = _instance(i, nx, ny)
+            inputs.append((n, p))
+            ctx = qla.qla_batch_context(b, i)
+            qla.qla_set_index(ctx, n)
+            qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam)
+        qla.qla_batch_plan(b, STEPS, mode)
+        info = qla.qla_batch_plan_info(b)
+        assert info["mode"] == mode and info["steps_per_pass"] in (1, 2)
+        assert info["passes"] == max(STEPS) // info["steps_per_pass"]
+        assert info["site_updates"] == sum(nx * ny * s for (nx, ny), s in zip(SIZES, STEPS))
+        qla.qla_batch_run(b)
+        for i, (nx, ny) in enumerate(SIZES):
+            ctx = qla.qla_batch_context(b, i)
+            assert qla.qla_step_count(ctx) == STEPS[i]
+            got = qla.qla_get_fields(ctx, nx, ny)
+            want = _single(qla, *inputs[i], STEPS[i], prec)
+            np.testing.assert_array_equal(got, want, err_msg=f"instance {i} {nx}x{ny}")
+        # a second run of the same graph continues from there (odd pass counts included)
+        qla.qla_batch_run(b)
+        ctx = qla.qla_batch_context(b, 3)
+        np.testing.assert_array_equal(qla.qla_get_fields(ctx, 200, 200),
+                                      _single(qla, *inputs[3], 2 * STEPS[3], prec))
+    finally:
+        qla.qla_batch_destroy(b)
+
+
+def test_batch_against_oracle_and_energy(qla):
+    nx, ny, steps = 96, 72, 24
+    n, p = _instance(7, nx, ny)
+    b = qla.qla_batch_create([nx, 40], [ny, 40], [0.25, 0.25], precision=0)
+    try:
+        ctx = qla.qla_batch_context(b, 0)
+        qla.qla_set_index(ctx, n)
+        qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam)
+        ctx1 = qla.qla_batch_context(b, 1)
+        qla.qla_set_index(ctx1, np.full((40, 40), 1.3))
+        qla.qla_init_packet(ctx1, 10.0, 20.0, 4.0, 9.0)
+        qla.qla_batch_plan(b, [steps, 10], 0)
+        qla.qla_batch_run(b)
+        got = qla.qla_get_fields(ctx, nx, ny)
+        e = qla.qla_energy(ctx)
+    finally:
+        qla.qla_batch_destroy(b)
+    want = oracle.advance(oracle.packet_from(n, p), n, 0.25, steps)
+    assert np.linalg.norm(got - want[2:5]) / np.linalg.norm(want[2:5]) <= 1e-12
+    assert abs(e / oracle.energy(want) - 1) < 1e-12
+
+
+def test_batch_odd_steps_and_errors(qla):
+    b = qla.qla_batch_create([32, 48], [40, 24], [0.25, 0.25], precision=1)
+    try:
+        ctx0 = qla.qla_batch_context(b, 0)
+        with pytest.raises(qla.QlaError) as e:
+            qla.qla_batch_plan(b, [4, 4], 2)               # cooperative mode is off
+        assert e.value.status == qla.QLA_EINVAL
+        with pytest.raises(qla.QlaError) as e:
+            qla.qla_batch_plan(b, [4, 4], 0)               # no index yet
+        assert e.value.status == qla.QLA_ESTATE
+        with pytest.raises(qla.QlaError):
+            qla.qla_destroy(ctx0)                           # owned by the batch
+        with pytest.raises(qla.QlaError):
+            qla.qla_batch_context(b, 2)
+        ns = []
+        for i, (nx, ny) in enumerate(((32, 40), (48, 24))):
+            n, p = _instance(20 + i, nx, ny)
+            ns.append((n, p))
+            ctx = qla.qla_batch_context(b, i)
+            qla.qla_set_index(ctx, n)
+            qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam)
+        qla.qla_batch_plan(b, [7, 4], 0)                    # odd: one step per pass
+        assert qla.qla_batch_plan_info(b)["steps_per_pass"] == 1
+        qla.qla_batch_run(b)
+        for i, (nx, ny) in enumerate(((32, 40), (48, 24))):
+            got = qla.qla_get_fields(qla.qla_batch_context(b, i), nx, ny)
+            np.testing.assert_array_equal(got, _single(qla, *ns[i], (7, 4)[i], 1))
+        qla.qla_batch_run(b)                                # 7 passes: parity flips
+        for i, (nx, ny) in enumerate(((32, 40), (48, 24))):
+            got = qla.qla_get_fields(qla.qla_batch_context(b, i), nx, ny)
+            np.testing.assert_array_equal(got, _single(qla, *ns[i], 2 * (7, 4)[i], 1))
+    finally:
+        qla.qla_batch_destroy(b)
