@@ -299,6 +299,85 @@ def precision_study(qla, torch, w, snapshot_every):
             "seconds": t_run, "snapshots": snaps}
 
 
+def batched_study(qla, torch, count, seed, error_samples):
+    """The batched workload: `count` instances drawn by workloads.sample_instances, each run
+    4 N steps in FP32. Times one captured batched run and the same instances run one after
+    another with the single-lattice kernel, and measures the batched FP32 field error
+    against FP64 single-lattice runs of sampled instances."""
+    import numpy as np
+    import workloads
+    inst = workloads.sample_instances(count, seed=seed)
+    sp = torch.cuda.current_stream().cuda_stream
+    t0 = time.perf_counter()
+    b = qla.qla_batch_create([i.n_side for i in inst], [i.n_side for i in inst],
+                             [i.delta for i in inst], qla.QLA_F32, qla.QLA_V_SKEW_HALF, sp)
+    ctxs = [qla.qla_batch_context(b, k) for k in range(count)]
+    ns = []
+    for k, i in enumerate(inst):
+        n = workloads.ellipse_index(i.n_side, i.n_side, i.ellipse)
+        ns.append(n)
+        qla.qla_set_index(ctxs[k], n)
+
+    def init_all():
+        for k, i in enumerate(inst):
+            p = i.packet
+            qla.qla_init_packet(ctxs[k], p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
+
+    init_all()
+    steps = [i.steps for i in inst]
+    qla.qla_batch_plan(b, steps, 0)
+    info = qla.qla_batch_plan_info(b)
+    print(f"[batch] {count} instances set up and planned in {time.perf_counter() - t0:.1f} s: "
+          f"{info}", file=sys.stderr, flush=True)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    times = []
+    for rep in range(2):
+        init_all()
+        torch.cuda.synchronize()
+        a, z = ev(), ev()
+        a.record()
+        qla.qla_batch_run(b)
+        z.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(z) / 1e3)
+        print(f"[batch] batched run {rep}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
+    t_batch = min(times)
+    # field error of the batched FP32 result against FP64 single-lattice runs
+    rng = np.random.default_rng(seed + 1)
+    picks = sorted(rng.choice(count, size=min(error_samples, count), replace=False).tolist())
+    errs = []
+    for k in picks:
+        i = inst[k]
+        got = qla.qla_get_fields(ctxs[k], i.n_side, i.n_side)
+        with qla.Lattice(i.n_side, i.n_side, i.delta, qla.QLA_F64, qla.QLA_V_SKEW_HALF, sp) as lat:
+            lat.set_index(ns[k])
+            lat.init_packet(i.packet)
+            lat.advance(i.steps)
+            want = lat.fields()
+        errs.append(float(np.linalg.norm(got - want) / np.linalg.norm(want)))
+    # the same instances one after another with the single-lattice kernel (plain QLA)
+    init_all()
+    torch.cuda.synchronize()
+    a, z = ev(), ev()
+    a.record()
+    for k, i in enumerate(inst):
+        qla.qla_advance(ctxs[k], i.steps)
+    z.record()
+    torch.cuda.synchronize()
+    t_plain = a.elapsed_time(z) / 1e3
+    qla.qla_batch_destroy(b)
+    updates = info["site_updates"]
+    return {"workload": f"qla_batched_{count}_instances_256_1024", "instances": count,
+            "seed": seed, "site_updates": updates,
+            "batched": {"seconds": t_batch, "instances_per_s": count / t_batch,
+                        "glups": updates / t_batch / 1e9, "plan": info},
+            "plain_sequential": {"seconds": t_plain, "instances_per_s": count / t_plain,
+                                 "glups": updates / t_plain / 1e9},
+            "speedup": t_plain / t_batch,
+            "field_rel_l2_fp32_batched_vs_fp64": {"instances": picks, "max": max(errs),
+                                                  "median": float(np.median(errs))}}
+
+
 def cpu_baseline(w, sample_steps):
     import numpy as np
     import oracle
@@ -331,6 +410,10 @@ def main():
                     help="FP32 against FP64 on the 8192^2 bubble workload (field L2, energy drift "
                          "per snapshot); prints its own JSON line")
     ap.add_argument("--snapshot-every", type=int, default=1000)
+    ap.add_argument("--batched", action="store_true",
+                    help="the batched workload (512 instances, FP32); prints its own JSON line")
+    ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--error-samples", type=int, default=6)
     ap.add_argument("--tuning-json", default="",
                     help='fixed tuning instead of autotuning, e.g. {"f64": [176, 3, 2]}')
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -359,6 +442,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.batched:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out = batched_study(qla, torch, args.instances, 0, args.error_samples)
+        print(json.dumps(out), flush=True)
+        return
     if args.precision_study:
         w = workloads.bubble_8192()
         if args.qla_steps:
