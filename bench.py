@@ -378,6 +378,100 @@ def batched_study(qla, torch, count, seed, error_samples):
                                                   "median": float(np.median(errs))}}
 
 
+def surrogate_study(qla, torch, args):
+    """The learned-surrogate workload: QLA-generated pairs on a fixed grid (instances drawn
+    as in the batched workload), training of the neural operator on the GPU, then the
+    held-out set through surrogate + energy check + QLA fallback, against plain QLA."""
+    import numpy as np
+    import workloads
+    from paper_2604_21128_amd import surrogate as S
+    side, steps, B = args.side, args.surrogate_steps, args.batch
+    log = lambda m: print(f"[surrogate] {m}", file=sys.stderr, flush=True)
+    train_i = workloads.sample_instances(args.train_count, seed=10, fixed_side=side)
+    test_i = workloads.sample_instances(args.test_count, seed=11, fixed_side=side)
+
+    def index_fn(insts):
+        return lambda c0, k: workloads.ellipse_index_batch(
+            side, side, [i.ellipse for i in insts[c0:c0 + k]], device="cuda")
+
+    def packets(insts):
+        return [S.PacketSpec(i.packet.x0, i.packet.y0, i.packet.sigma, i.packet.lam,
+                             i.packet.phi, i.packet.amp, i.packet.planar) for i in insts]
+    delta = workloads.DELTA
+    t0 = time.perf_counter()
+    train = S.qla_pairs(index_fn(train_i), len(train_i), packets(train_i), delta, steps,
+                        chunk=args.chunk, log=log)
+    test = S.qla_pairs(index_fn(test_i), len(test_i), packets(test_i), delta, steps,
+                       chunk=args.chunk, keep_f32=True, log=log)
+    gen_s = time.perf_counter() - t0
+    log(f"pairs ready in {gen_s:.1f} s")
+    sur = S.Surrogate(side, side, max_batch=B, seed=args.seed)
+
+    def field_errors(out):
+        d = (out - test.targets_f32).flatten(1).norm(dim=1)
+        return (d / test.targets_f32.flatten(1).norm(dim=1)).cpu().numpy()
+
+    # the untrained network, for comparison
+    out0, e_0 = S.predict_all(sur, test.inputs, B)
+    err_untrained = field_errors(out0)
+    del out0
+    hist = S.train(sur, train.inputs, train.targets, B, args.epochs, args.lr,
+                   time_budget_s=args.train_budget_s, log=log)
+    pred, energy = S.predict_all(sur, test.inputs, B)
+    err_pred = field_errors(pred)
+    ok = S.accept(energy, test.e0, args.accept_tol).cpu().numpy()
+    e_rel = (energy / test.e0 - 1).abs().cpu().numpy()
+    del pred
+    out, ok2, t = S.run_with_fallback(sur, test.inputs, test.e0, index_fn(test_i),
+                                      packets(test_i), delta, steps, B, args.accept_tol,
+                                      args.chunk)
+    err_final = field_errors(out)
+    n_test = len(test_i)
+    t_plain = test.qla_seconds
+    t_sur = t["surrogate_s"] + t["fallback_qla_s"]
+    losses = hist["losses"]
+    tail = losses[-max(1, len(losses) // 20):]
+    q = lambda a: {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)),
+                   "max": float(np.max(a))}
+    res = {
+        "workload": f"qla_surrogate_fno_{side}_{steps}_steps",
+        "grid": side, "qla_steps": steps, "train_instances": len(train_i),
+        "test_instances": n_test,
+        "network": dict(sur.shape, input="n - 2, q2, q3, q4", output="q2, q3, q4",
+                        params=int(qla.qla_fno_param_count(sur.h)), dtype="bf16 storage, "
+                        "fp32 accumulation"),
+        "training": {"steps": hist["steps"], "batch": B, "epochs": hist["steps"] * B
+                     / len(train_i), "lr": args.lr, "seconds": hist["seconds"],
+                     "samples_per_s": hist["steps"] * B / hist["seconds"],
+                     "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(tail))},
+        "qla_pair_generation": {"seconds_total": gen_s, "qla_seconds": train.qla_seconds
+                                + test.qla_seconds,
+                                "glups": (train.site_updates + test.site_updates)
+                                / (train.qla_seconds + test.qla_seconds) / 1e9},
+        "held_out": {
+            "field_rel_l2_untrained": q(err_untrained),
+            "field_rel_l2_prediction": q(err_pred),
+            "energy_rel_error": q(e_rel),
+            "accept_tol": args.accept_tol,
+            "accepted": int(ok.sum()),
+            "field_rel_l2_accepted": q(err_pred[ok]) if ok.any() else None,
+            "field_rel_l2_after_fallback": q(err_final),
+        },
+        "throughput": {
+            "plain_qla_instances_per_s": n_test / t_plain,
+            "surrogate_with_fallback_instances_per_s": n_test / t_sur,
+            "surrogate_forward_and_check_s": t["surrogate_s"],
+            "fallback_qla_s": t["fallback_qla_s"], "rejected": t["rejected"],
+            "plain_qla_s": t_plain, "gain": t_plain / t_sur,
+            "surrogate_only_instances_per_s": n_test / t["surrogate_s"],
+        },
+    }
+    if args.save_params:
+        np.save(args.save_params, sur.params())
+    sur.close()
+    return res
+
+
 def cpu_baseline(w, sample_steps):
     import numpy as np
     import oracle
@@ -414,6 +508,20 @@ def main():
                     help="the batched workload (512 instances, FP32); prints its own JSON line")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--error-samples", type=int, default=6)
+    ap.add_argument("--surrogate", action="store_true",
+                    help="the learned-surrogate workload; prints its own JSON line")
+    ap.add_argument("--side", type=int, default=512)
+    ap.add_argument("--surrogate-steps", type=int, default=1024)
+    ap.add_argument("--train-count", type=int, default=20000)
+    ap.add_argument("--test-count", type=int, default=1000)
+    ap.add_argument("--chunk", type=int, default=512)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--epochs", type=float, default=1.0)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--train-budget-s", type=float, default=None)
+    ap.add_argument("--accept-tol", type=float, default=1e-2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--save-params", default="")
     ap.add_argument("--tuning-json", default="",
                     help='fixed tuning instead of autotuning, e.g. {"f64": [176, 3, 2]}')
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -446,6 +554,12 @@ def main():
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             out = batched_study(qla, torch, args.instances, 0, args.error_samples)
+        print(json.dumps(out), flush=True)
+        return
+    if args.surrogate:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out = surrogate_study(qla, torch, args)
         print(json.dumps(out), flush=True)
         return
     if args.precision_study:

@@ -210,6 +210,101 @@ qla_status qla_batch_plan_info(const qla_batch *batch, int *rows_per_segment,
 /* Release the batch and every lattice in it (NULL is accepted). Synchronises. */
 qla_status qla_batch_destroy(qla_batch *batch);
 
+/* ---------------------------------------------------------------------------
+ * Learned surrogate: a Fourier neural operator (FNO) that maps the medium and the
+ * initial fields of a lattice to its fields a fixed number of steps later. QLA stays
+ * the reference and the fallback: a caller accepts a prediction only if its energy
+ * (Eq. A13, qla_fno_output_energy) is within a tolerance of the initial energy that
+ * QLA conserves, and advances the lattice with QLA otherwise.
+ *
+ * Network (all sizes fixed at creation):
+ *   v0 = P u + p                                    (lift, Cin -> C channels)
+ *   v_{l+1} = act(IDFT_m[R_l . DFT_m(v_l)] + W_l v_l + b_l),   l = 0 .. L-1
+ *   out = Q2 GELU(Q1 v_L + q1) + q2                 (projection C -> C2 -> Cout)
+ * act is the exact GELU, x Phi(x), except after the last Fourier layer (identity).
+ * DFT_m keeps the modes ky in [0, m) U [H - m, H), kx in [0, m) of the real 2D
+ * transform over the periodic H x W grid; R_l holds a complex C x C matrix per kept
+ * mode. Activations are stored in BF16 and every contraction runs on the matrix
+ * cores in BF16 with FP32 accumulation; parameters, gradients and Adam moments are
+ * FP32.
+ *
+ * Tensors are [batch][channel][y][x] with x fastest (H rows of W). The network input
+ * is BF16 [B][Cin][H][W]; the output FP32 [B][Cout][H][W]; targets BF16
+ * [B][Cout][H][W]. BF16 values are raw 16-bit patterns (the upper half of an
+ * IEEE-754 binary32, rounded to nearest even). All tensor pointers are device
+ * pointers owned by the caller; work is enqueued on the surrogate's stream.
+ *
+ * Parameter vector (FP32, qla_fno_param_count entries), in this order:
+ *   P [C][Cin], p [C];
+ *   for each layer: W [C][C] (out, in), b [C], R [ky index][kx][c_in][c_out][re, im]
+ *     with ky index 0 .. 2m-1 for ky = 0 .. m-1, H-m .. H-1;
+ *   Q1 [C2][C], q1 [C2], Q2 [Cout][C2], q2 [Cout].
+ * --------------------------------------------------------------------------- */
+typedef struct qla_fno qla_fno;
+
+/* Create a surrogate for an H x W grid (2m <= H, 2m <= W) with the given channel
+ * counts, m kept modes per axis, L Fourier layers and batches up to max_batch
+ * (max_batch * max(C, C2) * H * W < 2^31). Allocates the parameters, optimiser state
+ * and the activations of a max_batch batch. Weights are initialised from `seed`:
+ * linear maps uniform in +-1/sqrt(fan_in), spectral weights uniform in [0, 1/C^2).
+ * hip_stream: the stream to use, or NULL for a library-owned one. Synchronises. */
+qla_status qla_fno_create(int height, int width, int in_channels, int out_channels,
+                          int channels, int modes, int layers, int proj_channels,
+                          int max_batch, uint64_t seed, void *hip_stream, qla_fno **out);
+
+/* Release the surrogate (NULL is accepted). Synchronises. */
+qla_status qla_fno_destroy(qla_fno *fno);
+
+/* Number of FP32 parameters. */
+qla_status qla_fno_param_count(const qla_fno *fno, int64_t *count);
+
+/* Copy the parameters to / from a host array of qla_fno_param_count floats
+ * (layout above). Setting refreshes the BF16 weight copies. Synchronise. */
+qla_status qla_fno_get_params(qla_fno *fno, float *params_host);
+qla_status qla_fno_set_params(qla_fno *fno, const float *params_host);
+
+/* Gradient of the last qla_fno_loss_grad / qla_fno_train_step call, to a host array
+ * of qla_fno_param_count floats. Synchronises. */
+qla_status qla_fno_get_grads(qla_fno *fno, float *grads_host);
+
+/* Forward pass of `batch` (1..max_batch) inputs; writes the FP32 output (device,
+ * batch * Cout * H * W floats). The output also stays inside the surrogate for
+ * qla_fno_output_energy. Asynchronous. */
+qla_status qla_fno_forward(qla_fno *fno, const uint16_t *input_device, int batch,
+                           float *output_device);
+
+/* Forward and backward pass of the loss mean_b ||out_b - target_b|| / ||target_b||
+ * (relative L2 per sample, averaged over the batch); the gradient replaces the
+ * stored one. If loss_host is not NULL the loss is copied there (synchronises),
+ * else the call is asynchronous. */
+qla_status qla_fno_loss_grad(qla_fno *fno, const uint16_t *input_device,
+                             const uint16_t *target_device, int batch, float *loss_host);
+
+/* One Adam update of the parameters from the stored gradient (bias-corrected,
+ * step counter kept by the surrogate). lr >= 0, 0 <= beta1, beta2 < 1, eps > 0.
+ * Asynchronous. */
+qla_status qla_fno_adam_step(qla_fno *fno, float lr, float beta1, float beta2, float eps);
+
+/* qla_fno_loss_grad then qla_fno_adam_step(lr, 0.9, 0.999, 1e-8); the loss is
+ * written to one device float if loss_device is not NULL. Asynchronous. */
+qla_status qla_fno_train_step(qla_fno *fno, const uint16_t *input_device,
+                              const uint16_t *target_device, int batch, float lr,
+                              float *loss_device);
+
+/* Energy sum over the Cout output planes of out^2, per sample of the last forward
+ * pass of `batch` samples, to `batch` device doubles (Eq. A13 when the outputs are
+ * (q2, q3, q4)). Asynchronous. */
+qla_status qla_fno_output_energy(qla_fno *fno, int batch, double *energy_device);
+
+/* Build one sample from a lattice's state: q_device = 3 FP64 planes (q2, q3, q4)
+ * (as qla_get_fields_device writes them), n_device = the nx * ny index (FP64).
+ * input_device (may be NULL) receives 4 BF16 planes (n - n_shift, q2, q3, q4);
+ * target_device (may be NULL) receives 3 BF16 planes (q2, q3, q4). Asynchronous on
+ * hip_stream (NULL = the null stream). */
+qla_status qla_fno_pack(const double *q_device, const double *n_device, int nx, int ny,
+                        double n_shift, uint16_t *input_device, uint16_t *target_device,
+                        void *hip_stream);
+
 const char *qla_strerror(qla_status status);
 const char *qla_last_error(void);
 

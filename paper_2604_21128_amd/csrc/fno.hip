@@ -1,0 +1,1030 @@
+// Neural-operator surrogate of the QLA run: a Fourier neural operator (lift, L
+// Fourier layers, two-layer projection) in BF16 storage with FP32 accumulation,
+// trained and run entirely with this library's kernels (C ABI: qla_fno_* in qla.h).
+//
+// A Fourier layer maps v (C channels on an H x W periodic grid) to
+//   act( IDFT[ R . DFT(v) ] + W v + b ),   act = GELU except after the last layer,
+// where DFT keeps the modes ky in [0, m) U [H - m, H), kx in [0, m) of the 2D real
+// transform and R mixes channels per mode with complex C x C weights. The truncated
+// transforms are products with cosine/sine bases, done as BF16 GEMMs on the matrix
+// cores (fno_gemm.hip):
+//   x:   Z[(b,c,y)][2kx+p]   = sum_x v[(b,c,y)][x] Fx[x][2kx+p]       (p = re, im)
+//   y:   T[(b,c)][2kyi+p][kx] = A1 . Zre + A2 . Zim                    (complex e^{-i..})
+//   mix: S[(b,o)] = sum_c R[kyi][kx][c][o] T[(b,c)]                     (complex)
+//   y^-1: U[(b,o)][y][2kx+p] = IY_p . S
+//   x^-1: out[(b,o,y)][x]    = sum U Ix,  with weights 1 (kx = 0), 2 (kx > 0) and 1/(HW)
+// which is the real inverse transform of the retained half spectrum. The backward pass
+// uses the transposed products; gradients of the mode mixing and the pointwise parts
+// are accumulated in FP32, and Adam updates FP32 master weights whose BF16 copies feed
+// the GEMMs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fno_internal.h"
+#include "qla.h"
+#include "qla_ctx.h"
+
+using qla::DeviceGuard;
+using qla::fail;
+using qla::hip_fail;
+using qla::fno::bf16_to_f32;
+using qla::fno::f32_to_bf16;
+using qla::fno::GemmDesc;
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ float gelu_prime(float x) {
+  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+  const float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
+  return cdf + x * pdf;
+}
+
+unsigned grid_for(size_t n) {
+  const size_t b = (n + kBlock - 1) / kBlock;
+  return static_cast<unsigned>(b < 16384 ? (b ? b : 1) : 16384);
+}
+
+__global__ void cast_kernel(const float* __restrict__ s, uint16_t* __restrict__ d, size_t n) {
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock)
+    d[i] = f32_to_bf16(s[i]);
+}
+
+// S[(b,o)][2kyi+p][kx] = sum_c R[kyi][kx][c][o] (complex) * T[(b,c)][2kyi+p][kx]
+__global__ void mix_forward_kernel(const float* __restrict__ T, const float* __restrict__ R,
+                                   uint16_t* __restrict__ S, int B, int C, int m) {
+  const int modes = 2 * m * m;
+  const size_t total = size_t(B) * C * modes;
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < total;
+       i += size_t(gridDim.x) * kBlock) {
+    const int o = static_cast<int>(i % C);
+    const int mode = static_cast<int>((i / C) % modes);
+    const int b = static_cast<int>(i / (size_t(C) * modes));
+    const int kyi = mode / m, kx = mode % m;
+    float sr = 0.f, si = 0.f;
+    for (int c = 0; c < C; ++c) {
+      const size_t tb = (size_t(b) * C + c) * (4 * m * m);
+      const float tr = T[tb + (2 * kyi) * m + kx], ti = T[tb + (2 * kyi + 1) * m + kx];
+      const size_t ri = ((size_t(mode) * C + c) * C + o) * 2;
+      const float rr = R[ri], rim = R[ri + 1];
+      sr += rr * tr - rim * ti;
+      si += rr * ti + rim * tr;
+    }
+    const size_t sb = (size_t(b) * C + o) * (4 * m * m);
+    S[sb + (2 * kyi) * m + kx] = f32_to_bf16(sr);
+    S[sb + (2 * kyi + 1) * m + kx] = f32_to_bf16(si);
+  }
+}
+
+// dT[(b,c)] = sum_o conj-transposed R applied to dS (real-pair calculus of the above)
+__global__ void mix_backward_input_kernel(const float* __restrict__ dS, const float* __restrict__ R,
+                                          uint16_t* __restrict__ dT, int B, int C, int m) {
+  const int modes = 2 * m * m;
+  const size_t total = size_t(B) * C * modes;
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < total;
+       i += size_t(gridDim.x) * kBlock) {
+    const int c = static_cast<int>(i % C);
+    const int mode = static_cast<int>((i / C) % modes);
+    const int b = static_cast<int>(i / (size_t(C) * modes));
+    const int kyi = mode / m, kx = mode % m;
+    float gr = 0.f, gi = 0.f;
+    for (int o = 0; o < C; ++o) {
+      const size_t sb = (size_t(b) * C + o) * (4 * m * m);
+      const float dr = dS[sb + (2 * kyi) * m + kx], di = dS[sb + (2 * kyi + 1) * m + kx];
+      const size_t ri = ((size_t(mode) * C + c) * C + o) * 2;
+      const float rr = R[ri], rim = R[ri + 1];
+      gr += dr * rr + di * rim;
+      gi += -dr * rim + di * rr;
+    }
+    const size_t tb = (size_t(b) * C + c) * (4 * m * m);
+    dT[tb + (2 * kyi) * m + kx] = f32_to_bf16(gr);
+    dT[tb + (2 * kyi + 1) * m + kx] = f32_to_bf16(gi);
+  }
+}
+
+// dR[mode][c][o] += sum_b (dS_r T_r + dS_i T_i, -dS_r T_i + dS_i T_r)
+__global__ void mix_backward_weight_kernel(const float* __restrict__ dS,
+                                           const float* __restrict__ T, float* __restrict__ dR,
+                                           int B, int C, int m) {
+  const int modes = 2 * m * m;
+  const size_t total = size_t(modes) * C * C;
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < total;
+       i += size_t(gridDim.x) * kBlock) {
+    const int o = static_cast<int>(i % C);
+    const int c = static_cast<int>((i / C) % C);
+    const int mode = static_cast<int>(i / (size_t(C) * C));
+    const int kyi = mode / m, kx = mode % m;
+    float ar = 0.f, ai = 0.f;
+    for (int b = 0; b < B; ++b) {
+      const size_t tb = (size_t(b) * C + c) * (4 * m * m);
+      const size_t sb = (size_t(b) * C + o) * (4 * m * m);
+      const float tr = T[tb + (2 * kyi) * m + kx], ti = T[tb + (2 * kyi + 1) * m + kx];
+      const float dr = dS[sb + (2 * kyi) * m + kx], di = dS[sb + (2 * kyi + 1) * m + kx];
+      ar += dr * tr + di * ti;
+      ai += -dr * ti + di * tr;
+    }
+    dR[2 * i] += ar;
+    dR[2 * i + 1] += ai;
+  }
+}
+
+// dz = dv * GELU'(z)
+template <typename D>
+__global__ void gelu_grad_kernel(const D* __restrict__ dv, const uint16_t* __restrict__ z,
+                                 uint16_t* __restrict__ dz, size_t n) {
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock) {
+    float d;
+    if constexpr (sizeof(D) == 4) {
+      d = dv[i];
+    } else {
+      d = bf16_to_f32(dv[i]);
+    }
+    dz[i] = f32_to_bf16(d * gelu_prime(bf16_to_f32(z[i])));
+  }
+}
+
+// db[c] += sum over b, p of d[b][c][p]  (grid: channels x chunks)
+template <typename D>
+__global__ void bias_grad_kernel(const D* __restrict__ d, float* __restrict__ db, int B, int Cn,
+                                 size_t P) {
+  __shared__ float red[kBlock];
+  const int c = blockIdx.x;
+  float acc = 0.f;
+  const size_t total = size_t(B) * P;
+  for (size_t e = blockIdx.y * size_t(kBlock) + threadIdx.x; e < total;
+       e += size_t(gridDim.y) * kBlock) {
+    const size_t b = e / P, p = e % P;
+    const size_t idx = (b * Cn + c) * P + p;
+    if constexpr (sizeof(D) == 4) {
+      acc += d[idx];
+    } else {
+      acc += bf16_to_f32(d[idx]);
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(&db[c], red[0]);
+}
+
+// sums[2b] += sum (out - target)^2, sums[2b+1] += sum target^2 over sample b
+__global__ void loss_partial_kernel(const float* __restrict__ out, const uint16_t* __restrict__ tg,
+                                    double* __restrict__ sums, size_t per) {
+  __shared__ double r0[kBlock], r1[kBlock];
+  const int b = blockIdx.y;
+  double a0 = 0.0, a1 = 0.0;
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < per; i += size_t(gridDim.x) * kBlock) {
+    const double t = bf16_to_f32(tg[b * per + i]);
+    const double d = out[b * per + i] - t;
+    a0 += d * d;
+    a1 += t * t;
+  }
+  r0[threadIdx.x] = a0;
+  r1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) {
+      r0[threadIdx.x] += r0[threadIdx.x + s];
+      r1[threadIdx.x] += r1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&sums[2 * b], r0[0]);
+    atomicAdd(&sums[2 * b + 1], r1[0]);
+  }
+}
+
+// loss = mean_b |out_b - t_b| / |t_b|;  dout = (out - t) / (B |out_b - t_b| |t_b|)
+__global__ void loss_grad_kernel(const float* __restrict__ out, const uint16_t* __restrict__ tg,
+                                 const double* __restrict__ sums, uint16_t* __restrict__ dout,
+                                 int B, size_t per) {
+  const int b = blockIdx.y;
+  const double nd = sqrt(sums[2 * b]), nt = sqrt(sums[2 * b + 1]);
+  const float scale = (nd > 0.0 && nt > 0.0) ? static_cast<float>(1.0 / (B * nd * nt)) : 0.f;
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < per; i += size_t(gridDim.x) * kBlock) {
+    const float d = out[b * per + i] - bf16_to_f32(tg[b * per + i]);
+    dout[b * per + i] = f32_to_bf16(d * scale);
+  }
+}
+
+__global__ void loss_final_kernel(const double* __restrict__ sums, int B, float* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc = 0.0;
+  for (int b = 0; b < B; ++b) acc += sums[2 * b + 1] > 0.0 ? sqrt(sums[2 * b] / sums[2 * b + 1]) : 0.0;
+  *loss = static_cast<float>(acc / B);
+}
+
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                            float* __restrict__ m1, float* __restrict__ m2, size_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock) {
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.f - b1) * gi;
+    const float v = b2 * m2[i] + (1.f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = v;
+    p[i] -= lr * (a * c1) / (sqrtf(v * c2) + eps);
+  }
+}
+
+// Network input (n - n_shift, q2, q3, q4) and target (q2, q3, q4) as BF16 planes.
+__global__ void pack_kernel(const double* __restrict__ q, const double* __restrict__ n, size_t P,
+                            double n_shift, uint16_t* __restrict__ in4, uint16_t* __restrict__ t3) {
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < P; i += size_t(gridDim.x) * kBlock) {
+    if (in4) {
+      in4[i] = f32_to_bf16(static_cast<float>(n[i] - n_shift));
+      for (int c = 0; c < 3; ++c) in4[(c + 1) * P + i] = f32_to_bf16(static_cast<float>(q[c * P + i]));
+    }
+    if (t3)
+      for (int c = 0; c < 3; ++c) t3[c * P + i] = f32_to_bf16(static_cast<float>(q[c * P + i]));
+  }
+}
+
+// Energy sum q^2 over the three output channels of each sample of an FP32 batch.
+__global__ void energy_batch_kernel(const float* __restrict__ out, double* __restrict__ e,
+                                    size_t per) {
+  __shared__ double r[kBlock];
+  const int b = blockIdx.y;
+  double a = 0.0;
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < per; i += size_t(gridDim.x) * kBlock) {
+    const double v = out[b * per + i];
+    a += v * v;
+  }
+  r[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) r[threadIdx.x] += r[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(&e[b], r[0]);
+}
+
+// Small deterministic generator for the initial weights (splitmix64).
+struct Rng {
+  uint64_t s;
+  double uniform() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return static_cast<double>(z >> 11) * (1.0 / 9007199254740992.0);
+  }
+};
+
+}  // namespace
+
+struct qla_fno {
+  int H = 0, W = 0, P = 0, Cin = 0, C = 0, C2 = 0, Cout = 0, L = 0, m = 0, Bmax = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // flat parameter layout
+  size_t nparam = 0, o_Wp = 0, o_bp = 0, o_Q1 = 0, o_bq1 = 0, o_Q2 = 0, o_bq2 = 0;
+  std::vector<size_t> o_W, o_b, o_R;
+  size_t nweights16 = 0;  // BF16 copies: Wp | W_0..W_{L-1} | Q1 | Q2
+  float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
+  uint16_t* w16 = nullptr;
+  uint16_t *Fx = nullptr, *A1 = nullptr, *A2 = nullptr, *IY1 = nullptr, *IY2 = nullptr,
+           *IX = nullptr;
+  // activations (batch Bmax)
+  std::vector<uint16_t*> v, z;
+  uint16_t *Zb = nullptr, *Sb = nullptr, *Ub = nullptr, *zq = nullptr, *h = nullptr,
+           *dout = nullptr, *dh = nullptr, *dzq = nullptr, *dz = nullptr, *dU = nullptr,
+           *dT = nullptr, *dZ = nullptr, *dv16 = nullptr;
+  std::vector<float*> T;
+  float *spec = nullptr, *out = nullptr, *dS = nullptr, *dva = nullptr, *dvb = nullptr,
+        *loss = nullptr;
+  double* sums = nullptr;
+  int64_t adam_t = 0;
+  std::vector<void*> allocs;
+
+  size_t w16_Wp() const { return 0; }
+  size_t w16_W(int l) const { return size_t(C) * Cin + size_t(l) * C * C; }
+  size_t w16_Q1() const { return size_t(C) * Cin + size_t(L) * C * C; }
+  size_t w16_Q2() const { return w16_Q1() + size_t(C2) * C; }
+};
+
+namespace {
+
+qla_status dalloc(qla_fno* f, void** p, size_t bytes) {
+  const hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(QLA_ENOMEM, std::string("FNO allocation: ") + hipGetErrorString(e));
+  }
+  f->allocs.push_back(*p);
+  return QLA_OK;
+}
+
+template <typename P>
+qla_status dalloc_t(qla_fno* f, P** p, size_t count) {
+  return dalloc(f, reinterpret_cast<void**>(p), count * sizeof(P));
+}
+
+void release(qla_fno* f) {
+  for (void* p : f->allocs) (void)hipFree(p);
+  f->allocs.clear();
+  if (f->own_stream && f->stream) (void)hipStreamDestroy(f->stream);
+}
+
+std::vector<uint16_t> to_bf16(const std::vector<double>& v) {
+  std::vector<uint16_t> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = f32_to_bf16(static_cast<float>(v[i]));
+  return o;
+}
+
+qla_status upload16(qla_fno* f, uint16_t** dst, const std::vector<double>& v) {
+  qla_status st = dalloc_t(f, dst, v.size());
+  if (st != QLA_OK) return st;
+  const std::vector<uint16_t> h = to_bf16(v);
+  QLA_HIP(hipMemcpy(*dst, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  return QLA_OK;
+}
+
+// The cosine/sine bases of the truncated transforms (see the header comment).
+qla_status make_bases(qla_fno* f) {
+  const int H = f->H, W = f->W, m = f->m;
+  const double two_pi = 6.283185307179586476925286766559;
+  std::vector<double> Fx(size_t(W) * 2 * m), IX(size_t(2 * m) * W);
+  for (int x = 0; x < W; ++x)
+    for (int kx = 0; kx < m; ++kx) {
+      const double a = two_pi * kx * x / W;
+      Fx[size_t(x) * 2 * m + 2 * kx] = std::cos(a);
+      Fx[size_t(x) * 2 * m + 2 * kx + 1] = -std::sin(a);
+      const double w = (kx == 0 ? 1.0 : 2.0) / (double(H) * W);
+      IX[size_t(2 * kx) * W + x] = w * std::cos(a);
+      IX[size_t(2 * kx + 1) * W + x] = -w * std::sin(a);
+    }
+  std::vector<double> A1(size_t(4 * m) * H), A2(size_t(4 * m) * H), IY1(size_t(H) * 4 * m),
+      IY2(size_t(H) * 4 * m);
+  for (int kyi = 0; kyi < 2 * m; ++kyi) {
+    const int ky = kyi < m ? kyi : H - 2 * m + kyi;
+    for (int y = 0; y < H; ++y) {
+      const double a = two_pi * double(ky) * y / H, c = std::cos(a), s = std::sin(a);
+      A1[size_t(2 * kyi) * H + y] = c;       // T_re from Z_re
+      A1[size_t(2 * kyi + 1) * H + y] = -s;  // T_im from Z_re
+      A2[size_t(2 * kyi) * H + y] = s;       // T_re from Z_im
+      A2[size_t(2 * kyi + 1) * H + y] = c;   // T_im from Z_im
+      IY1[size_t(y) * 4 * m + 2 * kyi] = c;       // U_re from S_re
+      IY1[size_t(y) * 4 * m + 2 * kyi + 1] = -s;  // U_re from S_im
+      IY2[size_t(y) * 4 * m + 2 * kyi] = s;       // U_im from S_re
+      IY2[size_t(y) * 4 * m + 2 * kyi + 1] = c;   // U_im from S_im
+    }
+  }
+  qla_status st = upload16(f, &f->Fx, Fx);
+  if (st == QLA_OK) st = upload16(f, &f->IX, IX);
+  if (st == QLA_OK) st = upload16(f, &f->A1, A1);
+  if (st == QLA_OK) st = upload16(f, &f->A2, A2);
+  if (st == QLA_OK) st = upload16(f, &f->IY1, IY1);
+  if (st == QLA_OK) st = upload16(f, &f->IY2, IY2);
+  return st;
+}
+
+// BF16 copies of the GEMM weights from the FP32 master parameters.
+qla_status refresh_w16(qla_fno* f) {
+  auto cast = [&](size_t off, size_t dst, size_t n) -> hipError_t {
+    hipLaunchKernelGGL(cast_kernel, dim3(grid_for(n)), dim3(kBlock), 0, f->stream, f->p + off,
+                       f->w16 + dst, n);
+    return hipGetLastError();
+  };
+  QLA_HIP(cast(f->o_Wp, f->w16_Wp(), size_t(f->C) * f->Cin));
+  for (int l = 0; l < f->L; ++l) QLA_HIP(cast(f->o_W[l], f->w16_W(l), size_t(f->C) * f->C));
+  QLA_HIP(cast(f->o_Q1, f->w16_Q1(), size_t(f->C2) * f->C));
+  QLA_HIP(cast(f->o_Q2, f->w16_Q2(), size_t(f->Cout) * f->C2));
+  return QLA_OK;
+}
+
+// Per-sample 1x1 convolution: out[b][mo][p] = sum_k Wt[mo][k] in[b][k][p] (weights
+// row-major mo x k, or transposed when wt_t).
+GemmDesc pointwise(const uint16_t* wt, bool wt_t, int Mo, int K, const uint16_t* in, int B,
+                   size_t P) {
+  GemmDesc g;
+  g.A = wt;
+  g.sAb = 0;
+  g.sAm = wt_t ? 1 : K;
+  g.sAk = wt_t ? Mo : 1;
+  g.B = in;
+  g.sBb = static_cast<long long>(K) * P;
+  g.sBk = static_cast<long long>(P);
+  g.sBn = 1;
+  g.sCb = static_cast<long long>(Mo) * P;
+  g.sCm = static_cast<long long>(P);
+  g.sCn = 1;
+  g.M = Mo;
+  g.N = static_cast<int>(P);
+  g.K = K;
+  g.batch = B;
+  return g;
+}
+
+// Weight gradient dWt[mo][k] += sum_{b,p} d[b][mo][p] x[b][k][p] (split over pixels).
+GemmDesc weight_grad(const uint16_t* d, int Mo, const uint16_t* x, int K, int B, size_t P,
+                     float* dW) {
+  GemmDesc g;
+  g.A = d;
+  g.sAb = static_cast<long long>(Mo) * P;
+  g.sAm = static_cast<long long>(P);
+  g.sAk = 1;
+  g.B = x;
+  g.sBb = static_cast<long long>(K) * P;
+  g.sBk = 1;
+  g.sBn = static_cast<long long>(P);
+  g.C = dW;
+  g.sCb = 0;
+  g.sCm = K;
+  g.sCn = 1;
+  g.M = Mo;
+  g.N = K;
+  g.K = static_cast<int>(P);
+  g.batch = B;
+  g.ksplit = static_cast<int>(std::max<size_t>(1, std::min<size_t>(256, P / 2048)));
+  g.atomic = 1;
+  return g;
+}
+
+qla_status bias_grad16(qla_fno* f, const uint16_t* d, int B, int Cn, float* db) {
+  hipLaunchKernelGGL(bias_grad_kernel<uint16_t>, dim3(Cn, 64), dim3(kBlock), 0, f->stream, d, db,
+                     B, Cn, size_t(f->P));
+  QLA_HIP(hipGetLastError());
+  return QLA_OK;
+}
+
+#define QLA_GEMM(desc) QLA_HIP(qla::fno::launch_gemm((desc), f->stream))
+
+// Forward pass of batch B: input BF16 [B][Cin][P] -> f->out FP32 [B][Cout][P].
+qla_status forward(qla_fno* f, const uint16_t* in, int B) {
+  const size_t P = f->P;
+  const int C = f->C, H = f->H, W = f->W, m = f->m;
+  const long long modes_sz = 4LL * m * m;  // floats per (b, c) in T, S
+  // lift
+  {
+    GemmDesc g = pointwise(f->w16 + f->w16_Wp(), false, C, f->Cin, in, B, P);
+    g.C = f->v[0];
+    g.out_bf16 = 1;
+    g.bias = f->p + f->o_bp;
+    QLA_GEMM(g);
+  }
+  for (int l = 0; l < f->L; ++l) {
+    const uint16_t* vl = f->v[l];
+    // x transform: Z[(b,c,y)][2kx+p]
+    {
+      GemmDesc g;
+      g.A = vl;
+      g.sAm = W;
+      g.sAk = 1;
+      g.B = f->Fx;
+      g.sBk = 2 * m;
+      g.sBn = 1;
+      g.C = f->Zb;
+      g.sCm = 2 * m;
+      g.sCn = 1;
+      g.M = B * C * H;
+      g.N = 2 * m;
+      g.K = W;
+      g.out_bf16 = 1;
+      QLA_GEMM(g);
+    }
+    // y transform: T[(b,c)] = A1 Zre + A2 Zim
+    for (int part = 0; part < 2; ++part) {
+      GemmDesc g;
+      g.A = part ? f->A2 : f->A1;
+      g.sAm = H;
+      g.sAk = 1;
+      g.B = f->Zb + part;
+      g.sBb = static_cast<long long>(H) * 2 * m;
+      g.sBk = 2 * m;
+      g.sBn = 2;
+      g.C = f->T[l];
+      g.sCb = modes_sz;
+      g.sCm = m;
+      g.sCn = 1;
+      g.M = 4 * m;
+      g.N = m;
+      g.K = H;
+      g.batch = B * C;
+      g.beta = part;
+      QLA_GEMM(g);
+    }
+    hipLaunchKernelGGL(mix_forward_kernel, dim3(grid_for(size_t(B) * C * 2 * m * m)),
+                       dim3(kBlock), 0, f->stream, f->T[l], f->p + f->o_R[l], f->Sb, B, C, m);
+    QLA_HIP(hipGetLastError());
+    // inverse y: U[(b,o)][y][2kx+p] = IY_p S
+    for (int part = 0; part < 2; ++part) {
+      GemmDesc g;
+      g.A = part ? f->IY2 : f->IY1;
+      g.sAm = 4 * m;
+      g.sAk = 1;
+      g.B = f->Sb;
+      g.sBb = modes_sz;
+      g.sBk = m;
+      g.sBn = 1;
+      g.C = f->Ub + part;
+      g.sCb = static_cast<long long>(H) * 2 * m;
+      g.sCm = 2 * m;
+      g.sCn = 2;
+      g.M = H;
+      g.N = m;
+      g.K = 4 * m;
+      g.batch = B * C;
+      g.out_bf16 = 1;
+      QLA_GEMM(g);
+    }
+    // inverse x: spec[(b,o,y)][x]
+    {
+      GemmDesc g;
+      g.A = f->Ub;
+      g.sAm = 2 * m;
+      g.sAk = 1;
+      g.B = f->IX;
+      g.sBk = W;
+      g.sBn = 1;
+      g.C = f->spec;
+      g.sCm = W;
+      g.sCn = 1;
+      g.M = B * C * H;
+      g.N = W;
+      g.K = 2 * m;
+      QLA_GEMM(g);
+    }
+    // pointwise + spectral + bias, then GELU (not after the last layer)
+    {
+      GemmDesc g = pointwise(f->w16 + f->w16_W(l), false, C, C, vl, B, P);
+      g.bias = f->p + f->o_b[l];
+      g.res = f->spec;
+      g.sRb = static_cast<long long>(C) * P;
+      g.sRm = static_cast<long long>(P);
+      g.sRn = 1;
+      g.out_bf16 = 1;
+      if (l + 1 < f->L) {
+        g.C = f->z[l];
+        g.act = f->v[l + 1];
+      } else {
+        g.C = f->v[l + 1];
+      }
+      QLA_GEMM(g);
+    }
+  }
+  // projection: h = GELU(Q1 v_L + bq1), out = Q2 h + bq2
+  {
+    GemmDesc g = pointwise(f->w16 + f->w16_Q1(), false, f->C2, C, f->v[f->L], B, P);
+    g.bias = f->p + f->o_bq1;
+    g.C = f->zq;
+    g.out_bf16 = 1;
+    g.act = f->h;
+    QLA_GEMM(g);
+  }
+  {
+    GemmDesc g = pointwise(f->w16 + f->w16_Q2(), false, f->Cout, f->C2, f->h, B, P);
+    g.bias = f->p + f->o_bq2;
+    g.C = f->out;
+    QLA_GEMM(g);
+  }
+  return QLA_OK;
+}
+
+// Loss and gradients of the batch (forward must have run on `in`). Gradients are
+// accumulated into f->g, which the caller zeroes.
+qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int B) {
+  const size_t P = f->P;
+  const int C = f->C, C2 = f->C2, H = f->H, W = f->W, m = f->m, L = f->L;
+  const size_t per = size_t(f->Cout) * P;
+  const long long modes_sz = 4LL * m * m;
+  QLA_HIP(hipMemsetAsync(f->sums, 0, 2 * B * sizeof(double), f->stream));
+  hipLaunchKernelGGL(loss_partial_kernel, dim3(256, B), dim3(kBlock), 0, f->stream, f->out,
+                     target, f->sums, per);
+  QLA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, f->stream, f->sums, B, f->loss);
+  QLA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(256, B), dim3(kBlock), 0, f->stream, f->out, target,
+                     f->sums, f->dout, B, per);
+  QLA_HIP(hipGetLastError());
+  // projection 2
+  QLA_GEMM(weight_grad(f->dout, f->Cout, f->h, C2, B, P, f->g + f->o_Q2));
+  {
+    const qla_status st = bias_grad16(f, f->dout, B, f->Cout, f->g + f->o_bq2);
+    if (st != QLA_OK) return st;
+  }
+  {
+    GemmDesc g = pointwise(f->w16 + f->w16_Q2(), true, C2, f->Cout, f->dout, B, P);
+    g.C = f->dh;
+    g.out_bf16 = 1;
+    QLA_GEMM(g);
+  }
+  hipLaunchKernelGGL(gelu_grad_kernel<uint16_t>, dim3(grid_for(size_t(B) * C2 * P)), dim3(kBlock), 0,
+                     f->stream, f->dh, f->zq, f->dzq, size_t(B) * C2 * P);
+  QLA_HIP(hipGetLastError());
+  // projection 1
+  QLA_GEMM(weight_grad(f->dzq, C2, f->v[L], C, B, P, f->g + f->o_Q1));
+  {
+    const qla_status st = bias_grad16(f, f->dzq, B, C2, f->g + f->o_bq1);
+    if (st != QLA_OK) return st;
+  }
+  float* dv = f->dva;  // gradient with respect to v_{l+1}
+  float* dv_next = f->dvb;
+  {
+    GemmDesc g = pointwise(f->w16 + f->w16_Q1(), true, C, C2, f->dzq, B, P);
+    g.C = dv;
+    QLA_GEMM(g);
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    const size_t nact = size_t(B) * C * P;
+    if (l + 1 < L) {
+      hipLaunchKernelGGL(gelu_grad_kernel<float>, dim3(grid_for(nact)), dim3(kBlock), 0, f->stream,
+                         dv, f->z[l], f->dz, nact);
+    } else {
+      hipLaunchKernelGGL(cast_kernel, dim3(grid_for(nact)), dim3(kBlock), 0, f->stream, dv, f->dz,
+                         nact);
+    }
+    QLA_HIP(hipGetLastError());
+    const uint16_t* vl = f->v[l];
+    // pointwise branch
+    QLA_GEMM(weight_grad(f->dz, C, vl, C, B, P, f->g + f->o_W[l]));
+    {
+      const qla_status st = bias_grad16(f, f->dz, B, C, f->g + f->o_b[l]);
+      if (st != QLA_OK) return st;
+    }
+    {
+      GemmDesc g = pointwise(f->w16 + f->w16_W(l), true, C, C, f->dz, B, P);
+      g.C = dv_next;
+      QLA_GEMM(g);
+    }
+    // spectral branch: dU = dz IX^T
+    {
+      GemmDesc g;
+      g.A = f->dz;
+      g.sAm = W;
+      g.sAk = 1;
+      g.B = f->IX;
+      g.sBk = 1;
+      g.sBn = W;
+      g.C = f->dU;
+      g.sCm = 2 * m;
+      g.sCn = 1;
+      g.M = B * C * H;
+      g.N = 2 * m;
+      g.K = W;
+      g.out_bf16 = 1;
+      QLA_GEMM(g);
+    }
+    // dS = IY1^T dUre + IY2^T dUim
+    for (int part = 0; part < 2; ++part) {
+      GemmDesc g;
+      g.A = part ? f->IY2 : f->IY1;
+      g.sAm = 1;
+      g.sAk = 4 * m;
+      g.B = f->dU + part;
+      g.sBb = static_cast<long long>(H) * 2 * m;
+      g.sBk = 2 * m;
+      g.sBn = 2;
+      g.C = f->dS;
+      g.sCb = modes_sz;
+      g.sCm = m;
+      g.sCn = 1;
+      g.M = 4 * m;
+      g.N = m;
+      g.K = H;
+      g.batch = B * C;
+      g.beta = part;
+      QLA_GEMM(g);
+    }
+    hipLaunchKernelGGL(mix_backward_weight_kernel, dim3(grid_for(size_t(2 * m * m) * C * C)),
+                       dim3(kBlock), 0, f->stream, f->dS, f->T[l], f->g + f->o_R[l], B, C, m);
+    QLA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(mix_backward_input_kernel, dim3(grid_for(size_t(B) * C * 2 * m * m)),
+                       dim3(kBlock), 0, f->stream, f->dS, f->p + f->o_R[l], f->dT, B, C, m);
+    QLA_HIP(hipGetLastError());
+    // dZ_p = A_p^T dT  (p = re, im)
+    for (int part = 0; part < 2; ++part) {
+      GemmDesc g;
+      g.A = part ? f->A2 : f->A1;
+      g.sAm = 1;
+      g.sAk = H;
+      g.B = f->dT;
+      g.sBb = modes_sz;
+      g.sBk = m;
+      g.sBn = 1;
+      g.C = f->dZ + part;
+      g.sCb = static_cast<long long>(H) * 2 * m;
+      g.sCm = 2 * m;
+      g.sCn = 2;
+      g.M = H;
+      g.N = m;
+      g.K = 4 * m;
+      g.batch = B * C;
+      g.out_bf16 = 1;
+      QLA_GEMM(g);
+    }
+    // dv_l += dZ Fx^T
+    {
+      GemmDesc g;
+      g.A = f->dZ;
+      g.sAm = 2 * m;
+      g.sAk = 1;
+      g.B = f->Fx;
+      g.sBk = 1;
+      g.sBn = 2 * m;
+      g.C = dv_next;
+      g.sCm = W;
+      g.sCn = 1;
+      g.M = B * C * H;
+      g.N = W;
+      g.K = 2 * m;
+      g.beta = 1;
+      QLA_GEMM(g);
+    }
+    std::swap(dv, dv_next);
+  }
+  // lift
+  const size_t n0 = size_t(B) * C * P;
+  hipLaunchKernelGGL(cast_kernel, dim3(grid_for(n0)), dim3(kBlock), 0, f->stream, dv, f->dv16, n0);
+  QLA_HIP(hipGetLastError());
+  QLA_GEMM(weight_grad(f->dv16, C, in, f->Cin, B, P, f->g + f->o_Wp));
+  return bias_grad16(f, f->dv16, B, C, f->g + f->o_bp);
+}
+
+qla_status check_batch(const qla_fno* f, int B) {
+  if (B < 1 || B > f->Bmax) return fail(QLA_EINVAL, "batch must be in [1, max_batch]");
+  return QLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qla_status qla_fno_create(int height, int width, int in_channels, int out_channels, int channels,
+                          int modes, int layers, int proj_channels, int max_batch, uint64_t seed,
+                          void* hip_stream, qla_fno** out) {
+  if (!out) return fail(QLA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (height < 2 || width < 2 || in_channels < 1 || out_channels < 1 || channels < 1 ||
+      modes < 1 || layers < 1 || proj_channels < 1 || max_batch < 1)
+    return fail(QLA_EINVAL, "sizes must be positive");
+  if (2 * modes > height || 2 * modes > width)
+    return fail(QLA_EINVAL, "need 2 * modes <= height and 2 * modes <= width");
+  if (static_cast<long long>(max_batch) * std::max(channels, proj_channels) * height * width >=
+      (1ll << 31))
+    return fail(QLA_EINVAL, "max_batch * channels * height * width must be < 2^31");
+  qla_fno* f = new (std::nothrow) qla_fno;
+  if (!f) return fail(QLA_ENOMEM, "host allocation");
+  f->H = height;
+  f->W = width;
+  f->P = height * width;
+  f->Cin = in_channels;
+  f->Cout = out_channels;
+  f->C = channels;
+  f->C2 = proj_channels;
+  f->L = layers;
+  f->m = modes;
+  f->Bmax = max_batch;
+  hipError_t e = hipGetDevice(&f->device);
+  if (e == hipSuccess && hip_stream) {
+    f->stream = static_cast<hipStream_t>(hip_stream);
+  } else if (e == hipSuccess) {
+    e = hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking);
+    f->own_stream = e == hipSuccess;
+  }
+  if (e != hipSuccess) {
+    delete f;
+    return hip_fail(e, "stream");
+  }
+  // parameter layout
+  const int C = channels, m = modes;
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    const size_t o = off;
+    off += n;
+    return o;
+  };
+  f->o_Wp = take(size_t(C) * in_channels);
+  f->o_bp = take(C);
+  for (int l = 0; l < layers; ++l) {
+    f->o_W.push_back(take(size_t(C) * C));
+    f->o_b.push_back(take(C));
+    f->o_R.push_back(take(size_t(2 * m * m) * C * C * 2));
+  }
+  f->o_Q1 = take(size_t(proj_channels) * C);
+  f->o_bq1 = take(proj_channels);
+  f->o_Q2 = take(size_t(out_channels) * proj_channels);
+  f->o_bq2 = take(out_channels);
+  f->nparam = off;
+  f->nweights16 = size_t(C) * in_channels + size_t(layers) * C * C + size_t(proj_channels) * C +
+                  size_t(out_channels) * proj_channels;
+  const size_t B = max_batch, P = f->P;
+  qla_status st = QLA_OK;
+  auto A = [&](auto** p, size_t n) {
+    if (st == QLA_OK) st = dalloc_t(f, p, n);
+  };
+  A(&f->p, f->nparam);
+  A(&f->g, f->nparam);
+  A(&f->m1, f->nparam);
+  A(&f->m2, f->nparam);
+  A(&f->w16, f->nweights16);
+  f->v.assign(layers + 1, nullptr);
+  f->z.assign(layers, nullptr);
+  f->T.assign(layers, nullptr);
+  for (int l = 0; l <= layers; ++l) A(&f->v[l], B * C * P);
+  for (int l = 0; l + 1 < layers; ++l) A(&f->z[l], B * C * P);
+  for (int l = 0; l < layers; ++l) A(&f->T[l], B * C * 4 * m * m);
+  A(&f->Zb, B * C * height * 2 * m);
+  A(&f->Sb, B * C * 4 * m * m);
+  A(&f->Ub, B * C * height * 2 * m);
+  A(&f->spec, B * C * P);
+  A(&f->zq, B * proj_channels * P);
+  A(&f->h, B * proj_channels * P);
+  A(&f->out, B * out_channels * P);
+  A(&f->dout, B * out_channels * P);
+  A(&f->dh, B * proj_channels * P);
+  A(&f->dzq, B * proj_channels * P);
+  A(&f->dva, B * C * P);
+  A(&f->dvb, B * C * P);
+  A(&f->dz, B * C * P);
+  A(&f->dv16, B * C * P);
+  A(&f->dU, B * C * height * 2 * m);
+  A(&f->dS, B * C * 4 * m * m);
+  A(&f->dT, B * C * 4 * m * m);
+  A(&f->dZ, B * C * height * 2 * m);
+  A(&f->loss, 1);
+  A(&f->sums, 2 * B);
+  if (st == QLA_OK) st = make_bases(f);
+  if (st != QLA_OK) {
+    release(f);
+    delete f;
+    return st;
+  }
+  // initial weights: linear maps U(-1/sqrt(fan_in), 1/sqrt(fan_in)); spectral weights
+  // 1/(C*C) times U(0, 1) for both parts
+  std::vector<float> hp(f->nparam);
+  Rng rng{seed};
+  auto lin = [&](size_t o, size_t n, int fan_in) {
+    const double a = 1.0 / std::sqrt(double(fan_in));
+    for (size_t i = 0; i < n; ++i) hp[o + i] = static_cast<float>((2.0 * rng.uniform() - 1.0) * a);
+  };
+  lin(f->o_Wp, size_t(C) * in_channels, in_channels);
+  lin(f->o_bp, C, in_channels);
+  for (int l = 0; l < layers; ++l) {
+    lin(f->o_W[l], size_t(C) * C, C);
+    lin(f->o_b[l], C, C);
+    const size_t n = size_t(2 * m * m) * C * C * 2;
+    for (size_t i = 0; i < n; ++i) hp[f->o_R[l] + i] = static_cast<float>(rng.uniform() / (double(C) * C));
+  }
+  lin(f->o_Q1, size_t(proj_channels) * C, C);
+  lin(f->o_bq1, proj_channels, C);
+  lin(f->o_Q2, size_t(out_channels) * proj_channels, proj_channels);
+  lin(f->o_bq2, out_channels, proj_channels);
+  e = hipMemcpy(f->p, hp.data(), hp.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(f->m1, 0, f->nparam * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(f->m2, 0, f->nparam * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(f->g, 0, f->nparam * sizeof(float));
+  if (e != hipSuccess) {
+    release(f);
+    delete f;
+    return hip_fail(e, "FNO initialisation");
+  }
+  st = refresh_w16(f);
+  if (st == QLA_OK) {
+    e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+  }
+  if (st != QLA_OK) {
+    release(f);
+    delete f;
+    return st;
+  }
+  *out = f;
+  return QLA_OK;
+}
+
+qla_status qla_fno_destroy(qla_fno* f) {
+  if (!f) return QLA_OK;
+  DeviceGuard g(f->device);
+  if (f->stream) (void)hipStreamSynchronize(f->stream);
+  release(f);
+  delete f;
+  return QLA_OK;
+}
+
+qla_status qla_fno_param_count(const qla_fno* f, int64_t* count) {
+  if (!f || !count) return fail(QLA_EINVAL, "NULL argument");
+  *count = static_cast<int64_t>(f->nparam);
+  return QLA_OK;
+}
+
+qla_status qla_fno_get_params(qla_fno* f, float* host) {
+  if (!f || !host) return fail(QLA_EINVAL, "NULL argument");
+  DeviceGuard g(f->device);
+  QLA_HIP(hipMemcpyAsync(host, f->p, f->nparam * sizeof(float), hipMemcpyDeviceToHost, f->stream));
+  QLA_HIP(hipStreamSynchronize(f->stream));
+  return QLA_OK;
+}
+
+qla_status qla_fno_set_params(qla_fno* f, const float* host) {
+  if (!f || !host) return fail(QLA_EINVAL, "NULL argument");
+  DeviceGuard g(f->device);
+  QLA_HIP(hipMemcpyAsync(f->p, host, f->nparam * sizeof(float), hipMemcpyHostToDevice, f->stream));
+  qla_status st = refresh_w16(f);
+  if (st != QLA_OK) return st;
+  QLA_HIP(hipStreamSynchronize(f->stream));
+  return QLA_OK;
+}
+
+qla_status qla_fno_get_grads(qla_fno* f, float* host) {
+  if (!f || !host) return fail(QLA_EINVAL, "NULL argument");
+  DeviceGuard g(f->device);
+  QLA_HIP(hipMemcpyAsync(host, f->g, f->nparam * sizeof(float), hipMemcpyDeviceToHost, f->stream));
+  QLA_HIP(hipStreamSynchronize(f->stream));
+  return QLA_OK;
+}
+
+qla_status qla_fno_forward(qla_fno* f, const uint16_t* input, int batch, float* output) {
+  if (!f || !input || !output) return fail(QLA_EINVAL, "NULL argument");
+  qla_status st = check_batch(f, batch);
+  if (st != QLA_OK) return st;
+  DeviceGuard g(f->device);
+  st = forward(f, input, batch);
+  if (st != QLA_OK) return st;
+  QLA_HIP(hipMemcpyAsync(output, f->out, size_t(batch) * f->Cout * f->P * sizeof(float),
+                         hipMemcpyDeviceToDevice, f->stream));
+  return QLA_OK;
+}
+
+qla_status qla_fno_loss_grad(qla_fno* f, const uint16_t* input, const uint16_t* target, int batch,
+                             float* loss_host) {
+  if (!f || !input || !target) return fail(QLA_EINVAL, "NULL argument");
+  qla_status st = check_batch(f, batch);
+  if (st != QLA_OK) return st;
+  DeviceGuard g(f->device);
+  QLA_HIP(hipMemsetAsync(f->g, 0, f->nparam * sizeof(float), f->stream));
+  st = forward(f, input, batch);
+  if (st == QLA_OK) st = backward(f, input, target, batch);
+  if (st != QLA_OK) return st;
+  if (loss_host) {
+    QLA_HIP(hipMemcpyAsync(loss_host, f->loss, sizeof(float), hipMemcpyDeviceToHost, f->stream));
+    QLA_HIP(hipStreamSynchronize(f->stream));
+  }
+  return QLA_OK;
+}
+
+qla_status qla_fno_adam_step(qla_fno* f, float lr, float beta1, float beta2, float eps) {
+  if (!f) return fail(QLA_EINVAL, "NULL argument");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return fail(QLA_EINVAL, "bad Adam hyper-parameters");
+  DeviceGuard g(f->device);
+  ++f->adam_t;
+  const float c1 = static_cast<float>(1.0 / (1.0 - std::pow(double(beta1), double(f->adam_t))));
+  const float c2 = static_cast<float>(1.0 / (1.0 - std::pow(double(beta2), double(f->adam_t))));
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(f->nparam)), dim3(kBlock), 0, f->stream, f->p, f->g,
+                     f->m1, f->m2, f->nparam, lr, beta1, beta2, eps, c1, c2);
+  QLA_HIP(hipGetLastError());
+  return refresh_w16(f);
+}
+
+qla_status qla_fno_train_step(qla_fno* f, const uint16_t* input, const uint16_t* target,
+                              int batch, float lr, float* loss_device) {
+  qla_status st = qla_fno_loss_grad(f, input, target, batch, nullptr);
+  if (st != QLA_OK) return st;
+  if (loss_device) {
+    DeviceGuard g(f->device);
+    QLA_HIP(hipMemcpyAsync(loss_device, f->loss, sizeof(float), hipMemcpyDeviceToDevice,
+                           f->stream));
+  }
+  return qla_fno_adam_step(f, lr, 0.9f, 0.999f, 1e-8f);
+}
+
+qla_status qla_fno_output_energy(qla_fno* f, int batch, double* energy_device) {
+  if (!f || !energy_device) return fail(QLA_EINVAL, "NULL argument");
+  qla_status st = check_batch(f, batch);
+  if (st != QLA_OK) return st;
+  DeviceGuard g(f->device);
+  QLA_HIP(hipMemsetAsync(energy_device, 0, batch * sizeof(double), f->stream));
+  hipLaunchKernelGGL(energy_batch_kernel, dim3(256, batch), dim3(kBlock), 0, f->stream, f->out,
+                     energy_device, size_t(f->Cout) * f->P);
+  QLA_HIP(hipGetLastError());
+  return QLA_OK;
+}
+
+qla_status qla_fno_pack(const double* q_device, const double* n_device, int nx, int ny,
+                        double n_shift, uint16_t* input_device, uint16_t* target_device,
+                        void* hip_stream) {
+  if (!q_device || (input_device && !n_device) || nx < 1 || ny < 1)
+    return fail(QLA_EINVAL, "bad pack arguments");
+  const size_t P = size_t(nx) * ny;
+  hipLaunchKernelGGL(pack_kernel, dim3(grid_for(P)), dim3(kBlock), 0,
+                     static_cast<hipStream_t>(hip_stream), q_device, n_device, P, n_shift,
+                     input_device, target_device);
+  QLA_HIP(hipGetLastError());
+  return QLA_OK;
+}
+
+}  // extern "C"

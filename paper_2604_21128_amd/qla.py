@@ -30,7 +30,10 @@ EXPORTED = (
     "qla_energy", "qla_energy_device", "qla_get_coefficients", "qla_step_count",
     "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_destroy", "qla_strerror",
     "qla_last_error", "qla_batch_create", "qla_batch_context", "qla_batch_plan", "qla_batch_run",
-    "qla_batch_plan_info", "qla_batch_destroy",
+    "qla_batch_plan_info", "qla_batch_destroy", "qla_fno_create", "qla_fno_destroy",
+    "qla_fno_param_count", "qla_fno_get_params", "qla_fno_set_params", "qla_fno_get_grads",
+    "qla_fno_forward", "qla_fno_loss_grad", "qla_fno_adam_step", "qla_fno_train_step",
+    "qla_fno_output_energy", "qla_fno_pack",
 )
 
 
@@ -58,6 +61,7 @@ def load(path: str = LIB_PATH):
         raise ImportError(f"{path} is not built; run `python -m paper_2604_21128_amd.build`")
     lib = ctypes.CDLL(path)
     vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+    fp = ctypes.POINTER(ctypes.c_float)
     st = ctypes.c_int
     proto = {
         "qla_create": (st, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -88,6 +92,18 @@ def load(path: str = LIB_PATH):
         "qla_batch_plan_info": (st, [vp] + [ctypes.POINTER(ctypes.c_int)] * 5
                                 + [ctypes.POINTER(i64)]),
         "qla_batch_destroy": (st, [vp]),
+        "qla_fno_create": (st, [ctypes.c_int] * 9 + [ctypes.c_uint64, vp, ctypes.POINTER(vp)]),
+        "qla_fno_destroy": (st, [vp]),
+        "qla_fno_param_count": (st, [vp, ctypes.POINTER(i64)]),
+        "qla_fno_get_params": (st, [vp, fp]),
+        "qla_fno_set_params": (st, [vp, fp]),
+        "qla_fno_get_grads": (st, [vp, fp]),
+        "qla_fno_forward": (st, [vp, vp, ctypes.c_int, vp]),
+        "qla_fno_loss_grad": (st, [vp, vp, vp, ctypes.c_int, fp]),
+        "qla_fno_adam_step": (st, [vp] + [ctypes.c_float] * 4),
+        "qla_fno_train_step": (st, [vp, vp, vp, ctypes.c_int, ctypes.c_float, vp]),
+        "qla_fno_output_energy": (st, [vp, ctypes.c_int, vp]),
+        "qla_fno_pack": (st, [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]),
         "qla_strerror": (ctypes.c_char_p, [st]),
         "qla_last_error": (ctypes.c_char_p, []),
     }
@@ -265,6 +281,98 @@ def qla_batch_plan_info(batch: int) -> dict:
 
 def qla_batch_destroy(batch: int) -> None:
     _check(load().qla_batch_destroy(ctypes.c_void_p(batch)), "qla_batch_destroy")
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def qla_fno_create(height: int, width: int, in_channels: int, out_channels: int, channels: int,
+                   modes: int, layers: int, proj_channels: int, max_batch: int, seed: int = 0,
+                   hip_stream: Optional[int] = None) -> int:
+    out = ctypes.c_void_p()
+    _check(load().qla_fno_create(int(height), int(width), int(in_channels), int(out_channels),
+                                 int(channels), int(modes), int(layers), int(proj_channels),
+                                 int(max_batch), ctypes.c_uint64(int(seed)),
+                                 ctypes.c_void_p(hip_stream) if hip_stream else None,
+                                 ctypes.byref(out)), "qla_fno_create")
+    return int(out.value)
+
+
+def qla_fno_destroy(fno: int) -> None:
+    _check(load().qla_fno_destroy(ctypes.c_void_p(fno)), "qla_fno_destroy")
+
+
+def qla_fno_param_count(fno: int) -> int:
+    v = ctypes.c_int64()
+    _check(load().qla_fno_param_count(ctypes.c_void_p(fno), ctypes.byref(v)),
+           "qla_fno_param_count")
+    return int(v.value)
+
+
+def qla_fno_get_params(fno: int) -> np.ndarray:
+    out = np.empty(qla_fno_param_count(fno), dtype=np.float32)
+    _check(load().qla_fno_get_params(ctypes.c_void_p(fno), _fptr(out)), "qla_fno_get_params")
+    return out
+
+
+def qla_fno_set_params(fno: int, params: np.ndarray) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != qla_fno_param_count(fno):
+        raise ValueError("parameter vector has the wrong length")
+    _check(load().qla_fno_set_params(ctypes.c_void_p(fno), _fptr(p)), "qla_fno_set_params")
+
+
+def qla_fno_get_grads(fno: int) -> np.ndarray:
+    out = np.empty(qla_fno_param_count(fno), dtype=np.float32)
+    _check(load().qla_fno_get_grads(ctypes.c_void_p(fno), _fptr(out)), "qla_fno_get_grads")
+    return out
+
+
+def qla_fno_forward(fno: int, input_device, batch: int, output_device) -> None:
+    _check(load().qla_fno_forward(ctypes.c_void_p(fno), ctypes.c_void_p(_devptr(input_device)),
+                                  int(batch), ctypes.c_void_p(_devptr(output_device))),
+           "qla_fno_forward")
+
+
+def qla_fno_loss_grad(fno: int, input_device, target_device, batch: int) -> float:
+    loss = ctypes.c_float()
+    _check(load().qla_fno_loss_grad(ctypes.c_void_p(fno), ctypes.c_void_p(_devptr(input_device)),
+                                    ctypes.c_void_p(_devptr(target_device)), int(batch),
+                                    ctypes.byref(loss)), "qla_fno_loss_grad")
+    return float(loss.value)
+
+
+def qla_fno_adam_step(fno: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                      eps: float = 1e-8) -> None:
+    _check(load().qla_fno_adam_step(ctypes.c_void_p(fno), float(lr), float(beta1), float(beta2),
+                                    float(eps)), "qla_fno_adam_step")
+
+
+def qla_fno_train_step(fno: int, input_device, target_device, batch: int, lr: float,
+                       loss_device=None) -> None:
+    _check(load().qla_fno_train_step(ctypes.c_void_p(fno), ctypes.c_void_p(_devptr(input_device)),
+                                     ctypes.c_void_p(_devptr(target_device)), int(batch),
+                                     float(lr),
+                                     ctypes.c_void_p(_devptr(loss_device))
+                                     if loss_device is not None else None),
+           "qla_fno_train_step")
+
+
+def qla_fno_output_energy(fno: int, batch: int, energy_device) -> None:
+    _check(load().qla_fno_output_energy(ctypes.c_void_p(fno), int(batch),
+                                        ctypes.c_void_p(_devptr(energy_device))),
+           "qla_fno_output_energy")
+
+
+def qla_fno_pack(q_device, n_device, nx: int, ny: int, n_shift: float, input_device=None,
+                 target_device=None, hip_stream: Optional[int] = None) -> None:
+    def opt(x):
+        return ctypes.c_void_p(_devptr(x)) if x is not None else None
+    _check(load().qla_fno_pack(ctypes.c_void_p(_devptr(q_device)), opt(n_device), int(nx),
+                               int(ny), float(n_shift), opt(input_device), opt(target_device),
+                               ctypes.c_void_p(hip_stream) if hip_stream else None),
+           "qla_fno_pack")
 
 
 def qla_strerror(status: int) -> str:

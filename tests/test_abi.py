@@ -68,3 +68,27 @@ def test_null_context_is_rejected():
     assert lib.qla_advance(None, 1) == qla.QLA_EINVAL
     assert lib.qla_energy(None, None) == qla.QLA_EINVAL
     assert lib.qla_destroy(None) == qla.QLA_OK
+
+
+@pytest.mark.parametrize("args", [
+    (32, 32, 4, 3, 16, 17, 2, 32, 2),     # 2 * modes > height
+    (32, 20, 4, 3, 16, 12, 2, 32, 2),     # 2 * modes > width
+    (32, 32, 0, 3, 16, 4, 2, 32, 2),      # no input channels
+    (32, 32, 4, 3, 16, 4, 0, 32, 2),      # no layers
+    (32, 32, 4, 3, 16, 4, 2, 32, 0),      # no batch
+    (8192, 8192, 4, 3, 64, 12, 4, 128, 4),  # activations beyond 2^31 elements
+])
+def test_surrogate_create_rejects_bad_sizes_before_touching_the_device(args):
+    qla, lib = _lib()
+    out = ctypes.c_void_p(1234)
+    st = lib.qla_fno_create(*args, 0, None, ctypes.byref(out))
+    assert st == qla.QLA_EINVAL
+    assert out.value is None
+
+
+def test_surrogate_null_handle_is_rejected():
+    qla, lib = _lib()
+    assert lib.qla_fno_forward(None, None, 1, None) == qla.QLA_EINVAL
+    assert lib.qla_fno_adam_step(None, 1e-3, 0.9, 0.999, 1e-8) == qla.QLA_EINVAL
+    assert lib.qla_fno_param_count(None, None) == qla.QLA_EINVAL
+    assert lib.qla_fno_destroy(None) == qla.QLA_OK

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "Ellipse", "Packet", "Workload", "ellipse_index", "slab_index",
     "parity_small", "plain_4096", "bubble_8192", "workload_by_name",
-    "sample_instances", "Instance",
+    "sample_instances", "Instance", "ellipse_index_batch",
 ]
 
 
@@ -191,3 +191,26 @@ def sample_instances(count: int, seed: int = 0, n_min: int = 256, n_max: int = 1
             packet=Packet(x0=x0, y0=yc, sigma=sigma, lam=lam),
             steps=4 * side))
     return out
+
+
+def ellipse_index_batch(nx: int, ny: int, ellipses, device=None):
+    """`ellipse_index` for many ellipses at once, as a torch float64 tensor
+    [len(ellipses), ny, nx] on `device` (same formula, evaluated by torch)."""
+    import torch
+    k = len(ellipses)
+    t = lambda vals: torch.tensor(vals, dtype=torch.float64, device=device).view(k, 1, 1)
+    xc, yc = t([e.xc for e in ellipses]), t([e.yc for e in ellipses])
+    a, b = t([e.a for e in ellipses]), t([e.b for e in ellipses])
+    cr, sr = t([math.cos(e.rot) for e in ellipses]), t([math.sin(e.rot) for e in ellipses])
+    n_in, n_out = t([e.n_in for e in ellipses]), t([e.n_out for e in ellipses])
+    width = t([e.width for e in ellipses])
+    x = torch.arange(nx, dtype=torch.float64, device=device).view(1, 1, nx) - xc
+    y = torch.arange(ny, dtype=torch.float64, device=device).view(1, ny, 1) - yc
+    xp = x * cr + y * sr
+    yp = -x * sr + y * cr
+    rho2 = (xp / a) ** 2 + (yp / b) ** 2
+    g = torch.sqrt((xp / (a * a)) ** 2 + (yp / (b * b)) ** 2)
+    d = torch.where(g > 0.0, (rho2 - 1.0) / (2.0 * torch.where(g > 0.0, g, 1.0)),
+                    torch.full_like(g, -math.inf))
+    prof = 0.5 * (1.0 - torch.tanh(d / width))
+    return (n_out + (n_in - n_out) * prof).contiguous()
