@@ -387,8 +387,9 @@ def surrogate_study(qla, torch, args):
     from paper_2604_21128_amd import surrogate as S
     side, steps, B = args.side, args.surrogate_steps, args.batch
     log = lambda m: print(f"[surrogate] {m}", file=sys.stderr, flush=True)
-    train_i = workloads.sample_instances(args.train_count, seed=10, fixed_side=side)
-    test_i = workloads.sample_instances(args.test_count, seed=11, fixed_side=side)
+    lam = dict(lam_min=args.lam_range[0], lam_max=args.lam_range[1])
+    train_i = workloads.sample_instances(args.train_count, seed=10, fixed_side=side, **lam)
+    test_i = workloads.sample_instances(args.test_count, seed=11, fixed_side=side, **lam)
 
     def index_fn(insts):
         return lambda c0, k: workloads.ellipse_index_batch(
@@ -434,8 +435,10 @@ def surrogate_study(qla, torch, args):
     q = lambda a: {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)),
                    "max": float(np.max(a))}
     res = {
-        "workload": f"qla_surrogate_fno_{side}_{steps}_steps",
-        "grid": side, "qla_steps": steps, "train_instances": len(train_i),
+        "workload": f"qla_surrogate_fno_{side}_{steps}_steps_lambda_"
+                    f"{args.lam_range[0]:g}_{args.lam_range[1]:g}",
+        "grid": side, "qla_steps": steps, "wavelength_range": list(args.lam_range),
+        "train_instances": len(train_i),
         "test_instances": n_test,
         "network": dict(sur.shape, input="n - 2, q2, q3, q4", output="q2, q3, q4",
                         params=int(qla.qla_fno_param_count(sur.h)), dtype="bf16 storage, "
@@ -512,6 +515,8 @@ def main():
                     help="the learned-surrogate workload; prints its own JSON line")
     ap.add_argument("--side", type=int, default=512)
     ap.add_argument("--surrogate-steps", type=int, default=1024)
+    ap.add_argument("--lam-range", type=float, nargs=2, default=(8.0, 32.0),
+                    help="packet wavelength range (cells) of the surrogate's instances")
     ap.add_argument("--train-count", type=int, default=20000)
     ap.add_argument("--test-count", type=int, default=1000)
     ap.add_argument("--chunk", type=int, default=512)

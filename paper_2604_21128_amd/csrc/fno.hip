@@ -136,45 +136,10 @@ __global__ void mix_backward_weight_kernel(const float* __restrict__ dS,
 }
 
 // dz = dv * GELU'(z)
-template <typename D>
-__global__ void gelu_grad_kernel(const D* __restrict__ dv, const uint16_t* __restrict__ z,
+__global__ void gelu_grad_kernel(const float* __restrict__ dv, const uint16_t* __restrict__ z,
                                  uint16_t* __restrict__ dz, size_t n) {
-  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock) {
-    float d;
-    if constexpr (sizeof(D) == 4) {
-      d = dv[i];
-    } else {
-      d = bf16_to_f32(dv[i]);
-    }
-    dz[i] = f32_to_bf16(d * gelu_prime(bf16_to_f32(z[i])));
-  }
-}
-
-// db[c] += sum over b, p of d[b][c][p]  (grid: channels x chunks)
-template <typename D>
-__global__ void bias_grad_kernel(const D* __restrict__ d, float* __restrict__ db, int B, int Cn,
-                                 size_t P) {
-  __shared__ float red[kBlock];
-  const int c = blockIdx.x;
-  float acc = 0.f;
-  const size_t total = size_t(B) * P;
-  for (size_t e = blockIdx.y * size_t(kBlock) + threadIdx.x; e < total;
-       e += size_t(gridDim.y) * kBlock) {
-    const size_t b = e / P, p = e % P;
-    const size_t idx = (b * Cn + c) * P + p;
-    if constexpr (sizeof(D) == 4) {
-      acc += d[idx];
-    } else {
-      acc += bf16_to_f32(d[idx]);
-    }
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (static_cast<int>(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicAdd(&db[c], red[0]);
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock)
+    dz[i] = f32_to_bf16(dv[i] * gelu_prime(bf16_to_f32(z[i])));
 }
 
 // sums[2b] += sum (out - target)^2, sums[2b+1] += sum target^2 over sample b
@@ -300,11 +265,13 @@ struct qla_fno {
   // activations (batch Bmax)
   std::vector<uint16_t*> v, z;
   uint16_t *Zb = nullptr, *Sb = nullptr, *Ub = nullptr, *zq = nullptr, *h = nullptr,
-           *dout = nullptr, *dh = nullptr, *dzq = nullptr, *dz = nullptr, *dU = nullptr,
-           *dT = nullptr, *dZ = nullptr, *dv16 = nullptr;
+           *dout = nullptr, *dzq = nullptr, *dza = nullptr, *dzb = nullptr, *dU = nullptr,
+           *dT = nullptr, *dZ = nullptr;
   std::vector<float*> T;
-  float *spec = nullptr, *out = nullptr, *dS = nullptr, *dva = nullptr, *dvb = nullptr,
-        *loss = nullptr;
+  // spec and dv (FP32) only when W is not a multiple of the GEMM column tile, where
+  // the inverse x transform cannot be fused into the channel-mixing GEMM
+  float *spec = nullptr, *out = nullptr, *dS = nullptr, *dv = nullptr, *loss = nullptr;
+  bool fused = false;
   double* sums = nullptr;
   int64_t adam_t = 0;
   std::vector<void*> allocs;
@@ -428,9 +395,10 @@ GemmDesc pointwise(const uint16_t* wt, bool wt_t, int Mo, int K, const uint16_t*
   return g;
 }
 
-// Weight gradient dWt[mo][k] += sum_{b,p} d[b][mo][p] x[b][k][p] (split over pixels).
+// Weight gradient dWt[mo][k] += sum_{b,p} d[b][mo][p] x[b][k][p] (split over pixels);
+// the bias gradient db[mo] += sum_{b,p} d[b][mo][p] comes out of the same launch.
 GemmDesc weight_grad(const uint16_t* d, int Mo, const uint16_t* x, int K, int B, size_t P,
-                     float* dW) {
+                     float* dW, float* db) {
   GemmDesc g;
   g.A = d;
   g.sAb = static_cast<long long>(Mo) * P;
@@ -450,20 +418,44 @@ GemmDesc weight_grad(const uint16_t* d, int Mo, const uint16_t* x, int K, int B,
   g.batch = B;
   g.ksplit = static_cast<int>(std::max<size_t>(1, std::min<size_t>(256, P / 2048)));
   g.atomic = 1;
+  g.rowsum = db;
   return g;
-}
-
-qla_status bias_grad16(qla_fno* f, const uint16_t* d, int B, int Cn, float* db) {
-  hipLaunchKernelGGL(bias_grad_kernel<uint16_t>, dim3(Cn, 64), dim3(kBlock), 0, f->stream, d, db,
-                     B, Cn, size_t(f->P));
-  QLA_HIP(hipGetLastError());
-  return QLA_OK;
 }
 
 #define QLA_GEMM(desc) QLA_HIP(qla::fno::launch_gemm((desc), f->stream))
 
+// The inverse x transform of the spectral branch as a second contraction of the
+// channel-mixing GEMM g (whose columns are pixels): adds sum_j U[(b,o), y][j] IX[j][x].
+void add_inverse_x(const qla_fno* f, GemmDesc* g) {
+  g->A2 = f->Ub;
+  g->sA2b = static_cast<long long>(f->C) * f->H * 2 * f->m;
+  g->sA2m = static_cast<long long>(f->H) * 2 * f->m;
+  g->sA2y = 2 * f->m;
+  g->sA2k = 1;
+  g->B2 = f->IX;
+  g->sB2k = f->W;
+  g->sB2x = 1;
+  g->K2 = 2 * f->m;
+  g->row = f->W;
+}
+
+// The backward counterpart: adds sum_j dZ[(b,c), y][j] Fx[x][j].
+void add_forward_x_transposed(const qla_fno* f, GemmDesc* g) {
+  g->A2 = f->dZ;
+  g->sA2b = static_cast<long long>(f->C) * f->H * 2 * f->m;
+  g->sA2m = static_cast<long long>(f->H) * 2 * f->m;
+  g->sA2y = 2 * f->m;
+  g->sA2k = 1;
+  g->B2 = f->Fx;
+  g->sB2k = 1;
+  g->sB2x = 2 * f->m;
+  g->K2 = 2 * f->m;
+  g->row = f->W;
+}
+
 // Forward pass of batch B: input BF16 [B][Cin][P] -> f->out FP32 [B][Cout][P].
-qla_status forward(qla_fno* f, const uint16_t* in, int B) {
+// `training` keeps the pre-activations the backward pass needs.
+qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
   const size_t P = f->P;
   const int C = f->C, H = f->H, W = f->W, m = f->m;
   const long long modes_sz = 4LL * m * m;  // floats per (b, c) in T, S
@@ -540,8 +532,8 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B) {
       g.out_bf16 = 1;
       QLA_GEMM(g);
     }
-    // inverse x: spec[(b,o,y)][x]
-    {
+    if (!f->fused) {
+      // inverse x: spec[(b,o,y)][x]
       GemmDesc g;
       g.A = f->Ub;
       g.sAm = 2 * m;
@@ -561,13 +553,17 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B) {
     {
       GemmDesc g = pointwise(f->w16 + f->w16_W(l), false, C, C, vl, B, P);
       g.bias = f->p + f->o_b[l];
-      g.res = f->spec;
-      g.sRb = static_cast<long long>(C) * P;
-      g.sRm = static_cast<long long>(P);
-      g.sRn = 1;
+      if (f->fused) {
+        add_inverse_x(f, &g);
+      } else {
+        g.res = f->spec;
+        g.sRb = static_cast<long long>(C) * P;
+        g.sRm = static_cast<long long>(P);
+        g.sRn = 1;
+      }
       g.out_bf16 = 1;
       if (l + 1 < f->L) {
-        g.C = f->z[l];
+        g.C = training ? f->z[l] : nullptr;
         g.act = f->v[l + 1];
       } else {
         g.C = f->v[l + 1];
@@ -579,7 +575,7 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B) {
   {
     GemmDesc g = pointwise(f->w16 + f->w16_Q1(), false, f->C2, C, f->v[f->L], B, P);
     g.bias = f->p + f->o_bq1;
-    g.C = f->zq;
+    g.C = training ? f->zq : nullptr;
     g.out_bf16 = 1;
     g.act = f->h;
     QLA_GEMM(g);
@@ -593,8 +589,8 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B) {
   return QLA_OK;
 }
 
-// Loss and gradients of the batch (forward must have run on `in`). Gradients are
-// accumulated into f->g, which the caller zeroes.
+// Loss and gradients of the batch (forward(training) must have run on `in`).
+// Gradients are accumulated into f->g, which the caller zeroes.
 qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int B) {
   const size_t P = f->P;
   const int C = f->C, C2 = f->C2, H = f->H, W = f->W, m = f->m, L = f->L;
@@ -609,60 +605,32 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
   hipLaunchKernelGGL(loss_grad_kernel, dim3(256, B), dim3(kBlock), 0, f->stream, f->out, target,
                      f->sums, f->dout, B, per);
   QLA_HIP(hipGetLastError());
-  // projection 2
-  QLA_GEMM(weight_grad(f->dout, f->Cout, f->h, C2, B, P, f->g + f->o_Q2));
-  {
-    const qla_status st = bias_grad16(f, f->dout, B, f->Cout, f->g + f->o_bq2);
-    if (st != QLA_OK) return st;
-  }
+  // projection 2, then dzq = (Q2^T dout) GELU'(zq)
+  QLA_GEMM(weight_grad(f->dout, f->Cout, f->h, C2, B, P, f->g + f->o_Q2, f->g + f->o_bq2));
   {
     GemmDesc g = pointwise(f->w16 + f->w16_Q2(), true, C2, f->Cout, f->dout, B, P);
-    g.C = f->dh;
+    g.C = f->dzq;
+    g.out_bf16 = 1;
+    g.gz = f->zq;
+    QLA_GEMM(g);
+  }
+  // projection 1, then dz_{L-1} = Q1^T dzq (no activation after the last layer)
+  QLA_GEMM(weight_grad(f->dzq, C2, f->v[L], C, B, P, f->g + f->o_Q1, f->g + f->o_bq1));
+  uint16_t* dz = f->dza;       // gradient with respect to z_l
+  uint16_t* dz_prev = f->dzb;  // gradient with respect to z_{l-1} (or v_0)
+  {
+    GemmDesc g = pointwise(f->w16 + f->w16_Q1(), true, C, C2, f->dzq, B, P);
+    g.C = dz;
     g.out_bf16 = 1;
     QLA_GEMM(g);
   }
-  hipLaunchKernelGGL(gelu_grad_kernel<uint16_t>, dim3(grid_for(size_t(B) * C2 * P)), dim3(kBlock), 0,
-                     f->stream, f->dh, f->zq, f->dzq, size_t(B) * C2 * P);
-  QLA_HIP(hipGetLastError());
-  // projection 1
-  QLA_GEMM(weight_grad(f->dzq, C2, f->v[L], C, B, P, f->g + f->o_Q1));
-  {
-    const qla_status st = bias_grad16(f, f->dzq, B, C2, f->g + f->o_bq1);
-    if (st != QLA_OK) return st;
-  }
-  float* dv = f->dva;  // gradient with respect to v_{l+1}
-  float* dv_next = f->dvb;
-  {
-    GemmDesc g = pointwise(f->w16 + f->w16_Q1(), true, C, C2, f->dzq, B, P);
-    g.C = dv;
-    QLA_GEMM(g);
-  }
   for (int l = L - 1; l >= 0; --l) {
-    const size_t nact = size_t(B) * C * P;
-    if (l + 1 < L) {
-      hipLaunchKernelGGL(gelu_grad_kernel<float>, dim3(grid_for(nact)), dim3(kBlock), 0, f->stream,
-                         dv, f->z[l], f->dz, nact);
-    } else {
-      hipLaunchKernelGGL(cast_kernel, dim3(grid_for(nact)), dim3(kBlock), 0, f->stream, dv, f->dz,
-                         nact);
-    }
-    QLA_HIP(hipGetLastError());
     const uint16_t* vl = f->v[l];
-    // pointwise branch
-    QLA_GEMM(weight_grad(f->dz, C, vl, C, B, P, f->g + f->o_W[l]));
-    {
-      const qla_status st = bias_grad16(f, f->dz, B, C, f->g + f->o_b[l]);
-      if (st != QLA_OK) return st;
-    }
-    {
-      GemmDesc g = pointwise(f->w16 + f->w16_W(l), true, C, C, f->dz, B, P);
-      g.C = dv_next;
-      QLA_GEMM(g);
-    }
+    QLA_GEMM(weight_grad(dz, C, vl, C, B, P, f->g + f->o_W[l], f->g + f->o_b[l]));
     // spectral branch: dU = dz IX^T
     {
       GemmDesc g;
-      g.A = f->dz;
+      g.A = dz;
       g.sAm = W;
       g.sAk = 1;
       g.B = f->IX;
@@ -725,32 +693,48 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
       g.out_bf16 = 1;
       QLA_GEMM(g);
     }
-    // dv_l += dZ Fx^T
-    {
-      GemmDesc g;
-      g.A = f->dZ;
-      g.sAm = 2 * m;
-      g.sAk = 1;
-      g.B = f->Fx;
-      g.sBk = 1;
-      g.sBn = 2 * m;
-      g.C = dv_next;
-      g.sCm = W;
-      g.sCn = 1;
-      g.M = B * C * H;
-      g.N = W;
-      g.K = 2 * m;
-      g.beta = 1;
+    // dv_l = W_l^T dz + dZ Fx^T; dz_{l-1} = dv_l GELU'(z_{l-1}) (v_0 has no activation)
+    const uint16_t* gz = l > 0 ? f->z[l - 1] : nullptr;
+    GemmDesc g = pointwise(f->w16 + f->w16_W(l), true, C, C, dz, B, P);
+    if (f->fused) {
+      add_forward_x_transposed(f, &g);
+      g.C = dz_prev;
+      g.out_bf16 = 1;
+      g.gz = gz;
       QLA_GEMM(g);
+    } else {
+      g.C = f->dv;
+      QLA_GEMM(g);
+      GemmDesc h;
+      h.A = f->dZ;
+      h.sAm = 2 * m;
+      h.sAk = 1;
+      h.B = f->Fx;
+      h.sBk = 1;
+      h.sBn = 2 * m;
+      h.C = f->dv;
+      h.sCm = W;
+      h.sCn = 1;
+      h.M = B * C * H;
+      h.N = W;
+      h.K = 2 * m;
+      h.beta = 1;
+      QLA_GEMM(h);
+      const size_t nact = size_t(B) * C * P;
+      if (gz) {
+        hipLaunchKernelGGL(gelu_grad_kernel, dim3(grid_for(nact)), dim3(kBlock), 0, f->stream,
+                           f->dv, gz, dz_prev, nact);
+      } else {
+        hipLaunchKernelGGL(cast_kernel, dim3(grid_for(nact)), dim3(kBlock), 0, f->stream, f->dv,
+                           dz_prev, nact);
+      }
+      QLA_HIP(hipGetLastError());
     }
-    std::swap(dv, dv_next);
+    std::swap(dz, dz_prev);
   }
-  // lift
-  const size_t n0 = size_t(B) * C * P;
-  hipLaunchKernelGGL(cast_kernel, dim3(grid_for(n0)), dim3(kBlock), 0, f->stream, dv, f->dv16, n0);
-  QLA_HIP(hipGetLastError());
-  QLA_GEMM(weight_grad(f->dv16, C, in, f->Cin, B, P, f->g + f->o_Wp));
-  return bias_grad16(f, f->dv16, B, C, f->g + f->o_bp);
+  // lift (dz now holds the gradient with respect to v_0)
+  QLA_GEMM(weight_grad(dz, C, in, f->Cin, B, P, f->g + f->o_Wp, f->g + f->o_bp));
+  return QLA_OK;
 }
 
 qla_status check_batch(const qla_fno* f, int B) {
@@ -839,17 +823,18 @@ qla_status qla_fno_create(int height, int width, int in_channels, int out_channe
   A(&f->Zb, B * C * height * 2 * m);
   A(&f->Sb, B * C * 4 * m * m);
   A(&f->Ub, B * C * height * 2 * m);
-  A(&f->spec, B * C * P);
+  f->fused = width % 64 == 0;
+  if (!f->fused) {
+    A(&f->spec, B * C * P);
+    A(&f->dv, B * C * P);
+  }
   A(&f->zq, B * proj_channels * P);
   A(&f->h, B * proj_channels * P);
   A(&f->out, B * out_channels * P);
   A(&f->dout, B * out_channels * P);
-  A(&f->dh, B * proj_channels * P);
   A(&f->dzq, B * proj_channels * P);
-  A(&f->dva, B * C * P);
-  A(&f->dvb, B * C * P);
-  A(&f->dz, B * C * P);
-  A(&f->dv16, B * C * P);
+  A(&f->dza, B * C * P);
+  A(&f->dzb, B * C * P);
   A(&f->dU, B * C * height * 2 * m);
   A(&f->dS, B * C * 4 * m * m);
   A(&f->dT, B * C * 4 * m * m);
@@ -951,7 +936,7 @@ qla_status qla_fno_forward(qla_fno* f, const uint16_t* input, int batch, float* 
   qla_status st = check_batch(f, batch);
   if (st != QLA_OK) return st;
   DeviceGuard g(f->device);
-  st = forward(f, input, batch);
+  st = forward(f, input, batch, false);
   if (st != QLA_OK) return st;
   QLA_HIP(hipMemcpyAsync(output, f->out, size_t(batch) * f->Cout * f->P * sizeof(float),
                          hipMemcpyDeviceToDevice, f->stream));
@@ -965,7 +950,7 @@ qla_status qla_fno_loss_grad(qla_fno* f, const uint16_t* input, const uint16_t* 
   if (st != QLA_OK) return st;
   DeviceGuard g(f->device);
   QLA_HIP(hipMemsetAsync(f->g, 0, f->nparam * sizeof(float), f->stream));
-  st = forward(f, input, batch);
+  st = forward(f, input, batch, true);
   if (st == QLA_OK) st = backward(f, input, target, batch);
   if (st != QLA_OK) return st;
   if (loss_host) {

@@ -18,11 +18,18 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
   return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16);
 }
 
-// C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] (+ C if beta) (+ bias[m]) (+ res[b][m][n]);
-// if act, GELU of the stored value is also written (BF16) at act with C's strides;
-// atomic: atomicAdd alpha * product into an FP32 C (no bias, res, beta or act).
+// C[b][m][n] = alpha * (sum_k A[b][m][k] B[b][k][n] + seg2) (+ bias[m]) (+ res[b][m][n])
+//              (+ C if beta), then times GELU'(gz[b][m][n]) if gz;
+// stored at C (BF16 or FP32) if C is set; if act, GELU of the value is also stored
+// (BF16) at act with C's strides.
+// seg2 (K2 > 0): a second contraction whose operands depend on the row and column of
+// n = y * row + x in an H x row grid: sum_j A2[b][m][y][j] B2[j][x]. Needs
+// row % 64 == 0 and ksplit == 1.
+// atomic: atomicAdd alpha * product into an FP32 C (no bias, res, beta, gz or act).
+// rowsum: also atomically add each row sum of A over k into rowsum[m] (blocks of
+// the first column tile only; used for bias gradients).
 // Operands are BF16 bit patterns; element (b, m, k) of A is A[b*sAb + m*sAm + k*sAk].
-// The K range is split over ksplit blocks (only with atomic).
+// The K range of the first contraction is split over ksplit blocks (only with atomic).
 struct GemmDesc {
   const uint16_t* A = nullptr;
   long long sAb = 0, sAm = 0, sAk = 0;
@@ -37,6 +44,14 @@ struct GemmDesc {
   const float* res = nullptr;
   long long sRb = 0, sRm = 0, sRn = 0;
   uint16_t* act = nullptr;
+  const uint16_t* gz = nullptr;
+  float* rowsum = nullptr;
+  const uint16_t* A2 = nullptr;
+  long long sA2b = 0, sA2m = 0, sA2y = 0, sA2k = 0;
+  const uint16_t* B2 = nullptr;
+  long long sB2k = 0, sB2x = 0;
+  int K2 = 0, row = 0;
+  int vec = 0;  // set by launch_gemm: 16-byte row stores in the epilogue
 };
 
 hipError_t launch_gemm(const GemmDesc& g, hipStream_t stream);

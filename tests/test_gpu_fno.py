@@ -125,9 +125,12 @@ def gpu_forward(qla, net, u_bits, B):
     return out.cpu().numpy().astype(np.float64).reshape(B, net.s.cout, net.s.H, net.s.W)
 
 
+# "fused": rows a multiple of 64 cells, where the inverse x transform runs inside the
+# channel-mixing GEMM; the other two take the separate path.
 SPECS = {
     "small": fno.Spec(H=40, W=72, cin=4, cout=3, C=16, m=6, L=3, C2=24),
     "ragged": fno.Spec(H=33, W=70, cin=4, cout=3, C=10, m=5, L=2, C2=70),
+    "fused": fno.Spec(H=24, W=128, cin=4, cout=3, C=16, m=7, L=3, C2=40),
 }
 
 

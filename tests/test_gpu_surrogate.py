@@ -1,0 +1,69 @@
+"""What the trained surrogate gains over QLA alone (the surrogate workflow end to end).
+
+Instances of the batched scattering family on a 512^2 grid, 1024 QLA steps, with
+packet wavelengths 64-128 cells (inside the network's 12 kept modes): QLA generates
+the training pairs, the network trains on the GPU, and the held-out lattices go
+through the surrogate, the energy check (|E/E0 - 1| < 1e-2) and the QLA fallback.
+The untrained network must have every prediction rejected (so its path is slower
+than QLA alone), the trained one must have accepted predictions with small field
+error, and its path must beat QLA alone in lattices per second.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+SIDE, STEPS = 512, 1024
+
+
+@pytest.fixture(scope="module")
+def stream():
+    prev = torch.cuda.current_stream()
+    st = torch.cuda.Stream()
+    torch.cuda.set_stream(st)
+    yield st
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(prev)
+
+
+def _family(count, seed):
+    return workloads.sample_instances(count, seed=seed, fixed_side=SIDE, lam_min=64.0,
+                                      lam_max=128.0, steps=STEPS)
+
+
+def test_trained_surrogate_beats_plain_qla_at_the_acceptance_tolerance(stream):
+    from paper_2604_21128_amd import qla, surrogate as S
+    qla.load()
+    train_i, test_i = _family(4000, 20), _family(256, 21)
+
+    def index_fn(insts):
+        return lambda c0, k: workloads.ellipse_index_batch(
+            SIDE, SIDE, [i.ellipse for i in insts[c0:c0 + k]], device="cuda")
+
+    def packets(insts):
+        return [S.PacketSpec(i.packet.x0, i.packet.y0, i.packet.sigma, i.packet.lam)
+                for i in insts]
+    d = workloads.DELTA
+    train = S.qla_pairs(index_fn(train_i), len(train_i), packets(train_i), d, STEPS)
+    test = S.qla_pairs(index_fn(test_i), len(test_i), packets(test_i), d, STEPS, keep_f32=True)
+    with S.Surrogate(SIDE, SIDE, max_batch=16, seed=3) as sur:
+        _, e_untrained = S.predict_all(sur, test.inputs, 16)
+        assert not bool(S.accept(e_untrained, test.e0).any())
+        hist = S.train(sur, train.inputs, train.targets, 16, 6.0, 1e-3, log=print)
+        assert np.mean(hist["losses"][-50:]) < 0.5 * np.mean(hist["losses"][:50])
+        out, ok, t = S.run_with_fallback(sur, test.inputs, test.e0, index_fn(test_i),
+                                         packets(test_i), d, STEPS, 16)
+    ok = ok.cpu().numpy()
+    err = ((out - test.targets_f32).flatten(1).norm(dim=1)
+           / test.targets_f32.flatten(1).norm(dim=1)).cpu().numpy()
+    gain = test.qla_seconds / (t["surrogate_s"] + t["fallback_qla_s"])
+    print(f"accepted {ok.sum()}/{ok.size}, accepted field rel L2 median "
+          f"{np.median(err[ok]) if ok.any() else float('nan'):.3f}, gain {gain:.2f}x")
+    # rejected lattices were advanced by QLA itself: their fields are QLA's
+    assert float(err[~ok].max(initial=0.0)) < 1e-6
+    assert ok.mean() >= 0.3
+    assert np.median(err[ok]) < 0.12
+    assert gain > 1.0

@@ -156,15 +156,16 @@ class Instance:
 
 
 def sample_instances(count: int, seed: int = 0, n_min: int = 256, n_max: int = 1024,
-                     fixed_side: int | None = None) -> List[Instance]:
+                     fixed_side: int | None = None, lam_min: float = 8.0,
+                     lam_max: float = 32.0, steps: int | None = None) -> List[Instance]:
     """Independent scattering instances drawn with numpy's PCG64.
 
     Side N log-uniform in [n_min, n_max] (or `fixed_side`); semi-axes uniform in
     [0.05, 0.25] N; rotation uniform in [0, pi); n uniform in [1.5, 3]; dielectric in
     vacuum or vacuum bubble in dielectric with probability 1/2; wavelength uniform in
-    [8, 32] cells; envelope sigma = 0.75 wavelength; tanh edge 3 cells. The packet
-    moves in +x and starts 3 sigma left of the ellipse's rotated half-width. Each
-    instance runs 4 N steps.
+    [lam_min, lam_max] cells (default [8, 32]); envelope sigma = 0.75 wavelength; tanh
+    edge 3 cells. The packet moves in +x and starts 3 sigma left of the ellipse's
+    rotated half-width. Each instance runs 4 N steps unless `steps` is given.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
@@ -178,7 +179,7 @@ def sample_instances(count: int, seed: int = 0, n_min: int = 256, n_max: int = 1
         rot = rng.uniform(0.0, math.pi)
         n_d = rng.uniform(1.5, 3.0)
         bubble = rng.uniform() < 0.5
-        lam = rng.uniform(8.0, 32.0)
+        lam = rng.uniform(lam_min, lam_max)
         sigma = 0.75 * lam
         width = 3.0
         n_in, n_out = (1.0, n_d) if bubble else (n_d, 1.0)
@@ -189,7 +190,7 @@ def sample_instances(count: int, seed: int = 0, n_min: int = 256, n_max: int = 1
             n_side=side,
             ellipse=Ellipse(xc, yc, a, b, rot, n_in, n_out, width),
             packet=Packet(x0=x0, y0=yc, sigma=sigma, lam=lam),
-            steps=4 * side))
+            steps=4 * side if steps is None else int(steps)))
     return out
 
 
