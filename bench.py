@@ -435,6 +435,10 @@ def surrogate_study(qla, torch, args):
     q = lambda a: {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)),
                    "max": float(np.max(a))}
     res = {
+        "metric": "lattices/s through surrogate + energy check + QLA fallback",
+        "value": n_test / t_sur, "unit": "lattices/s", "higher_is_better": True,
+        "vs_plain_qla": t_plain / t_sur, "dtype": "bf16 (network), f32 (QLA)",
+        "data": "synthetic",
         "workload": f"qla_surrogate_fno_{side}_{steps}_steps_lambda_"
                     f"{args.lam_range[0]:g}_{args.lam_range[1]:g}",
         "grid": side, "qla_steps": steps, "wavelength_range": list(args.lam_range),
