@@ -158,3 +158,55 @@ def energy(q: np.ndarray) -> float:
 def physical_fields(q: np.ndarray, n: np.ndarray):
     """(Ez, Bx, By) from the E_z triple: Ez = q2 / n, Bx = q3, By = q4 (Eq. 3b3, c = 1)."""
     return q[2] / n, q[3].copy(), q[4].copy()
+
+
+def physical_fields_bz(q: np.ndarray, n: np.ndarray):
+    """(Ex, Ey, Bz) from the B_z triple: Ex = q0 / n, Ey = q1 / n, Bz = q5 (Eq. 3b3, c = 1)."""
+    return q[0] / n, q[1] / n, q[5].copy()
+
+
+def packet_bz(n: np.ndarray, x0: float, y0: float, sigma: float, lam: float, phi: float = 0.0,
+              amp: float = 1.0, planar: bool = True) -> np.ndarray:
+    """Initial state q[6, ny, nx] of a one-way B_z packet (the other polarisation).
+
+    Bz0 = amp exp(-r^2 / (2 sigma^2)) cos(2 pi s / lam), s the minimum-image displacement
+    along phi (r = s if planar, else the full distance), as for the E_z packet. A plane
+    wave travelling along k = (cos phi, sin phi) in a uniform medium has E = -(1/n) k x B,
+    so n E = (-sin phi, cos phi) Bz: q0 = -sin(phi) q5, q1 = cos(phi) q5, q5 = Bz0.
+    """
+    n = _index(n)
+    ny, nx = n.shape
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64),
+                       indexing="ij")
+    dx = x - x0
+    dy = y - y0
+    dx -= nx * np.floor(dx / nx + 0.5)
+    dy -= ny * np.floor(dy / ny + 0.5)
+    s = dx * np.cos(phi) + dy * np.sin(phi)
+    r2 = s * s if planar else dx * dx + dy * dy
+    bz = amp * np.exp(-r2 / (2.0 * sigma * sigma)) * np.cos(2.0 * np.pi * s / lam)
+    q = np.zeros((6, ny, nx), dtype=np.float64)
+    q[5] = bz
+    q[0] = -np.sin(phi) * bz
+    q[1] = np.cos(phi) * bz
+    return q
+
+
+def divergence(q: np.ndarray, n: np.ndarray, delta: float):
+    """Discrete divergences of the in-plane fields, centred differences, periodic.
+
+    div_B = d(Bx)/dx + d(By)/dy with (Bx, By) = (q3, q4) (the E_z triple), and
+    div_D = d(Dx)/dx + d(Dy)/dy with D = n^2 E = (n q0, n q1) (the B_z triple), where
+    d f/dx at x is (f[x + 1] - f[x - 1]) / (2 delta). Returns (div_B, div_D), each [ny, nx].
+    """
+    n = _index(n)
+
+    def ddx(f):
+        return (np.roll(f, -1, axis=1) - np.roll(f, 1, axis=1)) / (2.0 * delta)
+
+    def ddy(f):
+        return (np.roll(f, -1, axis=0) - np.roll(f, 1, axis=0)) / (2.0 * delta)
+
+    div_b = ddx(q[3]) + ddy(q[4])
+    div_d = ddx(n * q[0]) + ddy(n * q[1])
+    return div_b, div_d

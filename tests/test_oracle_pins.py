@@ -393,3 +393,91 @@ def test_normal_incidence_reflectance_is_fresnel():
     assert r0 < 0.05 * r_exact
     rp, tp = _fresnel_run(oracle.V_PAPER)
     assert rp + tp > 1.5
+
+
+# --------------------------------------------------------------------------------------
+# the B_z triple (q0, q1, q5) and the divergence diagnostic
+def test_vacuum_bz_packet_moves_one_way():
+    nx, ny, delta, steps = 512, 1, 0.25, 600
+    lam, sigma, x0 = 16.0, 12.0, 100.0
+    n = np.ones((ny, nx))
+    q = oracle.packet_bz(n, x0, 0.0, sigma, lam)
+    assert np.array_equal(q[1], q[5]) and not q[2:5].any()
+    e0 = oracle.energy(q)
+    oracle.advance(q, n, delta, steps)
+    assert not q[2:5].any()                                  # the triples never mix
+    e_x = (q ** 2).sum(axis=(0, 1))
+    assert _centroid(e_x) - x0 > 0.9 * steps * delta * 0.9
+    assert e_x[: int(x0)].sum() / e_x.sum() < 1e-6           # nothing moves towards -x
+    assert abs(e_x.sum() / e0 - 1) < 5e-12
+
+
+def _bz_slab_run(N, T, axis, spectral_ref=False):
+    # Bz packet in vacuum hitting a slab n = 2 along `axis` (1 = x, 0 = y)
+    delta = 1.0 / N
+    s = np.arange(N) * delta
+    prof = _slab_phys(s, 0.45, 0.85, 2.0, 0.03)
+    n = prof[None, :].copy() if axis == 1 else prof[:, None].copy()
+    bz = _gauss_packet_phys(s, 0.25, 0.06, 0.15)
+    q = np.zeros((6,) + n.shape)
+    if axis == 1:
+        q[5, 0] = bz
+        q[1, 0] = bz              # n Ey = Bz: one way along +x
+    else:
+        q[5, :, 0] = bz
+        q[0, :, 0] = -bz          # n Ex = -Bz: one way along +y
+    if spectral_ref:
+        ly, lx = (1.0 / N, 1.0) if axis == 1 else (1.0, 1.0 / N)
+        return spectral.solve(q, n, lx, ly, T)
+    oracle.advance(q, n, delta, int(round(T / delta ** 2)), oracle.V_SKEW_HALF)
+    return q
+
+
+@pytest.mark.parametrize("axis", [1, 0])
+def test_skew_half_bz_triple_converges_at_second_order_through_a_slab(axis):
+    # Eqs. (2d1), (2d2), (2d6): the B_z triple's gradient terms sit on q5; the same
+    # half-angle rotations supply them (reading of the potentials).
+    T, Nref = 0.25, 2048
+    ref = _bz_slab_run(Nref, T, axis, spectral_ref=True)
+    errs = []
+    for N in (64, 128, 256):
+        q = _bz_slab_run(N, T, axis)
+        r = ref[:, :, :: Nref // N] if axis == 1 else ref[:, :: Nref // N, :]
+        errs.append(np.linalg.norm(q[[0, 1, 5]] - r[[0, 1, 5]]) / np.linalg.norm(r[[0, 1, 5]]))
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert ratios[-1] > 3.6 and ratios[-2] > 2.5, (errs, ratios)
+    assert errs[-1] < 0.15
+
+
+def test_divergence_of_a_discrete_curl_vanishes():
+    # B = (D_y psi, -D_x psi) with the same centred differences: div B = 0 exactly
+    # (the two differences commute), up to rounding
+    rng = np.random.default_rng(5)
+    ny, nx, delta = 24, 40, 0.25
+    psi = rng.normal(size=(ny, nx))
+    n = rng.uniform(1.0, 3.0, size=(ny, nx))
+    ddx = lambda f: (np.roll(f, -1, 1) - np.roll(f, 1, 1)) / (2 * delta)
+    ddy = lambda f: (np.roll(f, -1, 0) - np.roll(f, 1, 0)) / (2 * delta)
+    q = np.zeros((6, ny, nx))
+    q[3], q[4] = ddy(psi), -ddx(psi)
+    q[0], q[1] = ddy(psi) / n, -ddx(psi) / n          # D = n q = curl psi
+    div_b, div_d = oracle.divergence(q, n, delta)
+    scale = np.abs(ddx(q[3])).max()
+    assert np.abs(div_b).max() < 1e-13 * scale and np.abs(div_d).max() < 1e-13 * scale
+
+
+def test_divergence_of_a_single_mode():
+    # centred difference of cos(k x): -sin(k delta) / delta * sin(k x), k = 2 pi m / nx
+    ny, nx, delta, m = 8, 32, 0.5, 3
+    x = np.arange(nx) * delta
+    k = 2 * np.pi * m / (nx * delta)
+    q = np.zeros((6, ny, nx))
+    q[3] = np.cos(k * x)[None, :]
+    q[1] = 2.0 * np.sin(2 * np.pi * np.arange(ny) / ny)[:, None]     # D_y = n q1 with n = 1
+    n = np.ones((ny, nx))
+    div_b, div_d = oracle.divergence(q, n, delta)
+    np.testing.assert_allclose(div_b, (-np.sin(k * delta) / delta * np.sin(k * x))[None, :]
+                               * np.ones((ny, 1)), atol=1e-13)
+    ky = 2 * np.pi / (ny * delta)
+    want = 2.0 * np.sin(ky * delta) / delta * np.cos(2 * np.pi * np.arange(ny) / ny)
+    np.testing.assert_allclose(div_d, want[:, None] * np.ones((1, nx)), atol=1e-13)
