@@ -10,12 +10,13 @@
  * Eq. (2e5), and the refractive-index potentials V_x, V_y (Eqs. 2e11-2e13).
  *
  * State. The qubit vector is Q = (n Ex, n Ey, n Ez, Bx, By, Bz) = (q0..q5)
- * (Eq. 3b3, c = 1, t -> ct). This library evolves the E_z polarisation: the
- * triple (q2, q3, q4) = (n Ez, Bx, By), which the operators of Eq. (2e14) never
- * couple to (q0, q1, q5); those stay zero for an E_z packet. Every field array
- * that crosses this ABI is a set of 3 planes ordered (q2, q3, q4) - or
- * (Ez, Bx, By) for physical readout - each plane row-major [y][x] with x
- * fastest, nx * ny doubles, planes contiguous one after another.
+ * (Eq. 3b3, c = 1, t -> ct). The operators of Eq. (2e14) never couple the
+ * triple (q2, q3, q4) = (n Ez, Bx, By) to (q0, q1, q5) = (n Ex, n Ey, Bz); a context
+ * evolves one of them (the E_z triple unless created with qla_create_triple). Every
+ * field array that crosses this ABI is a set of 3 planes ordered (q2, q3, q4) - or
+ * (Ez, Bx, By) for physical readout - for the E_z triple, (q0, q1, q5) - or
+ * (Ex, Ey, Bz) - for the B_z triple, each plane row-major [y][x] with x fastest,
+ * nx * ny doubles, planes contiguous one after another.
  *
  * Lattice. nx * ny sites, periodic in x and y, spacing delta (physical units);
  * one step advances time by delta^2 (Section IV, "diffusion ordering"), so light
@@ -80,13 +81,23 @@ typedef enum {
     QLA_V_NONE = 2
 } qla_potential;
 
+/* Which polarisation a context evolves. The operators of Eq. (2e14) never couple the
+ * triple (q2, q3, q4) = (n Ez, Bx, By) to (q0, q1, q5) = (n Ex, n Ey, Bz). */
+typedef enum {
+    QLA_TRIPLE_EZ = 0,  /* (q2, q3, q4): field arrays are planes (q2, q3, q4) */
+    QLA_TRIPLE_BZ = 1   /* (q0, q1, q5): field arrays are planes (q0, q1, q5) */
+} qla_triple;
+
 /* Gaussian-envelope plane-wave packet in E_z (Section V, initial conditions):
  * Ez0 = amp * exp(-r^2 / (2 sigma^2)) * cos(2 pi s / lambda), where s is the
  * minimum-image displacement from (x0, y0) (cells) projected on the direction of
  * travel phi (radians, 0 = +x) and r = s if planar != 0 (uniform across the
  * direction of travel, the paper's 1D packet), else the full minimum-image
  * distance. The paired magnetic field is that of a wave travelling one way along
- * phi in a uniform medium: q2 = n Ez0, q3 = q2 sin(phi), q4 = -q2 cos(phi). */
+ * phi in a uniform medium: q2 = n Ez0, q3 = q2 sin(phi), q4 = -q2 cos(phi).
+ * In a B_z-triple context the same envelope is the B_z packet of the other
+ * polarisation: q5 = Bz0 and, from E = -(1/n) k x B, (q0, q1) = n (Ex, Ey) =
+ * Bz0 (-sin(phi), cos(phi)). */
 typedef struct {
     double x0, y0, sigma, lambda, phi, amp;
     int planar;
@@ -100,6 +111,15 @@ typedef struct {
  * planes and small scratch; the state starts at zero with no index set. */
 qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
                       qla_potential potential, void *hip_stream, qla_ctx **out);
+
+/* As qla_create for either triple (qla_create is the E_z triple). The B_z triple is
+ * stepped with the same operators of Eq. (2e14) acting on (q0, q1, q5): C_x (Eq. 2e3)
+ * on (q1, q5), C_y (Eq. 2e8) on (q0, q5), streaming S_14, S_03 and S_25 (Eq. 2e5).
+ * Its field arrays are planes (q0, q1, q5), or (Ex, Ey, Bz) = (q0 / n, q1 / n, q5) for
+ * physical readout. QLA_V_PAPER is implemented for the E_z triple only (QLA_EINVAL). */
+qla_status qla_create_triple(int nx, int ny, double delta, qla_precision precision,
+                             qla_potential potential, qla_triple triple, void *hip_stream,
+                             qla_ctx **out);
 
 /* Set n(x, y) from a host array of ny rows of nx doubles, row stride ld >= nx
  * (elements). Computes the coefficients of Eqs. (2e4) and (2e13) in FP64 on the
@@ -115,26 +135,39 @@ qla_status qla_set_index_device(qla_ctx *ctx, const double *n_device, size_t ld)
  * (QLA_ESTATE if no index is set). Resets the step counter. Asynchronous. */
 qla_status qla_init_packet(qla_ctx *ctx, const qla_packet *packet);
 
-/* Replace the amplitudes by 3 host planes (q2, q3, q4) in FP64 (rounded to FP32
- * in QLA_F32 mode): checkpoint restore. Resets the step counter to `step`. */
+/* Replace the amplitudes by 3 host planes (q2, q3, q4), or (q0, q1, q5) for the B_z
+ * triple, in FP64 (rounded to FP32 in QLA_F32 mode): checkpoint restore. Resets the
+ * step counter to `step`. */
 qla_status qla_set_fields(qla_ctx *ctx, const double *q_host, int64_t step);
 
 /* Advance k >= 0 full steps of Eq. (2e14). Asynchronous. */
 qla_status qla_advance(qla_ctx *ctx, int64_t k);
 
 /* Copy the state to 3 host planes in FP64: (q2, q3, q4) if physical == 0,
- * else (Ez, Bx, By) = (q2 / n, q3, q4). Synchronises. */
+ * else (Ez, Bx, By) = (q2 / n, q3, q4); for the B_z triple (q0, q1, q5), else
+ * (Ex, Ey, Bz) = (q0 / n, q1 / n, q5). Synchronises. */
 qla_status qla_get_fields(qla_ctx *ctx, double *out_host, int physical);
 
 /* As qla_get_fields into 3 device planes (3 * nx * ny doubles). Asynchronous. */
 qla_status qla_get_fields_device(qla_ctx *ctx, double *out_device, int physical);
 
-/* Energy of Eq. (A13): the sum over sites of q2^2 + q3^2 + q4^2, accumulated in
- * FP64 in a fixed order (bitwise reproducible). Synchronises. */
+/* Energy of Eq. (A13): the sum over sites of q2^2 + q3^2 + q4^2 (q0^2 + q1^2 + q5^2
+ * for the B_z triple), accumulated in FP64 in a fixed order (bitwise reproducible).
+ * Synchronises. */
 qla_status qla_energy(qla_ctx *ctx, double *energy);
 
 /* As qla_energy, written to one device double. Asynchronous. */
 qla_status qla_energy_device(qla_ctx *ctx, double *energy_device);
+
+/* Divergence diagnostic (Section V: the paper monitors div D and div B). The in-plane
+ * field F is B = (q3, q4) for the E_z triple and D = n^2 E = n (q0, q1) for the B_z
+ * triple (whose other divergence is zero in 2D); with centred periodic differences
+ * dF/dx = (F[x+1] - F[x-1]) / (2 delta), div = dFx/dx + dFy/dy at every site. Writes
+ * through the non-NULL pointers: l2 = sqrt(sum div^2), max_abs = max |div| and
+ * scale = sqrt(sum (dFx/dx)^2 + (dFy/dy)^2), so l2 / scale is a relative divergence
+ * (0 for a divergence-free field, order 1 for a generic one). FP64, fixed order.
+ * Synchronises. QLA_ESTATE for the B_z triple without an index. */
+qla_status qla_divergence(qla_ctx *ctx, double *l2, double *max_abs, double *scale);
 
 /* Per-site FP64 coefficients the step uses, copied to host arrays of nx * ny
  * (any pointer may be NULL): theta = delta / (4 n) (Eq. 2e4) and

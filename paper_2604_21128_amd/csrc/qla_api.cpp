@@ -54,9 +54,16 @@ void release(qla_ctx* c) {
   if (c->n32) (void)hipFree(c->n32);
   if (c->staging) (void)hipFree(c->staging);
   if (c->partials) (void)hipFree(c->partials);
+  if (c->diag) (void)hipFree(c->diag);
   if (c->energy_dev) (void)hipFree(c->energy_dev);
   if (c->stats) (void)hipFree(c->stats);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+// Physical readout: E = q / n for the E components ((q2) or (q0, q1)); B as stored.
+int divide_mask(const qla_ctx* c, int physical) {
+  if (!physical) return 0;
+  return c->triple == 0 ? 1 : 3;
 }
 
 qla_status alloc(void** p, size_t bytes, const char* what) {
@@ -125,6 +132,7 @@ qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fuse
   L.fp32 = c->fp32;
   L.vmode = c->vmode;
   L.angle_class = c->angle_class;
+  L.triple = c->triple;
   // passes of `fused` steps, then single steps for the remainder
   int64_t done = 0;
   while (done < k) {
@@ -153,6 +161,7 @@ qla::StepLaunch step_launch_for(const qla_ctx* c, int rows, int prefetch, int fu
   L.fp32 = c->fp32;
   L.vmode = c->vmode;
   L.angle_class = c->angle_class;
+  L.triple = c->triple;
   const int from = c->cur ^ dir;
   for (int j = 0; j < 3; ++j) {
     L.in[j] = c->q[from][j];
@@ -182,6 +191,12 @@ const char* qla_last_error(void) { return g_last_error.c_str(); }
 
 qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
                       qla_potential potential, void* hip_stream, qla_ctx** out) {
+  return qla_create_triple(nx, ny, delta, precision, potential, QLA_TRIPLE_EZ, hip_stream, out);
+}
+
+qla_status qla_create_triple(int nx, int ny, double delta, qla_precision precision,
+                             qla_potential potential, qla_triple triple, void* hip_stream,
+                             qla_ctx** out) {
   if (!out) return fail(QLA_EINVAL, "out is NULL");
   *out = nullptr;
   if (nx < 8 || ny < 8) return fail(QLA_EINVAL, "nx and ny must be >= 8");
@@ -194,6 +209,9 @@ qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
   if (precision != QLA_F64 && precision != QLA_F32) return fail(QLA_EINVAL, "bad precision");
   if (potential != QLA_V_SKEW_HALF && potential != QLA_V_PAPER && potential != QLA_V_NONE)
     return fail(QLA_EINVAL, "bad potential mode");
+  if (triple != QLA_TRIPLE_EZ && triple != QLA_TRIPLE_BZ) return fail(QLA_EINVAL, "bad triple");
+  if (triple == QLA_TRIPLE_BZ && potential == QLA_V_PAPER)
+    return fail(QLA_EINVAL, "the printed potentials are implemented for the E_z triple only");
   qla_ctx* c = new (std::nothrow) qla_ctx;
   if (!c) return fail(QLA_ENOMEM, "host allocation");
   c->nx = nx;
@@ -201,6 +219,7 @@ qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
   c->delta = delta;
   c->fp32 = precision == QLA_F32;
   c->vmode = static_cast<int>(potential);
+  c->triple = static_cast<int>(triple);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
     delete c;
@@ -226,8 +245,9 @@ qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
   if (st == QLA_OK)
     st = alloc(reinterpret_cast<void**>(&c->staging), 3 * N * sizeof(double), "staging");
   if (st == QLA_OK)
-    st = alloc(reinterpret_cast<void**>(&c->partials), qla::kEnergyPartials * sizeof(double),
-               "partials");
+    st = alloc(reinterpret_cast<void**>(&c->partials),
+               3 * qla::kEnergyPartials * sizeof(double), "partials");
+  if (st == QLA_OK) st = alloc(reinterpret_cast<void**>(&c->diag), 3 * sizeof(double), "diag");
   if (st == QLA_OK) st = alloc(reinterpret_cast<void**>(&c->energy_dev), sizeof(double), "energy");
   if (st == QLA_OK)
     st = alloc(reinterpret_cast<void**>(&c->stats), 4 * sizeof(unsigned long long), "stats");
@@ -287,7 +307,7 @@ qla_status qla_init_packet(qla_ctx* c, const qla_packet* p) {
       !std::isfinite(p->lambda))
     return fail(QLA_EINVAL, "packet: sigma and lambda must be > 0 and all fields finite");
   DeviceGuard g(c->device);
-  qla::PacketArgs a{p->x0, p->y0, p->sigma, p->lambda, p->phi, p->amp, p->planar};
+  qla::PacketArgs a{p->x0, p->y0, p->sigma, p->lambda, p->phi, p->amp, p->planar, c->triple};
   QLA_HIP(qla::launch_packet(c->n64, c->nx, c->ny, a, c->fp32, c->q[c->cur][0], c->q[c->cur][1],
                              c->q[c->cur][2], c->stream));
   c->steps = 0;
@@ -301,8 +321,8 @@ qla_status qla_set_fields(qla_ctx* c, const double* q_host, int64_t step) {
   const size_t N = c->count();
   QLA_HIP(hipMemcpyAsync(c->staging, q_host, 3 * N * sizeof(double), hipMemcpyHostToDevice,
                          c->stream));
-  QLA_HIP(qla::launch_from_f64(c->staging, N, c->fp32, c->q[c->cur][0], c->q[c->cur][1],
-                               c->q[c->cur][2], c->stream));
+  QLA_HIP(qla::launch_from_f64(c->staging, N, c->fp32, c->q[c->cur][c->plane(0)],
+                               c->q[c->cur][c->plane(1)], c->q[c->cur][c->plane(2)], c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
   c->steps = step;
   return QLA_OK;
@@ -401,8 +421,9 @@ qla_status qla_get_fields_device(qla_ctx* c, double* out, int physical) {
   if (!c || !out) return fail(QLA_EINVAL, "NULL argument");
   if (physical && !c->have_index) return fail(QLA_ESTATE, "physical readout needs the index");
   DeviceGuard g(c->device);
-  QLA_HIP(qla::launch_readout(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->n64,
-                              c->count(), c->fp32, physical, out, c->stream));
+  QLA_HIP(qla::launch_readout(c->q[c->cur][c->plane(0)], c->q[c->cur][c->plane(1)],
+                              c->q[c->cur][c->plane(2)], c->n64,
+                              c->count(), c->fp32, divide_mask(c, physical), out, c->stream));
   return QLA_OK;
 }
 
@@ -410,8 +431,9 @@ qla_status qla_get_fields(qla_ctx* c, double* out_host, int physical) {
   if (!c || !out_host) return fail(QLA_EINVAL, "NULL argument");
   if (physical && !c->have_index) return fail(QLA_ESTATE, "physical readout needs the index");
   DeviceGuard g(c->device);
-  QLA_HIP(qla::launch_readout(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->n64,
-                              c->count(), c->fp32, physical, c->staging, c->stream));
+  QLA_HIP(qla::launch_readout(c->q[c->cur][c->plane(0)], c->q[c->cur][c->plane(1)],
+                              c->q[c->cur][c->plane(2)], c->n64,
+                              c->count(), c->fp32, divide_mask(c, physical), c->staging, c->stream));
   QLA_HIP(hipMemcpyAsync(out_host, c->staging, 3 * c->count() * sizeof(double),
                          hipMemcpyDeviceToHost, c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
@@ -434,6 +456,25 @@ qla_status qla_energy(qla_ctx* c, double* energy) {
   QLA_HIP(hipMemcpyAsync(energy, c->energy_dev, sizeof(double), hipMemcpyDeviceToHost,
                          c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
+  return QLA_OK;
+}
+
+qla_status qla_divergence(qla_ctx* c, double* l2, double* max_abs, double* scale) {
+  if (!c) return fail(QLA_EINVAL, "NULL context");
+  if (c->triple == 1 && !c->have_index)
+    return fail(QLA_ESTATE, "the B_z triple's divergence (of D = n^2 E) needs the index");
+  DeviceGuard g(c->device);
+  // stored planes (shared, y partner, x partner) = (q2, q3, q4) or (q5, q0, q1): the
+  // in-plane field is (stored 1, stored 2), i.e. (Bx, By) or (n Ex, n Ey)
+  QLA_HIP(qla::launch_divergence(c->q[c->cur][1], c->q[c->cur][2], c->n64, c->nx, c->ny,
+                                 c->delta, c->fp32, c->triple == 1, c->partials, c->diag,
+                                 c->stream));
+  double h[3];
+  QLA_HIP(hipMemcpyAsync(h, c->diag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  if (l2) *l2 = std::sqrt(h[0]);
+  if (max_abs) *max_abs = h[1];
+  if (scale) *scale = std::sqrt(h[2]);
   return QLA_OK;
 }
 

@@ -144,11 +144,19 @@ __global__ __launch_bounds__(kBlock) void packet_kernel(const double* __restrict
     dy -= ny * floor(dy / ny + 0.5);
     const double s = dx * kx + dy * ky;
     const double r2 = p.planar ? s * s : dx * dx + dy * dy;
-    const double ez = p.amp * exp(-r2 / (2.0 * p.sigma * p.sigma)) * cos(two_pi * s / p.lambda);
-    const double a = n64[i] * ez;
-    q2[i] = static_cast<T>(a);
-    q3[i] = static_cast<T>(a * ky);
-    q4[i] = static_cast<T>(-a * kx);
+    const double f = p.amp * exp(-r2 / (2.0 * p.sigma * p.sigma)) * cos(two_pi * s / p.lambda);
+    if (p.triple == 0) {
+      // E_z packet: q2 = n Ez, (q3, q4) = q2 (sin phi, -cos phi)
+      const double a = n64[i] * f;
+      q2[i] = static_cast<T>(a);
+      q3[i] = static_cast<T>(a * ky);
+      q4[i] = static_cast<T>(-a * kx);
+    } else {
+      // B_z packet into (q5, q0, q1): q5 = Bz, (q0, q1) = n E = Bz (-sin phi, cos phi)
+      q2[i] = static_cast<T>(f);
+      q3[i] = static_cast<T>(-f * ky);
+      q4[i] = static_cast<T>(f * kx);
+    }
   }
 }
 
@@ -192,14 +200,85 @@ __global__ __launch_bounds__(kBlock) void readout_kernel(const T* __restrict__ q
                                                          const T* __restrict__ q3,
                                                          const T* __restrict__ q4,
                                                          const double* __restrict__ n64,
-                                                         size_t count, int physical,
+                                                         size_t count, int divide_by_n,
                                                          double* __restrict__ out) {
   for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
        i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const double a = q2[i];
-    out[i] = physical ? a / n64[i] : a;
-    out[count + i] = q3[i];
-    out[2 * count + i] = q4[i];
+    const double a = q2[i], b = q3[i], c = q4[i];
+    out[i] = (divide_by_n & 1) ? a / n64[i] : a;
+    out[count + i] = (divide_by_n & 2) ? b / n64[i] : b;
+    out[2 * count + i] = (divide_by_n & 4) ? c / n64[i] : c;
+  }
+}
+
+// Per-block partial sums of div^2 and of the squared axis derivatives, and partial
+// maxima of |div|, for F = w (fx, fy): div = (Fx[x+1] - Fx[x-1] + Fy[y+1] - Fy[y-1]) / (2 delta)
+// with Fx = w fx, Fy = w fy (periodic). One partial per block, fixed order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void divergence_partial_kernel(
+    const T* __restrict__ fx, const T* __restrict__ fy, const double* __restrict__ n64, int nx,
+    int ny, double inv_2d, int weight_n, double* __restrict__ partials) {
+  __shared__ double l0[kBlock], l1[kBlock], l2[kBlock];
+  const size_t count = static_cast<size_t>(nx) * ny;
+  double s_div = 0.0, s_scale = 0.0, m_div = 0.0;
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
+    const size_t xl = static_cast<size_t>(y) * nx + (x == 0 ? nx - 1 : x - 1);
+    const size_t xr = static_cast<size_t>(y) * nx + (x == nx - 1 ? 0 : x + 1);
+    const size_t yd = static_cast<size_t>(y == 0 ? ny - 1 : y - 1) * nx + x;
+    const size_t yu = static_cast<size_t>(y == ny - 1 ? 0 : y + 1) * nx + x;
+    double fxr = fx[xr], fxl = fx[xl], fyu = fy[yu], fyd = fy[yd];
+    if (weight_n) {
+      fxr *= n64[xr];
+      fxl *= n64[xl];
+      fyu *= n64[yu];
+      fyd *= n64[yd];
+    }
+    const double dfx = (fxr - fxl) * inv_2d, dfy = (fyu - fyd) * inv_2d;
+    const double div = dfx + dfy;
+    s_div = fma(div, div, s_div);
+    s_scale = fma(dfx, dfx, fma(dfy, dfy, s_scale));
+    m_div = fmax(m_div, fabs(div));
+  }
+  l0[threadIdx.x] = s_div;
+  l1[threadIdx.x] = m_div;
+  l2[threadIdx.x] = s_scale;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) {
+      l0[threadIdx.x] += l0[threadIdx.x + s];
+      l1[threadIdx.x] = fmax(l1[threadIdx.x], l1[threadIdx.x + s]);
+      l2[threadIdx.x] += l2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = l0[0];
+    partials[kEnergyPartials + blockIdx.x] = l1[0];
+    partials[2 * kEnergyPartials + blockIdx.x] = l2[0];
+  }
+}
+
+__global__ __launch_bounds__(kEnergyPartials) void divergence_final_kernel(
+    const double* partials, double* out) {
+  __shared__ double l0[kEnergyPartials], l1[kEnergyPartials], l2[kEnergyPartials];
+  l0[threadIdx.x] = partials[threadIdx.x];
+  l1[threadIdx.x] = partials[kEnergyPartials + threadIdx.x];
+  l2[threadIdx.x] = partials[2 * kEnergyPartials + threadIdx.x];
+  __syncthreads();
+  for (int s = kEnergyPartials / 2; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) {
+      l0[threadIdx.x] += l0[threadIdx.x + s];
+      l1[threadIdx.x] = fmax(l1[threadIdx.x], l1[threadIdx.x + s]);
+      l2[threadIdx.x] += l2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = l0[0];
+    out[1] = l1[0];
+    out[2] = l2[0];
   }
 }
 
@@ -276,17 +355,37 @@ hipError_t launch_energy(const void* q2, const void* q3, const void* q4, size_t 
 }
 
 hipError_t launch_readout(const void* q2, const void* q3, const void* q4, const double* n64,
-                          size_t count, bool fp32, int physical, double* out,
+                          size_t count, bool fp32, int divide_by_n, double* out,
                           hipStream_t stream) {
   if (fp32) {
     hipLaunchKernelGGL(readout_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
                        static_cast<const float*>(q2), static_cast<const float*>(q3),
-                       static_cast<const float*>(q4), n64, count, physical, out);
+                       static_cast<const float*>(q4), n64, count, divide_by_n, out);
   } else {
     hipLaunchKernelGGL(readout_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
                        static_cast<const double*>(q2), static_cast<const double*>(q3),
-                       static_cast<const double*>(q4), n64, count, physical, out);
+                       static_cast<const double*>(q4), n64, count, divide_by_n, out);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_divergence(const void* fx, const void* fy, const double* n64, int nx, int ny,
+                             double delta, bool fp32, bool weight_n, double* partials,
+                             double* out, hipStream_t stream) {
+  const double inv_2d = 0.5 / delta;
+  if (fp32) {
+    hipLaunchKernelGGL(divergence_partial_kernel<float>, dim3(kEnergyPartials), dim3(kBlock), 0,
+                       stream, static_cast<const float*>(fx), static_cast<const float*>(fy), n64,
+                       nx, ny, inv_2d, weight_n ? 1 : 0, partials);
+  } else {
+    hipLaunchKernelGGL(divergence_partial_kernel<double>, dim3(kEnergyPartials), dim3(kBlock), 0,
+                       stream, static_cast<const double*>(fx), static_cast<const double*>(fy),
+                       n64, nx, ny, inv_2d, weight_n ? 1 : 0, partials);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(divergence_final_kernel, dim3(1), dim3(kEnergyPartials), 0, stream, partials,
+                     out);
   return hipGetLastError();
 }
 

@@ -21,6 +21,9 @@ struct qla_ctx {
   double delta = 0.0;
   bool fp32 = false;
   int vmode = 0;
+  // 0: the E_z triple, planes (q2, q3, q4); 1: the B_z triple, stored as (q5, q0, q1) so
+  // the step treats both alike (shared component first, then its y and x partners)
+  int triple = 0;
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -30,7 +33,8 @@ struct qla_ctx {
   double* n64 = nullptr;
   float* n32 = nullptr;
   double* staging = nullptr;  // 3 * nx * ny doubles
-  double* partials = nullptr;
+  double* partials = nullptr;  // 3 * kEnergyPartials doubles (energy, divergence)
+  double* diag = nullptr;      // 3 doubles: divergence results
   double* energy_dev = nullptr;
   unsigned long long* stats = nullptr;
   int64_t steps = 0;
@@ -41,6 +45,8 @@ struct qla_ctx {
   int fused = qla::kDefaultFused;
   size_t count() const { return static_cast<size_t>(nx) * static_cast<size_t>(ny); }
   size_t elem() const { return fp32 ? sizeof(float) : sizeof(double); }
+  // The stored plane holding component j of the ABI order ((q2, q3, q4) or (q0, q1, q5)).
+  int plane(int j) const { return triple == 0 ? j : (j + 1) % 3; }
 };
 
 namespace qla {

@@ -24,6 +24,7 @@ struct StepLaunch {
   bool fp32;
   int vmode;
   int angle_class;
+  int triple;  // 0: E_z triple (q2, q3, q4); 1: B_z triple (q5, q0, q1), collision angles negated
 };
 hipError_t launch_step(const StepLaunch& L, hipStream_t stream);
 
@@ -63,6 +64,7 @@ hipError_t launch_coefficients(const double* n64, int nx, int ny, double delta, 
 struct PacketArgs {
   double x0, y0, sigma, lambda, phi, amp;
   int planar;
+  int triple;  // 0: E_z packet into (q2, q3, q4); 1: B_z packet into (q5, q0, q1)
 };
 hipError_t launch_packet(const double* n64, int nx, int ny, const PacketArgs& p, bool fp32,
                          void* q2, void* q3, void* q4, hipStream_t stream);
@@ -72,9 +74,19 @@ constexpr int kEnergyPartials = 1024;
 hipError_t launch_energy(const void* q2, const void* q3, const void* q4, size_t count, bool fp32,
                          double* partials, double* out, hipStream_t stream);
 
-// Three planes to FP64 (q2, q3, q4), or (q2 / n, q3, q4) when physical.
+// Three planes to FP64, in the order given; plane j is divided by n where bit j of
+// divide_by_n is set (physical readout).
 hipError_t launch_readout(const void* q2, const void* q3, const void* q4, const double* n64,
-                          size_t count, bool fp32, int physical, double* out, hipStream_t stream);
+                          size_t count, bool fp32, int divide_by_n, double* out,
+                          hipStream_t stream);
+
+// Discrete divergence of the in-plane field F = w (fx, fy) with w = 1 (E_z triple:
+// B = (q3, q4)) or w = n (B_z triple: D = n (q0, q1)), centred differences, periodic:
+// out[0] = sum of div^2, out[1] = max |div|, out[2] = sum of (dFx/dx)^2 + (dFy/dy)^2,
+// all FP64 in a fixed order. partials: 3 * kEnergyPartials doubles.
+hipError_t launch_divergence(const void* fx, const void* fy, const double* n64, int nx, int ny,
+                             double delta, bool fp32, bool weight_n, double* partials,
+                             double* out, hipStream_t stream);
 
 // FP64 staging (3 consecutive planes) to the three amplitude planes.
 hipError_t launch_from_f64(const double* src, size_t count, bool fp32, void* q2, void* q3,

@@ -23,6 +23,12 @@
 //   SKEW_HALF: V_x = R(-beta_x/2) on (q2, q4); V_y = R(+beta_y/2) on (q2, q3).
 //   PAPER:     q4 <- -sin(beta_x) q2 + cos(beta_x) q4; q3 <- sin(beta_y) q2 + cos(beta_y) q3.
 //
+// The B_z triple (q0, q1, q5) follows the same algebra with a = q5 (streamed by S_25
+// along both axes), p = q1 along x (streamed by S_14) and p = q0 along y (by S_03):
+// on these pairs C_x is R(-th) and C_y is R(+th), the E_z rotations with th negated,
+// and the SKEW_HALF potentials are the same rotations as above. The sign of th comes
+// with the launch arguments; the planes are passed as (a, p_y, p_x).
+//
 // Mapping to the machine. A wavefront owns a strip of 56 output columns and a
 // segment of output rows. Its 64 lanes hold columns x0-4 .. x0+59 (4 halo columns
 // each side, periodic wrap), one column per lane. The wave marches down the rows:
@@ -112,6 +118,7 @@ struct StepArgs {
   unsigned plane_bytes;  // nx * ny * sizeof(T), at most 2^31
   int nx, ny, strips, segs, rows_per_seg, iters;
   T d4;  // delta / 4
+  T dc;  // collision angle over 1/n: +delta/4 (E_z triple) or -delta/4 (B_z triple)
 };
 
 // kWin: register window depth in rows (the loop is unrolled kWin times so every
@@ -285,7 +292,7 @@ struct Marcher {
     } else {
       const T m = recip(N[S0]);
       M[S0] = m;
-      const Shear<T> c = shear_of<T, CLS>(g.d4 * m);
+      const Shear<T> c = shear_of<T, CLS>(g.dc * m);
       Tt[S0] = c.t;
       Ts[S0] = c.s;
     }
@@ -415,6 +422,7 @@ StepArgs<T> make_args(const StepLaunch& L) {
   g.rows_per_seg = g.iters - 2 * halo;
   g.segs = (L.ny + g.rows_per_seg - 1) / g.rows_per_seg;
   g.d4 = static_cast<T>(L.delta * 0.25);
+  g.dc = L.triple ? -g.d4 : g.d4;
   return g;
 }
 

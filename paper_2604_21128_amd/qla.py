@@ -22,10 +22,11 @@ LIB_PATH = os.path.join(_HERE, "libqla.so")
 QLA_OK, QLA_EINVAL, QLA_ENOMEM, QLA_EDEVICE, QLA_ESTATE = 0, -1, -2, -3, -4
 QLA_F64, QLA_F32 = 0, 1
 QLA_V_SKEW_HALF, QLA_V_PAPER, QLA_V_NONE = 0, 1, 2
+QLA_TRIPLE_EZ, QLA_TRIPLE_BZ = 0, 1
 
 # Every symbol include/qla.h declares.
 EXPORTED = (
-    "qla_create", "qla_set_index", "qla_set_index_device", "qla_init_packet",
+    "qla_create", "qla_create_triple", "qla_divergence", "qla_set_index", "qla_set_index_device", "qla_init_packet",
     "qla_set_fields", "qla_advance", "qla_get_fields", "qla_get_fields_device",
     "qla_energy", "qla_energy_device", "qla_get_coefficients", "qla_step_count",
     "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_destroy", "qla_strerror",
@@ -66,6 +67,9 @@ def load(path: str = LIB_PATH):
     proto = {
         "qla_create": (st, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                             ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "qla_create_triple": (st, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "qla_divergence": (st, [vp, dp, dp, dp]),
         "qla_set_index": (st, [vp, dp, ctypes.c_size_t]),
         "qla_set_index_device": (st, [vp, vp, ctypes.c_size_t]),
         "qla_init_packet": (st, [vp, ctypes.POINTER(qla_packet)]),
@@ -148,6 +152,25 @@ def qla_create(nx: int, ny: int, delta: float, precision: int = QLA_F64,
                              ctypes.c_void_p(hip_stream) if hip_stream else None,
                              ctypes.byref(out)), "qla_create")
     return int(out.value)
+
+
+def qla_create_triple(nx: int, ny: int, delta: float, precision: int = QLA_F64,
+                      potential: int = QLA_V_SKEW_HALF, triple: int = QLA_TRIPLE_EZ,
+                      hip_stream: Optional[int] = None) -> int:
+    out = ctypes.c_void_p()
+    _check(load().qla_create_triple(int(nx), int(ny), float(delta), int(precision),
+                                    int(potential), int(triple),
+                                    ctypes.c_void_p(hip_stream) if hip_stream else None,
+                                    ctypes.byref(out)), "qla_create_triple")
+    return int(out.value)
+
+
+def qla_divergence(ctx: int):
+    """(l2, max_abs, scale) of the in-plane field's discrete divergence."""
+    v = [ctypes.c_double() for _ in range(3)]
+    _check(load().qla_divergence(ctypes.c_void_p(ctx), *[ctypes.byref(x) for x in v]),
+           "qla_divergence")
+    return v[0].value, v[1].value, v[2].value
 
 
 def qla_destroy(ctx: int) -> None:
@@ -387,9 +410,10 @@ class Lattice:
     """Owns one context; a convenience wrapper over the functions above."""
 
     def __init__(self, nx: int, ny: int, delta: float, precision: int = QLA_F64,
-                 potential: int = QLA_V_SKEW_HALF, hip_stream: Optional[int] = None):
+                 potential: int = QLA_V_SKEW_HALF, hip_stream: Optional[int] = None,
+                 triple: int = QLA_TRIPLE_EZ):
         self.nx, self.ny = int(nx), int(ny)
-        self.ctx = qla_create(nx, ny, delta, precision, potential, hip_stream)
+        self.ctx = qla_create_triple(nx, ny, delta, precision, potential, triple, hip_stream)
 
     def close(self):
         if self.ctx:
@@ -428,6 +452,9 @@ class Lattice:
 
     def coefficients(self):
         return qla_get_coefficients(self.ctx, self.nx, self.ny)
+
+    def divergence(self):
+        return qla_divergence(self.ctx)
 
     @property
     def steps(self) -> int:

@@ -92,3 +92,12 @@ def test_surrogate_null_handle_is_rejected():
     assert lib.qla_fno_adam_step(None, 1e-3, 0.9, 0.999, 1e-8) == qla.QLA_EINVAL
     assert lib.qla_fno_param_count(None, None) == qla.QLA_EINVAL
     assert lib.qla_fno_destroy(None) == qla.QLA_OK
+
+
+def test_bz_triple_rejects_the_printed_potentials_and_bad_triples():
+    qla, lib = _lib()
+    out = ctypes.c_void_p(1234)
+    assert lib.qla_create_triple(64, 64, 0.25, 0, qla.QLA_V_PAPER, qla.QLA_TRIPLE_BZ, None,
+                                 ctypes.byref(out)) == qla.QLA_EINVAL
+    assert lib.qla_create_triple(64, 64, 0.25, 0, 0, 7, None, ctypes.byref(out)) == qla.QLA_EINVAL
+    assert lib.qla_divergence(None, None, None, None) == qla.QLA_EINVAL
