@@ -479,6 +479,38 @@ def surrogate_study(qla, torch, args):
     return res
 
 
+def divergence_study(qla, torch, w, snapshot_every):
+    """Both polarisations on one workload (FP64): energy drift and the relative discrete
+    divergence ||div|| / ||(dFx/dx, dFy/dy)|| of B (E_z triple) or D (B_z triple) at each
+    snapshot."""
+    import numpy as np
+    import workloads
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    sp = torch.cuda.current_stream().cuda_stream
+    out = {"workload": w.name, "steps": w.steps, "snapshot_every": snapshot_every,
+           "triples": {}}
+    for triple, name in ((qla.QLA_TRIPLE_EZ, "ez"), (qla.QLA_TRIPLE_BZ, "bz")):
+        rows = []
+        with qla.Lattice(w.nx, w.ny, w.delta, qla.QLA_F64, qla.QLA_V_SKEW_HALF, sp,
+                         triple=triple) as lat:
+            lat.set_index(n)
+            lat.init_packet(w.packet)
+            e0 = lat.energy()
+            done = 0
+            while done < w.steps:
+                k = min(snapshot_every, w.steps - done)
+                lat.advance(k)
+                done += k
+                l2, mx, scale = lat.divergence()
+                rows.append({"step": done, "energy_drift": lat.energy() / e0 - 1,
+                             "div_l2": l2, "div_max": mx, "scale": scale,
+                             "rel_div": l2 / scale if scale > 0 else None})
+        print(f"[divergence] {name}: final rel_div {rows[-1]['rel_div']:.3e}, energy drift "
+              f"{rows[-1]['energy_drift']:.2e}", file=sys.stderr, flush=True)
+        out["triples"][name] = rows
+    return out
+
+
 def cpu_baseline(w, sample_steps):
     import numpy as np
     import oracle
@@ -515,6 +547,9 @@ def main():
                     help="the batched workload (512 instances, FP32); prints its own JSON line")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--error-samples", type=int, default=6)
+    ap.add_argument("--divergence-study", action="store_true",
+                    help="both polarisations on --workload: energy drift and relative "
+                         "divergence per snapshot (--snapshot-every); prints its own JSON line")
     ap.add_argument("--surrogate", action="store_true",
                     help="the learned-surrogate workload; prints its own JSON line")
     ap.add_argument("--side", type=int, default=512)
@@ -563,6 +598,15 @@ def main():
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             out = batched_study(qla, torch, args.instances, 0, args.error_samples)
+        print(json.dumps(out), flush=True)
+        return
+    if args.divergence_study:
+        w = workloads.workload_by_name(args.workload)
+        if args.qla_steps:
+            w = dataclasses.replace(w, steps=args.qla_steps)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out = divergence_study(qla, torch, w, args.snapshot_every)
         print(json.dumps(out), flush=True)
         return
     if args.surrogate:
