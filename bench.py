@@ -521,10 +521,55 @@ def cpu_baseline(w, sample_steps):
     oracle.advance(q, n, w.delta, sample_steps)
     dt = time.perf_counter() - t0
     del q
+    # the small parity workload, all of it
+    s = workloads.parity_small()
+    ns = workloads.ellipse_index(s.nx, s.ny, s.ellipse)
+    qs = oracle.packet_from(ns, s.packet)
+    t1 = time.perf_counter()
+    oracle.advance(qs, ns, s.delta, s.steps)
+    ds = time.perf_counter() - t1
     return {"value": round(w.nx * w.ny * sample_steps / dt / 1e9, 6), "unit": "GLUPS",
             "cores": oracle.threads(), "kind": "oracle",
             "sample": f"first {sample_steps} steps of the {w.nx}x{w.ny} workload, FP64, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "small_workload": {"workload": s.name, "steps": s.steps, "seconds": round(ds, 3),
+                               "glups": round(s.nx * s.ny * s.steps / ds / 1e9, 6)}}
+
+
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """A plain device copy of `mib` MiB timed with events: the practical streaming rate
+    (bytes read + written per second) beside the 8 TB/s spec."""
+    src = torch.ones(mib * 2**20 // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del src, dst
+    return round(2 * mib * 2**20 / best / 1e9, 1)
+
+
+def paper_mode_drift(qla, torch):
+    """Energy drift of the printed potentials against the default ones on the small
+    parity workload (256^2 ellipse, 200 steps, FP64)."""
+    import workloads
+    s = workloads.parity_small()
+    n = workloads.ellipse_index(s.nx, s.ny, s.ellipse)
+    sp = torch.cuda.current_stream().cuda_stream
+    out = {"workload": s.name, "steps": s.steps}
+    for mode, name in ((qla.QLA_V_PAPER, "paper"), (qla.QLA_V_SKEW_HALF, "skew_half")):
+        with qla.Lattice(s.nx, s.ny, s.delta, qla.QLA_F64, mode, sp) as lat:
+            lat.set_index(n)
+            lat.init_packet(s.packet)
+            e0 = lat.energy()
+            lat.advance(s.steps)
+            out[name + "_energy_drift"] = lat.energy() / e0 - 1
+    return out
 
 
 def main():
@@ -536,7 +581,7 @@ def main():
     ap.add_argument("--qla-steps", type=int, default=0, help="override the QLA step count")
     ap.add_argument("--precisions", default="f64,f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample-steps", type=int, default=12)
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR",
                                                                "TRACE_DIR", "TUNING_JSON"))
     ap.add_argument("--precision-study", action="store_true",
@@ -658,6 +703,9 @@ def main():
         "step_kernel_glups": round(r["kernel_glups"], 2),
         "energy_max_rel_drift": r["energy_max_rel_drift"],
     }
+    with torch.cuda.stream(stream):
+        line["copy_gbs"] = copy_bandwidth(torch)
+        line["potential_modes_small_workload"] = paper_mode_drift(qla, torch)
     for p in precs[1:]:
         rp = results[p]
         line[p] = {"value": round(rp["glups"], 3), "unit": "GLUPS",

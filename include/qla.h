@@ -131,6 +131,21 @@ qla_status qla_set_index(qla_ctx *ctx, const double *n_host, size_t ld);
 /* As qla_set_index, from device memory (ny rows of nx doubles, stride ld). */
 qla_status qla_set_index_device(qla_ctx *ctx, const double *n_device, size_t ld);
 
+/* Elliptical dielectric (or bubble) of the paper's scattering experiments (Section V,
+ * initial conditions), in cells and radians: semi-axis a along the x' axis rotated by
+ * rot about (xc, yc), b along y'; n_in inside, n_out outside, joined by a boundary
+ * layer about `width` cells thick. */
+typedef struct {
+    double xc, yc, a, b, rot, n_in, n_out, width;
+} qla_ellipse;
+
+/* Set n(x, y) from an ellipse, computed on the GPU in FP64:
+ * n = n_out + (n_in - n_out) (1 - tanh(d / width)) / 2 with d = (rho^2 - 1) / |grad rho^2|
+ * the first-order signed distance to rho^2 = (x'/a)^2 + (y'/b)^2 = 1 (n = n_in at the
+ * exact centre). Then as qla_set_index (checks, coefficients, step counter reset).
+ * QLA_EINVAL unless a, b, width > 0 and every field is finite. Synchronises. */
+qla_status qla_set_index_ellipse(qla_ctx *ctx, const qla_ellipse *ellipse);
+
 /* Fill the amplitudes with the packet of qla_packet on the current n
  * (QLA_ESTATE if no index is set). Resets the step counter. Asynchronous. */
 qla_status qla_init_packet(qla_ctx *ctx, const qla_packet *packet);

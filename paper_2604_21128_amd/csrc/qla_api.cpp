@@ -291,6 +291,20 @@ qla_status qla_set_index(qla_ctx* c, const double* n_host, size_t ld) {
   return install_index(c, c->staging, c->nx);
 }
 
+qla_status qla_set_index_ellipse(qla_ctx* c, const qla_ellipse* e) {
+  if (!c || !e) return fail(QLA_EINVAL, "NULL argument");
+  const double v[] = {e->xc, e->yc, e->a, e->b, e->rot, e->n_in, e->n_out, e->width};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(QLA_EINVAL, "ellipse: every field must be finite");
+  if (!(e->a > 0.0) || !(e->b > 0.0) || !(e->width > 0.0))
+    return fail(QLA_EINVAL, "ellipse: a, b and width must be > 0");
+  DeviceGuard g(c->device);
+  if (!g.ok()) return fail(QLA_EDEVICE, "cannot select the context's device");
+  const qla::EllipseArgs a{e->xc, e->yc, e->a, e->b, e->rot, e->n_in, e->n_out, e->width};
+  QLA_HIP(qla::launch_ellipse_index(c->nx, c->ny, a, c->staging, c->stream));
+  return install_index(c, c->staging, c->nx);
+}
+
 qla_status qla_set_index_device(qla_ctx* c, const double* n_device, size_t ld) {
   if (!c || !n_device) return fail(QLA_EINVAL, "NULL argument");
   if (ld < static_cast<size_t>(c->nx)) return fail(QLA_EINVAL, "ld < nx");

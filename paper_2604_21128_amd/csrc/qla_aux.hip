@@ -129,6 +129,28 @@ __global__ __launch_bounds__(kBlock) void coefficients_kernel(const double* __re
   }
 }
 
+// n(x, y) of an elliptical dielectric (or bubble) with a tanh boundary layer: the
+// first-order signed distance d = (rho^2 - 1) / (2 |grad rho^2| / 2) to the ellipse
+// rho^2 = (x'/a)^2 + (y'/b)^2 = 1 in coordinates rotated by rot about (xc, yc), and
+// n = n_out + (n_in - n_out) (1 - tanh(d / width)) / 2 (n_in at the exact centre).
+__global__ __launch_bounds__(kBlock) void ellipse_index_kernel(int nx, int ny, EllipseArgs e,
+                                                               double* __restrict__ out) {
+  const size_t count = static_cast<size_t>(nx) * ny;
+  const double cr = cos(e.rot), sr = sin(e.rot);
+  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * kBlock) {
+    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
+    const double dx = x - e.xc, dy = y - e.yc;
+    const double xp = dx * cr + dy * sr, yp = -dx * sr + dy * cr;
+    const double u = xp / e.a, v = yp / e.b;
+    const double rho2 = u * u + v * v;
+    const double gx = xp / (e.a * e.a), gy = yp / (e.b * e.b);
+    const double g = sqrt(gx * gx + gy * gy);
+    const double prof = g > 0.0 ? 0.5 * (1.0 - tanh((rho2 - 1.0) / (2.0 * g) / e.width)) : 1.0;
+    out[i] = e.n_out + (e.n_in - e.n_out) * prof;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void packet_kernel(const double* __restrict__ n64, int nx,
                                                         int ny, PacketArgs p, T* q2, T* q3,
@@ -318,6 +340,14 @@ hipError_t launch_coefficients(const double* n64, int nx, int ny, double delta, 
   const size_t count = static_cast<size_t>(nx) * ny;
   hipLaunchKernelGGL(coefficients_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64, nx,
                      ny, 0.25 * delta, theta, beta_x, beta_y);
+  return hipGetLastError();
+}
+
+hipError_t launch_ellipse_index(int nx, int ny, const EllipseArgs& e, double* out,
+                                hipStream_t stream) {
+  const size_t count = static_cast<size_t>(nx) * ny;
+  hipLaunchKernelGGL(ellipse_index_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, nx, ny,
+                     e, out);
   return hipGetLastError();
 }
 

@@ -61,6 +61,13 @@ hipError_t launch_index_prepare(const double* src, size_t ld, int nx, int ny, do
 hipError_t launch_coefficients(const double* n64, int nx, int ny, double delta, double* theta,
                                double* beta_x, double* beta_y, hipStream_t stream);
 
+struct EllipseArgs {
+  double xc, yc, a, b, rot, n_in, n_out, width;
+};
+// n of an elliptical dielectric with a tanh boundary layer into a packed FP64 plane.
+hipError_t launch_ellipse_index(int nx, int ny, const EllipseArgs& e, double* out,
+                                hipStream_t stream);
+
 struct PacketArgs {
   double x0, y0, sigma, lambda, phi, amp;
   int planar;

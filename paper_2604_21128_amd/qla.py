@@ -26,7 +26,8 @@ QLA_TRIPLE_EZ, QLA_TRIPLE_BZ = 0, 1
 
 # Every symbol include/qla.h declares.
 EXPORTED = (
-    "qla_create", "qla_create_triple", "qla_divergence", "qla_set_index", "qla_set_index_device", "qla_init_packet",
+    "qla_create", "qla_create_triple", "qla_divergence", "qla_set_index_ellipse",
+    "qla_set_index", "qla_set_index_device", "qla_init_packet",
     "qla_set_fields", "qla_advance", "qla_get_fields", "qla_get_fields_device",
     "qla_energy", "qla_energy_device", "qla_get_coefficients", "qla_step_count",
     "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_destroy", "qla_strerror",
@@ -42,6 +43,11 @@ class QlaError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         super().__init__(f"{where} failed with status {status}: {message}")
         self.status = status
+
+
+class qla_ellipse(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in
+                ("xc", "yc", "a", "b", "rot", "n_in", "n_out", "width")]
 
 
 class qla_packet(ctypes.Structure):
@@ -70,6 +76,7 @@ def load(path: str = LIB_PATH):
         "qla_create_triple": (st, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]),
         "qla_divergence": (st, [vp, dp, dp, dp]),
+        "qla_set_index_ellipse": (st, [vp, ctypes.POINTER(qla_ellipse)]),
         "qla_set_index": (st, [vp, dp, ctypes.c_size_t]),
         "qla_set_index_device": (st, [vp, vp, ctypes.c_size_t]),
         "qla_init_packet": (st, [vp, ctypes.POINTER(qla_packet)]),
@@ -182,6 +189,14 @@ def qla_set_index(ctx: int, n: np.ndarray) -> None:
     if n.ndim != 2:
         raise ValueError("n must be [ny, nx]")
     _check(load().qla_set_index(ctypes.c_void_p(ctx), _dptr(n), n.shape[1]), "qla_set_index")
+
+
+def qla_set_index_ellipse(ctx: int, xc: float, yc: float, a: float, b: float, rot: float,
+                          n_in: float, n_out: float, width: float) -> None:
+    e = qla_ellipse(float(xc), float(yc), float(a), float(b), float(rot), float(n_in),
+                    float(n_out), float(width))
+    _check(load().qla_set_index_ellipse(ctypes.c_void_p(ctx), ctypes.byref(e)),
+           "qla_set_index_ellipse")
 
 
 def qla_set_index_device(ctx: int, n_device, ld: int) -> None:

@@ -143,3 +143,21 @@ def test_divergence_of_the_initial_planar_packets_vanishes(qla):
             lat.init_packet(w.packet)
             l2, mx, scale = lat.divergence()
         assert mx == 0.0 and l2 == 0.0 and scale == 0.0
+
+
+@pytest.mark.parametrize("ellipse", [
+    workloads.Ellipse(128.0, 128.0, 40.0, 20.0, 0.0, 2.0, 1.0, 3.0),
+    workloads.Ellipse(70.3, 150.0, 55.0, 17.5, 0.9, 1.0, 2.6, 2.0),     # rotated bubble
+])
+def test_set_index_ellipse_matches_the_input_generator(qla, ellipse):
+    nx, ny = 256, 200
+    want = workloads.ellipse_index(nx, ny, ellipse)
+    with qla.Lattice(nx, ny, 0.25) as lat:
+        qla.qla_set_index_ellipse(lat.ctx, ellipse.xc, ellipse.yc, ellipse.a, ellipse.b,
+                                  ellipse.rot, ellipse.n_in, ellipse.n_out, ellipse.width)
+        th, _, _ = lat.coefficients()
+    # theta = delta / (4 n): n to a few ulps (cos, sin, tanh of the device libraries)
+    np.testing.assert_allclose(0.25 / (4 * th), want, rtol=1e-14, atol=0)
+    with qla.Lattice(nx, ny, 0.25) as lat:
+        with pytest.raises(qla.QlaError):
+            qla.qla_set_index_ellipse(lat.ctx, 1, 1, 0.0, 5, 0, 2, 1, 3)    # a = 0
