@@ -197,17 +197,18 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, tuning_json):
     lines = [f"# qla_step_ez_kernel on the {w.nx}x{w.ny} ellipse workload (MI355X, gfx950)", "",
              "Commands (from /tmp with TMPDIR=/tmp; R = repository root; tuning fixed to the "
              "autotuned values below):", "", "```"]
+    tj = "'" + json.dumps(tuning) + "'"
     lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_trace "
               f"-o trace -- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 2000 "
-              f"--no-cpu-baseline",
+              f"--no-cpu-baseline --no-extras --tuning-json {tj}",
               f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof_fetch -o fetch "
               f"-- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 100 --no-cpu-baseline "
-              f"--copy-probe-mib 1024",
+              f"--no-extras --copy-probe-mib 1024 --tuning-json {tj}",
               f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof_write -o write "
               f"-- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 100 --no-cpu-baseline "
-              f"--copy-probe-mib 1024",
+              f"--no-extras --copy-probe-mib 1024 --tuning-json {tj}",
               f"python3 $R/bench.py --summarize-counters $R/gpurun_out/prof_fetch "
-              f"$R/gpurun_out/prof_write $R/gpurun_out/prof_trace '<tuning json>'", "```", ""]
+              f"$R/gpurun_out/prof_write $R/gpurun_out/prof_trace {tj}", "```", ""]
     lines += ["## Kernel trace (--stats)", "", "| kernel | calls | average (us) | min (us) | max (us) |",
               "|---|---|---|---|---|"]
     avg_ns = {}
@@ -581,6 +582,9 @@ def main():
     ap.add_argument("--qla-steps", type=int, default=0, help="override the QLA step count")
     ap.add_argument("--precisions", default="f64,f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the copy-bandwidth probe and the potential-mode drift run (for "
+                         "profiling runs, whose per-kernel averages must cover the job only)")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR",
                                                                "TRACE_DIR", "TUNING_JSON"))
@@ -703,9 +707,10 @@ def main():
         "step_kernel_glups": round(r["kernel_glups"], 2),
         "energy_max_rel_drift": r["energy_max_rel_drift"],
     }
-    with torch.cuda.stream(stream):
-        line["copy_gbs"] = copy_bandwidth(torch)
-        line["potential_modes_small_workload"] = paper_mode_drift(qla, torch)
+    if not args.no_extras:
+        with torch.cuda.stream(stream):
+            line["copy_gbs"] = copy_bandwidth(torch)
+            line["potential_modes_small_workload"] = paper_mode_drift(qla, torch)
     for p in precs[1:]:
         rp = results[p]
         line[p] = {"value": round(rp["glups"], 3), "unit": "GLUPS",
