@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC_PATH = os.path.join(_HERE, "qla_oracle.c")
 
-V_SKEW_HALF, V_PAPER, V_NONE = 0, 1, 2
+V_SKEW_HALF, V_PAPER, V_NONE, V_BSTREAM = 0, 1, 2, 3
 
 # Operator codes, in the order of the C enum.
 (OP_CX, OP_CX_DAG, OP_CY, OP_CY_DAG,

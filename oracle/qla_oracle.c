@@ -44,6 +44,13 @@
  *     Eqs. (2d1)-(2d6). The test suite pins this by second-order convergence
  *     to a spectral solution of Eqs. (2d1)-(2d6).
  *   - V_NONE: potentials off (the homogeneous-medium scheme of Eq. 2e10).
+ *   - V_BSTREAM (beyond the paper, E_z triple): U_x and U_y built only from the sets
+ *     of Eqs. (2e6) and (2e9) that stream the B-qubit of the pair (S14 along x, S03
+ *     along y), each used twice, and no potentials. A set that streams the B-qubit puts
+ *     the angle of the E-qubit's site on the neighbour pair, which to first order
+ *     gives dt q2 = (1/n) d q4 and dt q4 = d(q2 / n): the Maxwell form of
+ *     Eqs. (2d3)-(2d5) without a potential. Pinned by the same convergence and
+ *     Fresnel tests as V_SKEW_HALF.
  */
 #include <math.h>
 #include <stddef.h>
@@ -54,7 +61,7 @@
 #include <omp.h>
 #endif
 
-enum { V_SKEW_HALF = 0, V_PAPER = 1, V_NONE = 2 };
+enum { V_SKEW_HALF = 0, V_PAPER = 1, V_NONE = 2, V_BSTREAM = 3 };
 
 /* Operator codes for single-operator application (tests drive these). */
 enum {
@@ -78,6 +85,25 @@ static const int UY_AS_PRINTED[16] = {
     OP_S25_PY, OP_CY_DAG, OP_S25_MY, OP_CY,
     OP_S03_MY, OP_CY_DAG, OP_S03_PY, OP_CY,
     OP_S25_MY, OP_CY, OP_S25_PY, OP_CY_DAG,
+    OP_S03_PY, OP_CY, OP_S03_MY, OP_CY_DAG,
+};
+
+/* V_BSTREAM (a scheme beyond the paper, for the E_z triple): the sets of Eq. (2e6) that
+ * stream the E-qubit q2 (S25) are replaced by copies of the neighbouring sets that
+ * stream the B-qubit q4 (S14), which couple the same neighbour pairs with the same
+ * rotation sense; likewise in Eq. (2e9) with S03. No potentials. Same notation as
+ * above: as printed, the rightmost factor acts first. In acting order the x sets are
+ * (C+, S14-, C, S14+) twice, then (C, S14+, C+, S14-) twice. */
+static const int UX_BSTREAM[16] = {
+    OP_S14_MX, OP_CX_DAG, OP_S14_PX, OP_CX,
+    OP_S14_MX, OP_CX_DAG, OP_S14_PX, OP_CX,
+    OP_S14_PX, OP_CX, OP_S14_MX, OP_CX_DAG,
+    OP_S14_PX, OP_CX, OP_S14_MX, OP_CX_DAG,
+};
+static const int UY_BSTREAM[16] = {
+    OP_S03_MY, OP_CY_DAG, OP_S03_PY, OP_CY,
+    OP_S03_MY, OP_CY_DAG, OP_S03_PY, OP_CY,
+    OP_S03_PY, OP_CY, OP_S03_MY, OP_CY_DAG,
     OP_S03_PY, OP_CY, OP_S03_MY, OP_CY_DAG,
 };
 
@@ -220,15 +246,19 @@ static void apply_op(int op, int nx, int ny, double *q, const site_angles *A, in
     case OP_S25_PY: stream(nx, ny, q, 2, 5, 0, +1, tmp); break;
     case OP_S25_MY: stream(nx, ny, q, 2, 5, 0, -1, tmp); break;
     case OP_VX: case OP_VY:
-        if (vmode == V_NONE) break;
+        if (vmode == V_NONE || vmode == V_BSTREAM) break;
         apply_local(nx, ny, q, A, op, vmode);
         break;
-    case OP_UX:
-        for (int i = 15; i >= 0; --i) apply_op(UX_AS_PRINTED[i], nx, ny, q, A, vmode, tmp);
+    case OP_UX: {
+        const int *ops = vmode == V_BSTREAM ? UX_BSTREAM : UX_AS_PRINTED;
+        for (int i = 15; i >= 0; --i) apply_op(ops[i], nx, ny, q, A, vmode, tmp);
         break;
-    case OP_UY:
-        for (int i = 15; i >= 0; --i) apply_op(UY_AS_PRINTED[i], nx, ny, q, A, vmode, tmp);
+    }
+    case OP_UY: {
+        const int *ops = vmode == V_BSTREAM ? UY_BSTREAM : UY_AS_PRINTED;
+        for (int i = 15; i >= 0; --i) apply_op(ops[i], nx, ny, q, A, vmode, tmp);
         break;
+    }
     case OP_STEP: /* Eq. (2e14): V_y V_x U_y U_x */
         apply_op(OP_UX, nx, ny, q, A, vmode, tmp);
         apply_op(OP_UY, nx, ny, q, A, vmode, tmp);
@@ -292,7 +322,8 @@ static int build_angles(int nx, int ny, double delta, int vmode, const double *n
 static int check_args(int nx, int ny, double delta, int vmode, const double *n, const double *q)
 {
     if (nx < 1 || ny < 1 || !(delta > 0.0) || !n || !q) return -1;
-    if (vmode != V_SKEW_HALF && vmode != V_PAPER && vmode != V_NONE) return -1;
+    if (vmode != V_SKEW_HALF && vmode != V_PAPER && vmode != V_NONE && vmode != V_BSTREAM)
+        return -1;
     return 0;
 }
 

@@ -481,3 +481,82 @@ def test_divergence_of_a_single_mode():
     ky = 2 * np.pi / (ny * delta)
     want = 2.0 * np.sin(ky * delta) / delta * np.cos(2 * np.pi * np.arange(ny) / ny)
     np.testing.assert_allclose(div_d, want[:, None] * np.ones((1, nx)), atol=1e-13)
+
+
+# --------------------------------------------------------------------------------------
+# V_BSTREAM: every collide-stream set streams the B-qubit of its pair, no potentials
+# (a fully unitary scheme beyond the paper)
+def test_bstream_sets_are_the_printed_sets_with_the_e_sets_replaced():
+    # U_x of V_BSTREAM differs from Eq. (2e6) only where the printed sets stream q2:
+    # in a medium of uniform n the two agree exactly (both are Eq. 2e10's scheme)
+    rng = np.random.default_rng(3)
+    n = np.full((6, 10), 1.7)
+    q = rng.standard_normal((6, 6, 10))
+    q[[0, 1, 5]] = 0.0
+    a = oracle.apply(oracle.OP_UX, q.copy(), n, 0.3, oracle.V_NONE)
+    b = oracle.apply(oracle.OP_UX, q.copy(), n, 0.3, oracle.V_BSTREAM)
+    np.testing.assert_allclose(a[2:5], b[2:5], atol=1e-14)
+    # with varying n they differ (the angle of the E or the B site enters the pair)
+    n2 = rng.uniform(1.0, 2.5, size=(6, 10))
+    a = oracle.apply(oracle.OP_UX, q.copy(), n2, 0.3, oracle.V_NONE)
+    b = oracle.apply(oracle.OP_UX, q.copy(), n2, 0.3, oracle.V_BSTREAM)
+    assert np.abs(a - b).max() > 1e-6
+
+
+def test_bstream_converges_at_second_order_through_a_slab_without_potentials(slab_reference):
+    errs = _slab_errors(oracle.V_BSTREAM, slab_reference)
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert ratios[-1] > 3.6 and ratios[-2] > 2.5, (errs, ratios)
+    assert errs[-1] < 0.15
+    # energy: every operator is a rotation or a shift
+    n, q = None, None
+    T, N = 0.25, 128
+    x = np.arange(N) / N
+    n = _slab_phys(x, 0.45, 0.85, 2.0, 0.03)[None, :].copy()
+    q = np.zeros((6, 1, N))
+    q[2, 0] = n[0] * _gauss_packet_phys(x, 0.25, 0.06, 0.15)
+    q[4, 0] = -q[2, 0]
+    e0 = oracle.energy(q)
+    oracle.advance(q, n, 1.0 / N, int(round(T * N * N)), oracle.V_BSTREAM)
+    assert abs(oracle.energy(q) / e0 - 1) < 1e-11
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_bstream_converges_in_2d_around_an_ellipse(axis):
+    T, Nref = 0.06, 256
+
+    def index(N):
+        c = np.arange(N) / N
+        X, Y = np.meshgrid(c, c)
+        rho2 = ((X - 0.5) / 0.2) ** 2 + ((Y - 0.5) / 0.12) ** 2
+        return 1.0 + 0.5 * (1.0 - np.tanh((rho2 - 1.0) / 0.35))
+
+    def init(N, n):
+        c = np.arange(N) / N
+        X, Y = np.meshgrid(c, c)
+        q = np.zeros((6, N, N))
+        if axis == "x":
+            q[2] = n * _gauss_packet_phys(X, 0.3, 0.05, 0.12)
+            q[4] = -q[2]
+        else:
+            q[2] = n * _gauss_packet_phys(Y, 0.3, 0.05, 0.12)
+            q[3] = q[2]                      # one way along +y
+        return q
+
+    nref = index(Nref)
+    qref = spectral.solve(init(Nref, nref), nref, 1.0, 1.0, T)
+    errs = []
+    for N in (32, 64, 128):
+        n = index(N)
+        q = init(N, n)
+        oracle.advance(q, n, 1.0 / N, int(round(T * N * N)), oracle.V_BSTREAM)
+        r = qref[:, :: Nref // N, :: Nref // N][2:5]
+        errs.append(np.linalg.norm(q[2:5] - r) / np.linalg.norm(r))
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert ratios[-1] > 3.3, (errs, ratios)
+
+
+def test_bstream_normal_incidence_reflectance_is_fresnel():
+    r, t = _fresnel_run(oracle.V_BSTREAM)
+    assert abs(r / (1.0 / 9.0) - 1) < 0.03, r
+    assert abs(r + t - 1) < 1e-6
