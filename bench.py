@@ -31,11 +31,14 @@ BYTES_PER_SITE = {"f64": 56, "f32": 28}
 METRIC = "lattice-site updates/s (GLUPS) + HBM GB/s; batched/surrogate instances/s at error"
 
 
+POTENTIALS = {"skew_half": 0, "paper": 1, "none": 2, "bstream": 3}
+
+
 def run_job(qla, torch, w, n_dev, prec_code, out_dev, energies, stream_ptr, record_kernel,
-            tuning=None):
+            tuning=None, potential=0):
     """The whole job once; returns (ctx, list of (start, end) events around advances).
     With tuning=None the context autotunes (untimed warm-up only)."""
-    ctx = qla.qla_create(w.nx, w.ny, w.delta, prec_code, qla.QLA_V_SKEW_HALF, stream_ptr)
+    ctx = qla.qla_create(w.nx, w.ny, w.delta, prec_code, potential, stream_ptr)
     try:
         qla.qla_set_index_device(ctx, n_dev, w.nx)
         if tuning is None:
@@ -64,7 +67,7 @@ def run_job(qla, torch, w, n_dev, prec_code, out_dev, energies, stream_ptr, reco
     return ctx, pairs
 
 
-def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None):
+def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None, potential=0):
     code = qla.QLA_F64 if prec == "f64" else qla.QLA_F32
     import workloads
     n_host = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
@@ -78,7 +81,8 @@ def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None):
         raise RuntimeError("bench needs a non-default torch stream")
     tuning = tuple(forced_tuning) if forced_tuning else None
     for _ in range(max(1, warmup)):
-        ctx, _ = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, False, tuning)
+        ctx, _ = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, False, tuning,
+                         potential)
         torch.cuda.synchronize()
         if tuning is None:
             tuning = qla.qla_get_tuning(ctx)
@@ -90,7 +94,8 @@ def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None):
         t1 = torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
         t0.record()
-        ctx, pairs = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, True, tuning)
+        ctx, pairs = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, True, tuning,
+                             potential)
         t1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
@@ -581,6 +586,9 @@ def main():
     ap.add_argument("--workload", default="qla_4096_ellipse_20000")
     ap.add_argument("--qla-steps", type=int, default=0, help="override the QLA step count")
     ap.add_argument("--precisions", default="f64,f32")
+    ap.add_argument("--potential", default="skew_half", choices=sorted(POTENTIALS),
+                    help="potential mode of the measured job (skew_half: the default "
+                         "half-angle potentials; bstream: the B-streaming scheme)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the copy-bandwidth probe and the potential-mode drift run (for "
@@ -680,9 +688,11 @@ def main():
     results = {}
     stream = torch.cuda.Stream()   # default priority
     with torch.cuda.stream(stream):
-        forced = json.loads(args.tuning_json) if args.tuning_json else recorded_tuning(w)
+        forced = json.loads(args.tuning_json) if args.tuning_json else (
+            recorded_tuning(w) if args.potential == "skew_half" else {})
         for p in precs:
-            results[p] = bench_precision(qla, torch, w, p, args.steps, args.warmup, forced.get(p))
+            results[p] = bench_precision(qla, torch, w, p, args.steps, args.warmup, forced.get(p),
+                                         POTENTIALS[args.potential])
     main_p = precs[0]
     r = results[main_p]
     line = {
@@ -699,7 +709,7 @@ def main():
         "dtype": main_p,
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "qla_steps": w.steps,
-                   "energy_every": w.energy_every, "delta": w.delta, "potential": "skew_half",
+                   "energy_every": w.energy_every, "delta": w.delta, "potential": args.potential,
                    "ellipse": dataclasses.asdict(w.ellipse), "packet": dataclasses.asdict(w.packet)},
         "roofline": r["roofline"],
         "launch": r["launch"],
@@ -711,6 +721,13 @@ def main():
         with torch.cuda.stream(stream):
             line["copy_gbs"] = copy_bandwidth(torch)
             line["potential_modes_small_workload"] = paper_mode_drift(qla, torch)
+            if args.potential == "skew_half" and "f64" in precs:
+                # the same job with the B-streaming scheme (no potentials, fully unitary)
+                rb = bench_precision(qla, torch, w, "f64", 1, 1, None, POTENTIALS["bstream"])
+                line["bstream_f64"] = {"value": round(rb["glups"], 3), "unit": "GLUPS",
+                                       "roofline_frac": rb["roofline"]["frac"],
+                                       "launch": rb["launch"],
+                                       "energy_max_rel_drift": rb["energy_max_rel_drift"]}
     for p in precs[1:]:
         rp = results[p]
         line[p] = {"value": round(rp["glups"], 3), "unit": "GLUPS",

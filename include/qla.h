@@ -78,7 +78,13 @@ typedef enum {
      * unitary; kept for comparison. */
     QLA_V_PAPER = 1,
     /* Potentials off: the homogeneous-medium scheme of Eq. (2e10). */
-    QLA_V_NONE = 2
+    QLA_V_NONE = 2,
+    /* A scheme beyond the paper (E_z triple only): no potentials, and U_x, U_y built
+     * only from the sets of Eqs. (2e6), (2e9) that stream the B-qubit of each pair
+     * (S_14 along x, S_03 along y), each used twice. Every neighbour pair then takes
+     * the angle of its E site, which gives the Maxwell form of Eqs. (2d3)-(2d5)
+     * without a potential: fully unitary, second order in delta. */
+    QLA_V_BSTREAM = 3
 } qla_potential;
 
 /* Which polarisation a context evolves. The operators of Eq. (2e14) never couple the
@@ -116,7 +122,8 @@ qla_status qla_create(int nx, int ny, double delta, qla_precision precision,
  * stepped with the same operators of Eq. (2e14) acting on (q0, q1, q5): C_x (Eq. 2e3)
  * on (q1, q5), C_y (Eq. 2e8) on (q0, q5), streaming S_14, S_03 and S_25 (Eq. 2e5).
  * Its field arrays are planes (q0, q1, q5), or (Ex, Ey, Bz) = (q0 / n, q1 / n, q5) for
- * physical readout. QLA_V_PAPER is implemented for the E_z triple only (QLA_EINVAL). */
+ * physical readout. QLA_V_PAPER and QLA_V_BSTREAM are implemented for the E_z triple
+ * only (QLA_EINVAL). */
 qla_status qla_create_triple(int nx, int ny, double delta, qla_precision precision,
                              qla_potential potential, qla_triple triple, void *hip_stream,
                              qla_ctx **out);

@@ -207,11 +207,13 @@ qla_status qla_create_triple(int nx, int ny, double delta, qla_precision precisi
                             "2^29 in FP32)");
   if (!(delta > 0.0) || !std::isfinite(delta)) return fail(QLA_EINVAL, "delta must be > 0");
   if (precision != QLA_F64 && precision != QLA_F32) return fail(QLA_EINVAL, "bad precision");
-  if (potential != QLA_V_SKEW_HALF && potential != QLA_V_PAPER && potential != QLA_V_NONE)
+  if (potential != QLA_V_SKEW_HALF && potential != QLA_V_PAPER && potential != QLA_V_NONE &&
+      potential != QLA_V_BSTREAM)
     return fail(QLA_EINVAL, "bad potential mode");
   if (triple != QLA_TRIPLE_EZ && triple != QLA_TRIPLE_BZ) return fail(QLA_EINVAL, "bad triple");
-  if (triple == QLA_TRIPLE_BZ && potential == QLA_V_PAPER)
-    return fail(QLA_EINVAL, "the printed potentials are implemented for the E_z triple only");
+  if (triple == QLA_TRIPLE_BZ && (potential == QLA_V_PAPER || potential == QLA_V_BSTREAM))
+    return fail(QLA_EINVAL, "the printed potentials and the B-streaming scheme are implemented "
+                            "for the E_z triple only");
   qla_ctx* c = new (std::nothrow) qla_ctx;
   if (!c) return fail(QLA_ENOMEM, "host allocation");
   c->nx = nx;

@@ -8,7 +8,7 @@
 
 namespace qla {
 
-enum VMode : int { kVSkewHalf = 0, kVPaper = 1, kVNone = 2 };
+enum VMode : int { kVSkewHalf = 0, kVPaper = 1, kVNone = 2, kVBStream = 3 };
 
 // One fused step (qla_step.hip): three amplitude planes in, three out, n in the
 // stepping precision; all planes nx * ny, row pitch nx.

@@ -22,6 +22,9 @@
 // differences, i.e. beta/2 = (delta/4) (n_{+1} - n_{-1}) / n^2 in cell units:
 //   SKEW_HALF: V_x = R(-beta_x/2) on (q2, q4); V_y = R(+beta_y/2) on (q2, q3).
 //   PAPER:     q4 <- -sin(beta_x) q2 + cos(beta_x) q4; q3 <- sin(beta_y) q2 + cos(beta_y) q3.
+//   BSTREAM:   no potentials; sets 2 and 4 of U_x and U_y are replaced by copies of
+//              sets 1 and 3 (every set streams the B-qubit p), so every neighbour
+//              pair takes the angle of its a site (a scheme beyond the paper).
 //
 // The B_z triple (q0, q1, q5) follows the same algebra with a = q5 (streamed by S_25
 // along both axes), p = q1 along x (streamed by S_14) and p = q0 along y (by S_03):
@@ -134,6 +137,9 @@ struct StepArgs {
 template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
 struct Marcher {
   static_assert(PF + 4 * TS + 2 <= kWin, "a prefetched row must not overwrite a live one");
+  // B streaming: every set streams the B-qubit, so each neighbour pair takes the angle
+  // of its a site, and there are no potentials
+  static constexpr bool kBStream = VMODE == kVBStream;
   // Row window: amplitudes, index, 1/n and the collision shear of each row.
   T A[kWin], P4[kWin], P3[kWin], N[kWin], M[kWin], Tt[kWin], Ts[kWin];
   // Per-row wave-uniform facts, one bit per slot in scalar registers: umask bit s
@@ -184,12 +190,13 @@ struct Marcher {
       p = rotate_second(ap, p, tr, sr);
       a = an;
     }
-    // set 2: C^T on site; C(th_{i-1}) on (a_i, p_{i-1})
+    // set 2: C^T on site; C(th_{i-1}) on (a_i, p_{i-1}); with B streaming a copy of
+    // set 1 (the pair takes the angle of its a site)
     rotate(a, p, -t0, -s0);
     {
       const T pm = from_left(p), ap = from_right(a);
-      const T an = rotate_first(a, pm, tl, sl);
-      p = rotate_second(ap, p, t0, s0);
+      const T an = kBStream ? rotate_first(a, pm, t0, s0) : rotate_first(a, pm, tl, sl);
+      p = kBStream ? rotate_second(ap, p, tr, sr) : rotate_second(ap, p, t0, s0);
       a = an;
     }
     // set 3: C on site; C^T(th_i) on (a_i, p_{i+1})
@@ -200,12 +207,13 @@ struct Marcher {
       p = rotate_second(am, p, -tl, -sl);
       a = an;
     }
-    // set 4: C on site; C^T(th_{i+1}) on (a_i, p_{i+1})
+    // set 4: C on site; C^T(th_{i+1}) on (a_i, p_{i+1}); with B streaming a copy of
+    // set 3
     rotate(a, p, t0, s0);
     {
       const T pp = from_right(p), am = from_left(a);
-      const T an = rotate_first(a, pp, -tr, -sr);
-      p = rotate_second(am, p, -t0, -s0);
+      const T an = kBStream ? rotate_first(a, pp, -t0, -s0) : rotate_first(a, pp, -tr, -sr);
+      p = kBStream ? rotate_second(am, p, -tl, -sl) : rotate_second(am, p, -t0, -s0);
       a = an;
     }
     A[s] = a;
@@ -222,20 +230,24 @@ struct Marcher {
     rotate(A[s0], P3[s0], Tt[s0], Ts[s0]);
     rotate(A[s0], P3[s1], -Tt[s0], -Ts[s0]);
     // set 2 on row a-1: on-site C_y^T, then (a_{a-1}, p_{a-2}) with C_y(th_{a-2})
+    // (with B streaming: th_{a-1}, a copy of set 1)
+    constexpr int s2a = kBStream ? s1 : s2;
     rotate(A[s1], P3[s1], Tt[s1], Ts[s1]);
-    rotate(A[s1], P3[s2], -Tt[s2], -Ts[s2]);
+    rotate(A[s1], P3[s2], -Tt[s2a], -Ts[s2a]);
     // set 3 on row a-2: on-site C_y, then (a_{a-3}, p_{a-2}) with C_y^T(th_{a-3})
     rotate(A[s2], P3[s2], -Tt[s2], -Ts[s2]);
     rotate(A[s3], P3[s2], Tt[s3], Ts[s3]);
     // set 4 on row a-3: on-site C_y, then (a_{a-4}, p_{a-3}) with C_y^T(th_{a-3})
+    // (with B streaming: th_{a-4}, a copy of set 3)
+    constexpr int s4a = kBStream ? s4 : s3;
     rotate(A[s3], P3[s3], -Tt[s3], -Ts[s3]);
-    rotate(A[s4], P3[s3], Tt[s3], Ts[s3]);
+    rotate(A[s4], P3[s3], Tt[s4a], Ts[s4a]);
   }
 
   // V_x, V_y on the row a - 4 that the stage just completed (slot SC).
   template <int SC>
   __device__ __forceinline__ void potentials(T d4) {
-    if constexpr (VMODE == kVNone) {
+    if constexpr (VMODE == kVNone || VMODE == kVBStream) {
       return;
     } else {
       constexpr int sc = SC, sup = slot(SC, -1), sdn = slot(SC, 1);
@@ -459,6 +471,9 @@ auto with_variant(int vmode, int angle_class, int prefetch, int fused, F&& f) {
     case kVPaper:
       return large ? with_shape<T, kVPaper, kLarge>(prefetch, fused, f)
                    : with_shape<T, kVPaper, kSmall>(prefetch, fused, f);
+    case kVBStream:
+      return large ? with_shape<T, kVBStream, kLarge>(prefetch, fused, f)
+                   : with_shape<T, kVBStream, kSmall>(prefetch, fused, f);
     default:
       return large ? with_shape<T, kVNone, kLarge>(prefetch, fused, f)
                    : with_shape<T, kVNone, kSmall>(prefetch, fused, f);

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libqla.so")
 
 QLA_OK, QLA_EINVAL, QLA_ENOMEM, QLA_EDEVICE, QLA_ESTATE = 0, -1, -2, -3, -4
 QLA_F64, QLA_F32 = 0, 1
-QLA_V_SKEW_HALF, QLA_V_PAPER, QLA_V_NONE = 0, 1, 2
+QLA_V_SKEW_HALF, QLA_V_PAPER, QLA_V_NONE, QLA_V_BSTREAM = 0, 1, 2, 3
 QLA_TRIPLE_EZ, QLA_TRIPLE_BZ = 0, 1
 
 # Every symbol include/qla.h declares.

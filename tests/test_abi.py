@@ -52,6 +52,7 @@ def test_status_strings():
     (64, 64, float("nan"), 0, 0),
     (64, 64, 0.25, 7, 0),      # bad precision
     (64, 64, 0.25, 0, 9),      # bad potential mode
+    (64, 64, 0.25, 0, 4),
     (65536, 65536, 0.25, 0, 0),  # nx * ny >= 2^31
 ])
 def test_create_rejects_bad_arguments_before_touching_the_device(nx, ny, delta, prec, pot):
@@ -100,4 +101,6 @@ def test_bz_triple_rejects_the_printed_potentials_and_bad_triples():
     assert lib.qla_create_triple(64, 64, 0.25, 0, qla.QLA_V_PAPER, qla.QLA_TRIPLE_BZ, None,
                                  ctypes.byref(out)) == qla.QLA_EINVAL
     assert lib.qla_create_triple(64, 64, 0.25, 0, 0, 7, None, ctypes.byref(out)) == qla.QLA_EINVAL
+    assert lib.qla_create_triple(64, 64, 0.25, 0, qla.QLA_V_BSTREAM, qla.QLA_TRIPLE_BZ, None,
+                                 ctypes.byref(out)) == qla.QLA_EINVAL
     assert lib.qla_divergence(None, None, None, None) == qla.QLA_EINVAL

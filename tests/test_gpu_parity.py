@@ -97,7 +97,7 @@ def test_energy_matches_oracle(qla, prec):
 # ---------------------------------------------------------------------------------------
 # the full step (a3 U_x, a4 U_y, a5 V_x, V_y)
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("vmode", [0, 1, 2])
+@pytest.mark.parametrize("vmode", [0, 1, 2, 3])
 def test_parity_small_workload(qla, prec, vmode):
     """256^2 ellipse, +x packet, 200 steps (the small parity workload), each potential mode."""
     w = workloads.parity_small()
@@ -128,7 +128,7 @@ def test_parity_small_workload(qla, prec, vmode):
 def test_parity_ragged_random(qla, prec, nx, ny, steps, rows, fused):
     n = _random_index(ny, nx, seed=nx * 1000 + ny)
     q = _random_fields((ny, nx), seed=ny)
-    for vmode in (0, 1):
+    for vmode in (0, 1, 3):
         want = oracle.advance(_oracle_state(n, q), n, 0.4, steps, vmode)[2:5]
         with qla.Lattice(nx, ny, 0.4, precision=prec, potential=vmode) as lat:
             qla.qla_set_tuning(lat.ctx, rows, 0, fused)
@@ -148,7 +148,7 @@ def test_parity_large_angles(qla):
     n = 1.0 + 0.5 * (1 + np.sin(2 * np.pi * np.arange(nx) / nx))[None, :] \
         * (1 + np.cos(2 * np.pi * np.arange(ny) / ny))[:, None] / 2
     q = _random_fields((ny, nx), seed=5)
-    for vmode in (0, 1):
+    for vmode in (0, 1, 3):
         want = oracle.advance(_oracle_state(n, q), n, 1.6, 12, vmode)[2:5]
         with qla.Lattice(nx, ny, 1.6, potential=vmode) as lat:
             lat.set_index(n)
