@@ -94,22 +94,38 @@ __device__ __forceinline__ uint4 fetch(const Operand& o, int r0, int k0) {
   return w;
 }
 
-// Stores fetched elements into the k-contiguous LDS tile.
+// LDS tiles hold element (r, k) of an operand at lds[r][col(r, k)]: k-contiguous in
+// groups of 8 (one 16-byte MFMA operand read), with the group index XORed by bits 3-4
+// of the row. Rows are 16-byte aligned, so without the swizzle the transposing stores
+// of row-contiguous operands (rows 8 apart in one instruction) all land in the same
+// LDS banks.
+__device__ __forceinline__ int col(int r, int k) {
+  return ((((k >> 3) ^ (r >> 3)) & 3) << 3) | (k & 7);
+}
+
+// Stores fetched elements into the LDS tile.
 template <int MODE>
 __device__ __forceinline__ void stash(uint16_t (*lds)[kBK + kPad], uint4 w) {
   const int t = threadIdx.x;
   if constexpr (MODE == 0) {
-    *reinterpret_cast<uint4*>(&lds[t >> 2][(t & 3) * 8]) = w;
+    const int r = t >> 2;
+    *reinterpret_cast<uint4*>(&lds[r][col(r, (t & 3) * 8)]) = w;
     return;
   }
   uint16_t v[8];
   __builtin_memcpy(v, &w, 16);
   if constexpr (MODE == 1) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lds[(t & 7) * 8 + i][t >> 3] = v[i];
+    for (int i = 0; i < 8; ++i) {
+      const int r = (t & 7) * 8 + i;
+      lds[r][col(r, t >> 3)] = v[i];
+    }
   } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lds[(t >> 5) + 8 * i][t & 31] = v[i];
+    for (int i = 0; i < 8; ++i) {
+      const int r = (t >> 5) + 8 * i;
+      lds[r][col(r, t & 31)] = v[i];
+    }
   }
 }
 
@@ -241,16 +257,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmDesc g) {
       }
     }
     if (do_rowsum && first) {
-      const uint16_t* row = &As[t >> 2][(t & 3) * 8];
+      const uint16_t* row = &As[t >> 2][(t & 3) * 8];  // all groups of the row, any order
 #pragma unroll
       for (int i = 0; i < 8; ++i) rs += bf16_to_f32(row[i]);
     }
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 16) {
-      const bf16x8 a =
-          *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
-      const bf16x8 bb =
-          *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+      const int ra = wm * 32 + (lane & 31), rb = wn * 32 + (lane & 31);
+      const int kg = kk + 8 * (lane >> 5);
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[ra][col(ra, kg)]);
+      const bf16x8 bb = *reinterpret_cast<const bf16x8*>(&Bs[rb][col(rb, kg)]);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
     }
     __syncthreads();
