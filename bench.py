@@ -34,6 +34,23 @@ METRIC = "lattice-site updates/s (GLUPS) + HBM GB/s; batched/surrogate instances
 POTENTIALS = {"skew_half": 0, "paper": 1, "none": 2, "bstream": 3}
 
 
+def full_tuning(t):
+    """(rows per segment, prefetch rows, steps per pass, columns per lane); the last
+    defaults to 1 where a recorded tuning has only the first three."""
+    t = tuple(int(v) for v in t)
+    return t if len(t) == 4 else t + (1,)
+
+
+def apply_tuning(qla, ctx, tuning):
+    t = full_tuning(tuning)
+    qla.qla_set_tuning(ctx, *t[:3])
+    qla.qla_set_lane_columns(ctx, t[3])
+
+
+def current_tuning(qla, ctx):
+    return tuple(qla.qla_get_tuning(ctx)) + (qla.qla_get_lane_columns(ctx),)
+
+
 def run_job(qla, torch, w, n_dev, prec_code, out_dev, energies, stream_ptr, record_kernel,
             tuning=None, potential=0):
     """The whole job once; returns (ctx, list of (start, end) events around advances).
@@ -44,7 +61,7 @@ def run_job(qla, torch, w, n_dev, prec_code, out_dev, energies, stream_ptr, reco
         if tuning is None:
             qla.qla_autotune(ctx)
         else:
-            qla.qla_set_tuning(ctx, *tuning)
+            apply_tuning(qla, ctx, tuning)
         p = w.packet
         qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
         pairs = []
@@ -79,13 +96,13 @@ def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None, pote
     sp = stream.cuda_stream
     if not sp:
         raise RuntimeError("bench needs a non-default torch stream")
-    tuning = tuple(forced_tuning) if forced_tuning else None
+    tuning = full_tuning(forced_tuning) if forced_tuning else None
     for _ in range(max(1, warmup)):
         ctx, _ = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, False, tuning,
                          potential)
         torch.cuda.synchronize()
         if tuning is None:
-            tuning = qla.qla_get_tuning(ctx)
+            tuning = current_tuning(qla, ctx)
         qla.qla_destroy(ctx)
     times, kernel_ms, drift = [], [], []
     for _ in range(steps):
@@ -111,7 +128,7 @@ def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None, pote
     t = max(times)
     sites = w.nx * w.ny * w.steps
     k_s = sum(kernel_ms) / len(kernel_ms) / 1e3          # seconds per QLA step
-    rows, pf, fused = tuning
+    rows, pf, fused, cols = tuning
     launch_s = k_s * fused                               # one launch applies `fused` steps
     algorithmic = BYTES_PER_SITE[prec] * w.nx * w.ny * fused
     achieved = algorithmic / launch_s / 1e9
@@ -125,6 +142,7 @@ def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None, pote
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (round(traffic / launch_s / 1e9, 1) if traffic else None)},
         "launch": {"steps_per_launch": fused, "rows_per_segment": rows, "prefetch_rows": pf,
+                   "columns_per_lane": cols,
                    "launch_us": round(launch_s * 1e6, 2),
                    "algorithmic_bytes_per_launch": algorithmic,
                    "hbm_bytes_per_launch": traffic},
@@ -156,7 +174,7 @@ def measured_traffic(w, prec, tuning):
     if rec.get("kernel_sha256") != step_kernel_sha() or rec.get("workload") != w.name:
         return None
     r = rec.get(prec)
-    if not r or tuple(r.get("tuning", ())) != tuple(tuning):
+    if not r or full_tuning(r.get("tuning", ())) != full_tuning(tuning):
         return None
     return r["hbm_bytes_per_launch"]
 
@@ -268,7 +286,7 @@ def precision_study(qla, torch, w, snapshot_every):
         qla.qla_set_index_device(c, n_dev, w.nx)
         tun = recorded_tuning(workloads.plain_4096()).get(prec)
         if tun:
-            qla.qla_set_tuning(c, *tun)
+            apply_tuning(qla, c, tun)
         else:
             qla.qla_autotune(c)
         p = w.packet
@@ -624,7 +642,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--save-params", default="")
     ap.add_argument("--tuning-json", default="",
-                    help='fixed tuning instead of autotuning, e.g. {"f64": [176, 3, 2]}')
+                    help='fixed tuning instead of autotuning: per precision, rows per '
+                         'segment, prefetch rows, steps per pass and optionally columns per '
+                         'lane, e.g. {"f64": [176, 3, 2], "f32": [56, 3, 2, 2]}')
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (a reference kernel of "
                          "known traffic for hardware counters)")

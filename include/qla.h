@@ -209,11 +209,21 @@ qla_status qla_step_count(const qla_ctx *ctx, int64_t *steps);
 qla_status qla_set_tuning(qla_ctx *ctx, int rows_per_segment, int prefetch_rows,
                           int steps_per_pass);
 
+/* Lattice columns each lane of the step kernel holds: 1, or 2 (FP32 contexts of
+ * even nx only: a wavefront then covers 128 columns, so fewer of its lanes are
+ * halo, and every load and store moves 8 bytes per lane). Each column goes
+ * through the same arithmetic either way, so results are bitwise the same.
+ * 0 restores the default (1). QLA_EINVAL for other values, for 2 on an FP64
+ * context or on odd nx. */
+qla_status qla_set_lane_columns(qla_ctx *ctx, int columns);
+qla_status qla_get_lane_columns(const qla_ctx *ctx, int *columns);
+
 /* Pick the tuning of the step kernel for this context's lattice by timing
- * candidate segment heights, prefetch depths and steps per pass on it (tens of
- * milliseconds). The state and step counter are saved and restored, so results
- * are unaffected; the chosen values are kept and returned through the non-NULL
- * pointers. Synchronises. QLA_ESTATE if no index is set. */
+ * candidate segment heights, prefetch depths, steps per pass and (FP32, even nx)
+ * columns per lane on it (tens of milliseconds). The state and step counter are
+ * saved and restored, so results are unaffected; the chosen values are kept and
+ * returned through the non-NULL pointers (columns per lane: qla_get_lane_columns).
+ * Synchronises. QLA_ESTATE if no index is set. */
 qla_status qla_autotune(qla_ctx *ctx, int *rows_per_segment, int *prefetch_rows,
                         int *steps_per_pass);
 

@@ -121,13 +121,14 @@ qla_status install_index(qla_ctx* c, const double* src, size_t ld) {
 namespace qla {
 
 // Enqueue k steps on the context's stream with the given tuning (no checks).
-qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused) {
+qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused, int cols) {
   qla::StepLaunch L{};
   L.n = c->fp32 ? static_cast<const void*>(c->n32) : static_cast<const void*>(c->n64);
   L.nx = c->nx;
   L.ny = c->ny;
   L.rows_per_seg = rows;
   L.prefetch = prefetch;
+  L.cols_per_lane = cols;
   L.delta = c->delta;
   L.fp32 = c->fp32;
   L.vmode = c->vmode;
@@ -157,6 +158,7 @@ qla::StepLaunch step_launch_for(const qla_ctx* c, int rows, int prefetch, int fu
   L.rows_per_seg = rows;
   L.prefetch = prefetch;
   L.fused_steps = fused;
+  L.cols_per_lane = 1;
   L.delta = c->delta;
   L.fp32 = c->fp32;
   L.vmode = c->vmode;
@@ -350,7 +352,7 @@ qla_status qla_advance(qla_ctx* c, int64_t k) {
   if (k < 0) return fail(QLA_EINVAL, "k < 0");
   if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
   DeviceGuard g(c->device);
-  return enqueue_steps(c, k, c->rows_per_seg, c->prefetch, c->fused);
+  return enqueue_steps(c, k, c->rows_per_seg, c->prefetch, c->fused, c->cols);
 }
 
 qla_status qla_autotune(qla_ctx* c, int* rows_out, int* prefetch_out, int* steps_per_pass_out) {
@@ -376,36 +378,41 @@ qla_status qla_autotune(qla_ctx* c, int* rows_out, int* prefetch_out, int* steps
   static const int kRows[] = {24, 40, 56, 80, 112, 144, 176, 240, 320, 480, 720};
   static const int kPrefetch[] = {2, 3};
   static const int kFused[] = {1, 2};
+  // two columns per lane only where the kernel has them (FP32, even width)
+  const int max_cols = (c->fp32 && c->nx % 2 == 0) ? 2 : 1;
   double best = 1e300;
-  int brows = c->rows_per_seg, bpf = c->prefetch, bfused = c->fused;
+  int brows = c->rows_per_seg, bpf = c->prefetch, bfused = c->fused, bcols = c->cols;
   qla_status st = QLA_OK;
-  for (int fused : kFused) {
-    for (int pf : kPrefetch) {
-      for (int rows : kRows) {
-        if (rows > c->ny + 8 && rows != kRows[0]) continue;
-        // one warm-up pass, then enough steps for a stable time
-        st = enqueue_steps(c, fused, rows, pf, fused);
-        if (st != QLA_OK) break;
-        const int64_t trial = 8 * fused;
-        he = hipEventRecord(e0, c->stream);
-        if (he == hipSuccess) st = enqueue_steps(c, trial, rows, pf, fused);
-        if (he == hipSuccess && st == QLA_OK) he = hipEventRecord(e1, c->stream);
-        if (he == hipSuccess && st == QLA_OK) he = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (he == hipSuccess && st == QLA_OK) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he != hipSuccess) st = hip_fail(he, "autotune timing");
-        if (st != QLA_OK) break;
-        const double per_step = ms / static_cast<double>(trial);
-        if (per_step < best) {
-          best = per_step;
-          brows = rows;
-          bpf = pf;
-          bfused = fused;
+  for (int cols = 1; cols <= max_cols && st == QLA_OK; ++cols) {
+    for (int fused : kFused) {
+      for (int pf : kPrefetch) {
+        for (int rows : kRows) {
+          if (rows > c->ny + 8 && rows != kRows[0]) continue;
+          // one warm-up pass, then enough steps for a stable time
+          st = enqueue_steps(c, fused, rows, pf, fused, cols);
+          if (st != QLA_OK) break;
+          const int64_t trial = 8 * fused;
+          he = hipEventRecord(e0, c->stream);
+          if (he == hipSuccess) st = enqueue_steps(c, trial, rows, pf, fused, cols);
+          if (he == hipSuccess && st == QLA_OK) he = hipEventRecord(e1, c->stream);
+          if (he == hipSuccess && st == QLA_OK) he = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (he == hipSuccess && st == QLA_OK) he = hipEventElapsedTime(&ms, e0, e1);
+          if (he != hipSuccess) st = hip_fail(he, "autotune timing");
+          if (st != QLA_OK) break;
+          const double per_step = ms / static_cast<double>(trial);
+          if (per_step < best) {
+            best = per_step;
+            brows = rows;
+            bpf = pf;
+            bfused = fused;
+            bcols = cols;
+          }
         }
+        if (st != QLA_OK) break;
       }
       if (st != QLA_OK) break;
     }
-    if (st != QLA_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -419,6 +426,7 @@ qla_status qla_autotune(qla_ctx* c, int* rows_out, int* prefetch_out, int* steps
   c->rows_per_seg = brows;
   c->prefetch = bpf;
   c->fused = bfused;
+  c->cols = bcols;
   if (rows_out) *rows_out = brows;
   if (prefetch_out) *prefetch_out = bpf;
   if (steps_per_pass_out) *steps_per_pass_out = bfused;
@@ -529,6 +537,21 @@ qla_status qla_set_tuning(qla_ctx* c, int rows_per_segment, int prefetch_rows,
   c->rows_per_seg = rows_per_segment ? rows_per_segment : qla::kDefaultRows;
   c->prefetch = prefetch_rows ? prefetch_rows : qla::kDefaultPrefetch;
   c->fused = steps_per_pass ? steps_per_pass : qla::kDefaultFused;
+  return QLA_OK;
+}
+
+qla_status qla_set_lane_columns(qla_ctx* c, int columns) {
+  if (!c) return fail(QLA_EINVAL, "NULL context");
+  if (columns < 0 || columns > 2) return fail(QLA_EINVAL, "columns must be 0 (default), 1 or 2");
+  if (columns == 2 && !c->fp32) return fail(QLA_EINVAL, "two columns per lane need FP32");
+  if (columns == 2 && c->nx % 2 != 0) return fail(QLA_EINVAL, "two columns per lane need even nx");
+  c->cols = columns ? columns : 1;
+  return QLA_OK;
+}
+
+qla_status qla_get_lane_columns(const qla_ctx* c, int* columns) {
+  if (!c || !columns) return fail(QLA_EINVAL, "NULL argument");
+  *columns = c->cols;
   return QLA_OK;
 }
 

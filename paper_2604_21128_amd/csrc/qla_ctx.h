@@ -43,6 +43,7 @@ struct qla_ctx {
   int rows_per_seg = qla::kDefaultRows;
   int prefetch = qla::kDefaultPrefetch;
   int fused = qla::kDefaultFused;
+  int cols = 1;  // lattice columns per lane of the step kernel (2: FP32, even nx only)
   size_t count() const { return static_cast<size_t>(nx) * static_cast<size_t>(ny); }
   size_t elem() const { return fp32 ? sizeof(float) : sizeof(double); }
   // The stored plane holding component j of the ABI order ((q2, q3, q4) or (q0, q1, q5)).
@@ -74,7 +75,7 @@ class DeviceGuard {
 };
 
 // Enqueue k steps of one context with the given tuning (no argument checks).
-qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused);
+qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused, int cols);
 
 // The step launch for one pass of context c: dir 0 reads the current buffer, dir 1
 // the other one.

@@ -60,11 +60,42 @@ constexpr std::array<double, kMaxTerms> kTanC = make_tan_coeffs();
 // The host measures the largest angles when n is set and picks the class.
 enum AngleClass : int { kSmall = 0, kLarge = 1 };
 
+// ---------------------------------------------------------------------------------
+// Two adjacent lattice columns held by one lane (FP32 stepping only). Every operation
+// acts on the two columns alike, so each column goes through exactly the arithmetic
+// of the one-column form and the results are bitwise the same; what changes is that a
+// wavefront covers 128 columns, so its halo columns are a smaller share of the lanes,
+// a lane shift moves one register for two columns, and every load or store moves
+// 8 bytes per lane.
+struct F32Pair {
+  float x, y;
+  F32Pair() = default;
+  __device__ constexpr F32Pair(float a, float b) : x(a), y(b) {}
+  __device__ explicit constexpr F32Pair(double v) : x(float(v)), y(float(v)) {}
+  friend __device__ __forceinline__ F32Pair operator-(F32Pair a) { return {-a.x, -a.y}; }
+  friend __device__ __forceinline__ F32Pair operator+(F32Pair a, F32Pair b) {
+    return {a.x + b.x, a.y + b.y};
+  }
+  friend __device__ __forceinline__ F32Pair operator-(F32Pair a, F32Pair b) {
+    return {a.x - b.x, a.y - b.y};
+  }
+  friend __device__ __forceinline__ F32Pair operator*(F32Pair a, F32Pair b) {
+    return {a.x * b.x, a.y * b.y};
+  }
+  friend __device__ __forceinline__ F32Pair operator*(float a, F32Pair b) {
+    return {a * b.x, a * b.y};
+  }
+  friend __device__ __forceinline__ F32Pair fma(F32Pair a, F32Pair b, F32Pair c) {
+    return {fmaf(a.x, b.x, c.x), fmaf(a.y, b.y, c.y)};
+  }
+};
+
 template <typename T, int C> struct Terms;
 template <> struct Terms<double, kSmall> { static constexpr int kSin = 6, kTan = 6, kCos = 7; };
 template <> struct Terms<double, kLarge> { static constexpr int kSin = 10, kTan = 13, kCos = 11; };
 template <> struct Terms<float, kSmall> { static constexpr int kSin = 3, kTan = 3, kCos = 3; };
 template <> struct Terms<float, kLarge> { static constexpr int kSin = 6, kTan = 7, kCos = 7; };
+template <int C> struct Terms<F32Pair, C> : Terms<float, C> {};
 
 template <typename T, int N>
 __device__ __forceinline__ T odd_series(T x, const std::array<double, kMaxTerms>& c) {
@@ -109,6 +140,7 @@ __device__ __forceinline__ float recip(float v) {
   const float e = fmaf(-v, r, 1.0f);
   return fmaf(r, e, r);
 }
+__device__ __forceinline__ F32Pair recip(F32Pair v) { return {recip(v.x), recip(v.y)}; }
 
 // ---------------------------------------------------------------------------------
 // A rotation R(phi): a' = cos(phi) a - sin(phi) p, p' = sin(phi) a + cos(phi) p,
@@ -168,6 +200,10 @@ __device__ __forceinline__ float from_left(float v) {
 __device__ __forceinline__ float from_right(float v) {
   return __builtin_bit_cast(float, dpp_from_right(__builtin_bit_cast(int, v)));
 }
+// A lane holding columns (2l, 2l+1): the left neighbour of column 2l is column 2l-1,
+// the second of lane l-1; the right neighbour of column 2l+1 is the first of lane l+1.
+__device__ __forceinline__ F32Pair from_left(F32Pair v) { return {from_left(v.y), v.x}; }
+__device__ __forceinline__ F32Pair from_right(F32Pair v) { return {v.y, from_right(v.x)}; }
 __device__ __forceinline__ double from_left(double v) {
   const long long b = __builtin_bit_cast(long long, v);
   const int lo = dpp_from_left(int(b));

@@ -20,6 +20,7 @@ struct StepLaunch {
   int rows_per_seg;  // requested output rows per wavefront segment (rounded up)
   int prefetch;      // rows the loads run ahead: 2 or 3
   int fused_steps;   // steps applied per pass: 1 or 2
+  int cols_per_lane;  // lattice columns per lane: 1, or 2 (FP32, even nx)
   double delta;
   bool fp32;
   int vmode;

@@ -32,9 +32,10 @@
 // and the SKEW_HALF potentials are the same rotations as above. The sign of th comes
 // with the launch arguments; the planes are passed as (a, p_y, p_x).
 //
-// Mapping to the machine. A wavefront owns a strip of 56 output columns and a
-// segment of output rows. Its 64 lanes hold columns x0-4 .. x0+59 (4 halo columns
-// each side, periodic wrap), one column per lane. The wave marches down the rows:
+// Mapping to the machine. A wavefront owns a strip of output columns and a segment
+// of output rows. Its 64 lanes hold consecutive columns, one per lane (or, in FP32
+// on lattices of even width, two per lane: 128 columns), with 4 halo columns per
+// step each side (periodic wrap). The wave marches down the rows:
 //   - each incoming row gets U_x across the lanes, with the neighbour values
 //     taken by DPP lane shifts (no LDS, no barriers);
 //   - U_y runs down the rows inside each lane as a software pipeline: when row r
@@ -49,6 +50,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <type_traits>
 #include <utility>
 
 #include "qla_device.h"
@@ -89,6 +91,20 @@ __device__ __forceinline__ unsigned long long lane0_bits(double v) {
 __device__ __forceinline__ unsigned long long lane0_bits(float v) {
   return __builtin_amdgcn_readfirstlane(__builtin_bit_cast(unsigned, v));
 }
+__device__ __forceinline__ unsigned long long lane0_bits(F32Pair v) { return lane0_bits(v.x); }
+// Does this lane hold a value other than the bit pattern b?
+template <typename V>
+__device__ __forceinline__ bool differs(V v, unsigned long long b) {
+  return bits_of(v) != b;
+}
+template <>
+__device__ __forceinline__ bool differs(F32Pair v, unsigned long long b) {
+  return (bits_of(v.x) != b) | (bits_of(v.y) != b);
+}
+
+// The value a lane holds: one column of T, or two FP32 columns.
+template <typename T, int CPL> struct LaneOf { using type = T; };
+template <> struct LaneOf<float, 2> { using type = F32Pair; };
 
 template <typename T>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
@@ -134,14 +150,16 @@ struct StepArgs {
 // share one window: a row keeps its slot from its load until its store. Each
 // stage widens the dependence by 4 cells in x and y, so a pass has 4 TS halo
 // columns on each side of the strip and 4 TS halo rows at each end of a segment.
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL>
 struct Marcher {
   static_assert(PF + 4 * TS + 2 <= kWin, "a prefetched row must not overwrite a live one");
+  using V = typename LaneOf<T, CPL>::type;
+  static_assert(sizeof(V) == CPL * sizeof(T), "one or two columns per lane");
   // B streaming: every set streams the B-qubit, so each neighbour pair takes the angle
   // of its a site, and there are no potentials
   static constexpr bool kBStream = VMODE == kVBStream;
   // Row window: amplitudes, index, 1/n and the collision shear of each row.
-  T A[kWin], P4[kWin], P3[kWin], N[kWin], M[kWin], Tt[kWin], Ts[kWin];
+  V A[kWin], P4[kWin], P3[kWin], N[kWin], M[kWin], Tt[kWin], Ts[kWin];
   // Per-row wave-uniform facts, one bit per slot in scalar registers: umask bit s
   // says all 64 lanes of the row in slot s hold the same n; emask bit s says so
   // and that this n equals the previous row's (also uniform) n. In a uniform row
@@ -151,7 +169,7 @@ struct Marcher {
   unsigned umask, emask;
   unsigned long long nb_prev;  // n's bit pattern in lane 0 of the previous row
   __amdgpu_buffer_rsrc_t r2i, r3i, r4i, rn, r2o, r3o, r4o;
-  unsigned col_bytes;    // this lane's column (wrapped) in bytes
+  unsigned col_bytes;    // this lane's (first) column (wrapped) in bytes
   unsigned store_bytes;  // col_bytes for lanes that own an output column, else kDropOffset
   unsigned row_bytes;    // nx * sizeof(T)
   int yin;               // row index of the next row to load (wrapped)
@@ -162,10 +180,10 @@ struct Marcher {
   // lane adds its fixed column offset.
   __device__ __forceinline__ void load_row(int s, int y) {
     const unsigned soff = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(y)) * row_bytes;
-    A[s] = buf_load<T>(r2i, col_bytes, soff);
-    P3[s] = buf_load<T>(r3i, col_bytes, soff);
-    P4[s] = buf_load<T>(r4i, col_bytes, soff);
-    N[s] = buf_load<T>(rn, col_bytes, soff);
+    A[s] = buf_load<V>(r2i, col_bytes, soff);
+    P3[s] = buf_load<V>(r3i, col_bytes, soff);
+    P4[s] = buf_load<V>(r4i, col_bytes, soff);
+    N[s] = buf_load<V>(rn, col_bytes, soff);
   }
 
   // U_x on one row (slot s): lanes exchange neighbour values by DPP. In a
@@ -179,14 +197,14 @@ struct Marcher {
     }
   }
 
-  __device__ __forceinline__ void ux_with(int s, T tl, T sl, T tr, T sr) {
-    T a = A[s], p = P4[s];
-    const T t0 = Tt[s], s0 = Ts[s];
+  __device__ __forceinline__ void ux_with(int s, V tl, V sl, V tr, V sr) {
+    V a = A[s], p = P4[s];
+    const V t0 = Tt[s], s0 = Ts[s];
     // set 1: C^T on site; C(th_i) on (a_i, p_{i-1})
     rotate(a, p, -t0, -s0);
     {
-      const T pm = from_left(p), ap = from_right(a);
-      const T an = rotate_first(a, pm, t0, s0);
+      const V pm = from_left(p), ap = from_right(a);
+      const V an = rotate_first(a, pm, t0, s0);
       p = rotate_second(ap, p, tr, sr);
       a = an;
     }
@@ -194,16 +212,16 @@ struct Marcher {
     // set 1 (the pair takes the angle of its a site)
     rotate(a, p, -t0, -s0);
     {
-      const T pm = from_left(p), ap = from_right(a);
-      const T an = kBStream ? rotate_first(a, pm, t0, s0) : rotate_first(a, pm, tl, sl);
+      const V pm = from_left(p), ap = from_right(a);
+      const V an = kBStream ? rotate_first(a, pm, t0, s0) : rotate_first(a, pm, tl, sl);
       p = kBStream ? rotate_second(ap, p, tr, sr) : rotate_second(ap, p, t0, s0);
       a = an;
     }
     // set 3: C on site; C^T(th_i) on (a_i, p_{i+1})
     rotate(a, p, t0, s0);
     {
-      const T pp = from_right(p), am = from_left(a);
-      const T an = rotate_first(a, pp, -t0, -s0);
+      const V pp = from_right(p), am = from_left(a);
+      const V an = rotate_first(a, pp, -t0, -s0);
       p = rotate_second(am, p, -tl, -sl);
       a = an;
     }
@@ -211,8 +229,8 @@ struct Marcher {
     // set 3
     rotate(a, p, t0, s0);
     {
-      const T pp = from_right(p), am = from_left(a);
-      const T an = kBStream ? rotate_first(a, pp, -t0, -s0) : rotate_first(a, pp, -tr, -sr);
+      const V pp = from_right(p), am = from_left(a);
+      const V an = kBStream ? rotate_first(a, pp, -t0, -s0) : rotate_first(a, pp, -tr, -sr);
       p = kBStream ? rotate_second(am, p, -tl, -sl) : rotate_second(am, p, -t0, -s0);
       a = an;
     }
@@ -252,21 +270,21 @@ struct Marcher {
     } else {
       constexpr int sc = SC, sup = slot(SC, -1), sdn = slot(SC, 1);
       if ((emask & (1u << sc)) && (emask & (1u << sup))) return;
-      const T m = M[sc];
-      const T dm = d4 * m * m;
-      const T nl = from_left(N[sc]), nr = from_right(N[sc]);
-      const T hbx = (nr - nl) * dm;          // beta_x / 2
-      const T hby = (N[sup] - N[sdn]) * dm;  // beta_y / 2
+      const V m = M[sc];
+      const V dm = d4 * m * m;
+      const V nl = from_left(N[sc]), nr = from_right(N[sc]);
+      const V hbx = (nr - nl) * dm;          // beta_x / 2
+      const V hby = (N[sup] - N[sdn]) * dm;  // beta_y / 2
       if constexpr (VMODE == kVSkewHalf) {
-        const Shear<T> vx = shear_of<T, CLS>(hbx);
+        const Shear<V> vx = shear_of<V, CLS>(hbx);
         rotate(A[sc], P4[sc], -vx.t, -vx.s);
-        const Shear<T> vy = shear_of<T, CLS>(hby);
+        const Shear<V> vy = shear_of<V, CLS>(hby);
         rotate(A[sc], P3[sc], vy.t, vy.s);
       } else {
-        const T bx = hbx + hbx, by = hby + hby;
-        const T sbx = sin_series<T, CLS>(bx), cbx = cos_series<T, CLS>(bx);
+        const V bx = hbx + hbx, by = hby + hby;
+        const V sbx = sin_series<V, CLS>(bx), cbx = cos_series<V, CLS>(bx);
         P4[sc] = fma(-sbx, A[sc], cbx * P4[sc]);
-        const T sby = sin_series<T, CLS>(by), cby = cos_series<T, CLS>(by);
+        const V sby = sin_series<V, CLS>(by), cby = cos_series<V, CLS>(by);
         P3[sc] = fma(sby, A[sc], cby * P3[sc]);
       }
     }
@@ -292,7 +310,7 @@ struct Marcher {
     // collision shear and 1/n are reused; otherwise they are computed.
     constexpr int sprev = slot(S0, 1);
     const unsigned long long nb = lane0_bits(N[S0]);
-    const bool uni = __builtin_amdgcn_ballot_w64(bits_of(N[S0]) != nb) == 0;
+    const bool uni = __builtin_amdgcn_ballot_w64(differs(N[S0], nb)) == 0;
     const bool same = uni && (umask & (1u << sprev)) && nb == nb_prev;
     umask = (umask & ~(1u << S0)) | (uni ? 1u << S0 : 0u);
     emask = (emask & ~(1u << S0)) | (same ? 1u << S0 : 0u);
@@ -302,9 +320,9 @@ struct Marcher {
       Tt[S0] = Tt[sprev];
       Ts[S0] = Ts[sprev];
     } else {
-      const T m = recip(N[S0]);
+      const V m = recip(N[S0]);
       M[S0] = m;
-      const Shear<T> c = shear_of<T, CLS>(g.dc * m);
+      const Shear<V> c = shear_of<V, CLS>(g.dc * m);
       Tt[S0] = c.t;
       Ts[S0] = c.s;
     }
@@ -316,22 +334,27 @@ struct Marcher {
     const bool row_ok = yo >= y0 && yo < yend;
     const unsigned soff = row_ok ? static_cast<unsigned>(yo) * row_bytes : 0u;
     const unsigned voff = row_ok ? store_bytes : kDropOffset;
-    buf_store<T>(A[sout], r2o, voff, soff);
-    buf_store<T>(P3[sout], r3o, voff, soff);
-    buf_store<T>(P4[sout], r4o, voff, soff);
+    buf_store<V>(A[sout], r2o, voff, soff);
+    buf_store<V>(P3[sout], r3o, voff, soff);
+    buf_store<V>(P4[sout], r4o, voff, soff);
   }
 };
 
-// One wavefront's work: the tile (strip, seg) of one pass over the lattice of g.
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
+// One wavefront's work: the tile (strip, seg) of one pass over the lattice of g. With
+// two columns per lane the width is even (checked on the host), so a lane's pair
+// (col, col + 1) never straddles the periodic wrap and lies wholly inside or outside
+// the strip's output columns.
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL>
 __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, int lane) {
   constexpr int halo = 4 * TS;
-  constexpr int strip_cols = kWave - 2 * halo;
-  Marcher<T, VMODE, CLS, kWin, PF, TS> w;
+  constexpr int strip_cols = kWave * CPL - 2 * halo;
+  Marcher<T, VMODE, CLS, kWin, PF, TS, CPL> w;
+  using V = typename Marcher<T, VMODE, CLS, kWin, PF, TS, CPL>::V;
   const int x0 = strip * strip_cols;
-  int col = (x0 - halo + lane) % g.nx;
+  const int c = CPL * lane - halo;  // the lane's first column, relative to the strip
+  int col = (x0 + c) % g.nx;
   if (col < 0) col += g.nx;
-  const bool store_lane = lane >= halo && lane < halo + strip_cols && x0 + lane - halo < g.nx;
+  const bool store_lane = c >= 0 && c < strip_cols && x0 + c < g.nx;
   w.col_bytes = static_cast<unsigned>(col) * sizeof(T);
   w.store_bytes = store_lane ? w.col_bytes : kDropOffset;
   w.row_bytes = static_cast<unsigned>(g.nx) * sizeof(T);
@@ -346,7 +369,7 @@ __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, 
   const int yend = min(y0 + g.rows_per_seg, g.ny);
 #pragma unroll
   for (int k = 0; k < kWin; ++k) {
-    w.A[k] = w.P4[k] = w.P3[k] = w.N[k] = w.M[k] = w.Tt[k] = w.Ts[k] = T(0);
+    w.A[k] = w.P4[k] = w.P3[k] = w.N[k] = w.M[k] = w.Tt[k] = w.Ts[k] = V(T(0));
   }
   w.umask = 0;
   w.emask = 0;
@@ -361,9 +384,9 @@ __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, 
   for (int k = 0; k < PF; ++k) {
     w.load_row(k, y);
     y = (y + 1 == g.ny) ? 0 : y + 1;
-    buf_store<T>(T(0), w.r2o, kDropOffset, 0u);
-    buf_store<T>(T(0), w.r3o, kDropOffset, 0u);
-    buf_store<T>(T(0), w.r4o, kDropOffset, 0u);
+    buf_store<V>(V(T(0)), w.r2o, kDropOffset, 0u);
+    buf_store<V>(V(T(0)), w.r3o, kDropOffset, 0u);
+    buf_store<V>(V(T(0)), w.r4o, kDropOffset, 0u);
   }
   w.yin = y;
 
@@ -374,7 +397,7 @@ __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, 
   }
 }
 
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(StepArgs<T> g) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
@@ -383,7 +406,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
   const int seg = blk / blocks_per_seg;
   const int strip = (blk % blocks_per_seg) * kWavesPerBlock + wib;
   if (seg >= g.segs || strip >= g.strips) return;  // whole wave exits together
-  march<T, VMODE, CLS, kWin, PF, TS>(g, strip, seg, lane);
+  march<T, VMODE, CLS, kWin, PF, TS, CPL>(g, strip, seg, lane);
 }
 
 // Batched passes. `args` holds two entries per instance (parity 0: the buffer that
@@ -408,14 +431,14 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_batch_kernel(
     const int tile = static_cast<int>(code & 0xFFFFFu);
     const int par = __builtin_amdgcn_readfirstlane(parity[inst]);
     const StepArgs<T> g = args[2 * inst + ((p + par) & 1)];
-    march<T, VMODE, CLS, kWin, PF, TS>(g, tile % g.strips, tile / g.strips, lane);
+    march<T, VMODE, CLS, kWin, PF, TS, 1>(g, tile % g.strips, tile / g.strips, lane);
   }
 }
 
-template <typename T, int kWin, int TS>
+template <typename T, int kWin, int TS, int CPL>
 StepArgs<T> make_args(const StepLaunch& L) {
   constexpr int halo = 4 * TS;
-  constexpr int strip_cols = kWave - 2 * halo;
+  constexpr int strip_cols = kWave * CPL - 2 * halo;
   StepArgs<T> g;
   g.q2i = static_cast<const T*>(L.in[0]);
   g.q3i = static_cast<const T*>(L.in[1]);
@@ -438,61 +461,71 @@ StepArgs<T> make_args(const StepLaunch& L) {
   return g;
 }
 
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL>
 hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
-  const StepArgs<T> g = make_args<T, kWin, TS>(L);
+  const StepArgs<T> g = make_args<T, kWin, TS, CPL>(L);
   const int blocks_per_seg = (g.strips + kWavesPerBlock - 1) / kWavesPerBlock;
   const int blocks = blocks_per_seg * g.segs;
-  hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF, TS>), dim3(blocks),
+  hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF, TS, CPL>), dim3(blocks),
                      dim3(kWave * kWavesPerBlock), 0, stream, g);
   return hipGetLastError();
 }
 
-// Calls f.template operator()<T, VMODE, CLS, kWin, PF, TS>() for the compiled variant
-// that matches the runtime choices. Window depth: the smallest that keeps every
-// live row (PF + 4 TS + 2 rows).
-template <typename T, int VMODE, int CLS, typename F>
-auto with_shape(int prefetch, int fused, F&& f) {
+// Calls f.template operator()<T, VMODE, CLS, kWin, PF, TS, CPL>() for the compiled
+// variant that matches the runtime choices. Window depth: the smallest that keeps
+// every live row (PF + 4 TS + 2 rows).
+template <typename T, int VMODE, int CLS, int CPL, typename F>
+auto with_depth(int prefetch, int fused, F&& f) {
   if (fused == 2) {
-    return prefetch == 2 ? f.template operator()<T, VMODE, CLS, 12, 2, 2>()
-                         : f.template operator()<T, VMODE, CLS, 13, 3, 2>();
+    return prefetch == 2 ? f.template operator()<T, VMODE, CLS, 12, 2, 2, CPL>()
+                         : f.template operator()<T, VMODE, CLS, 13, 3, 2, CPL>();
   }
-  return prefetch == 2 ? f.template operator()<T, VMODE, CLS, 8, 2, 1>()
-                       : f.template operator()<T, VMODE, CLS, 9, 3, 1>();
+  return prefetch == 2 ? f.template operator()<T, VMODE, CLS, 8, 2, 1, CPL>()
+                       : f.template operator()<T, VMODE, CLS, 9, 3, 1, CPL>();
 }
 
-template <typename T, typename F>
-auto with_variant(int vmode, int angle_class, int prefetch, int fused, F&& f) {
+// Two columns per lane exist for FP32 single-lattice launches (kPairs) only.
+template <typename T, bool kPairs, int VMODE, int CLS, typename F>
+auto with_shape(int prefetch, int fused, int cols, F&& f) {
+  if constexpr (kPairs && std::is_same_v<T, float>) {
+    if (cols == 2) return with_depth<T, VMODE, CLS, 2>(prefetch, fused, f);
+  }
+  return with_depth<T, VMODE, CLS, 1>(prefetch, fused, f);
+}
+
+template <typename T, bool kPairs, typename F>
+auto with_variant(int vmode, int angle_class, int prefetch, int fused, int cols, F&& f) {
   const bool large = angle_class == kLarge;
   switch (vmode) {
     case kVSkewHalf:
-      return large ? with_shape<T, kVSkewHalf, kLarge>(prefetch, fused, f)
-                   : with_shape<T, kVSkewHalf, kSmall>(prefetch, fused, f);
+      return large ? with_shape<T, kPairs, kVSkewHalf, kLarge>(prefetch, fused, cols, f)
+                   : with_shape<T, kPairs, kVSkewHalf, kSmall>(prefetch, fused, cols, f);
     case kVPaper:
-      return large ? with_shape<T, kVPaper, kLarge>(prefetch, fused, f)
-                   : with_shape<T, kVPaper, kSmall>(prefetch, fused, f);
+      return large ? with_shape<T, kPairs, kVPaper, kLarge>(prefetch, fused, cols, f)
+                   : with_shape<T, kPairs, kVPaper, kSmall>(prefetch, fused, cols, f);
     case kVBStream:
-      return large ? with_shape<T, kVBStream, kLarge>(prefetch, fused, f)
-                   : with_shape<T, kVBStream, kSmall>(prefetch, fused, f);
+      return large ? with_shape<T, kPairs, kVBStream, kLarge>(prefetch, fused, cols, f)
+                   : with_shape<T, kPairs, kVBStream, kSmall>(prefetch, fused, cols, f);
     default:
-      return large ? with_shape<T, kVNone, kLarge>(prefetch, fused, f)
-                   : with_shape<T, kVNone, kSmall>(prefetch, fused, f);
+      return large ? with_shape<T, kPairs, kVNone, kLarge>(prefetch, fused, cols, f)
+                   : with_shape<T, kPairs, kVNone, kSmall>(prefetch, fused, cols, f);
   }
 }
 
 template <typename T>
 hipError_t launch_prec(const StepLaunch& L, hipStream_t stream) {
-  return with_variant<T>(L.vmode, L.angle_class, L.prefetch, L.fused_steps,
-                         [&]<typename U, int VM, int CL, int W, int PF, int TS>() {
-                           return launch_typed<U, VM, CL, W, PF, TS>(L, stream);
-                         });
+  return with_variant<T, true>(
+      L.vmode, L.angle_class, L.prefetch, L.fused_steps, L.cols_per_lane,
+      [&]<typename U, int VM, int CL, int W, int PF, int TS, int CPL>() {
+        return launch_typed<U, VM, CL, W, PF, TS, CPL>(L, stream);
+      });
 }
 
 template <typename T>
 hipError_t launch_batch_prec(const BatchLaunch& B, hipStream_t stream) {
-  return with_variant<T>(
-      B.vmode, B.angle_class, B.prefetch, B.fused,
-      [&]<typename U, int VM, int CL, int W, int PF, int TS>() -> hipError_t {
+  return with_variant<T, false>(
+      B.vmode, B.angle_class, B.prefetch, B.fused, 1,
+      [&]<typename U, int VM, int CL, int W, int PF, int TS, int CPL>() -> hipError_t {
         auto kern = qla_batch_kernel<U, VM, CL, W, PF, TS>;
         const StepArgs<U>* args = static_cast<const StepArgs<U>*>(B.args);
         const unsigned* items = B.items;
@@ -506,9 +539,9 @@ hipError_t launch_batch_prec(const BatchLaunch& B, hipStream_t stream) {
 
 template <typename T>
 hipError_t batch_blocks_prec(const BatchLaunch& B, int* blocks) {
-  return with_variant<T>(
-      B.vmode, B.angle_class, B.prefetch, B.fused,
-      [&]<typename U, int VM, int CL, int W, int PF, int TS>() -> hipError_t {
+  return with_variant<T, false>(
+      B.vmode, B.angle_class, B.prefetch, B.fused, 1,
+      [&]<typename U, int VM, int CL, int W, int PF, int TS, int CPL>() -> hipError_t {
         int per_cu = 0, cus = 0, dev = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu, qla_batch_kernel<U, VM, CL, W, PF, TS>, kWave * kWavesPerBlock, 0);
@@ -522,15 +555,16 @@ hipError_t batch_blocks_prec(const BatchLaunch& B, int* blocks) {
       });
 }
 
+// Batch tables: one column per lane (instances of odd width share the kernel).
 template <typename T>
 void fill_args_prec(const StepLaunch& L, void* dst, int* tiles) {
-  with_variant<T>(L.vmode, L.angle_class, L.prefetch, L.fused_steps,
-                  [&]<typename U, int VM, int CL, int W, int PF, int TS>() {
-                    const StepArgs<U> g = make_args<U, W, TS>(L);
-                    std::memcpy(dst, &g, sizeof(g));
-                    *tiles = g.strips * g.segs;
-                    return 0;
-                  });
+  with_variant<T, false>(L.vmode, L.angle_class, L.prefetch, L.fused_steps, 1,
+                         [&]<typename U, int VM, int CL, int W, int PF, int TS, int CPL>() {
+                           const StepArgs<U> g = make_args<U, W, TS, 1>(L);
+                           std::memcpy(dst, &g, sizeof(g));
+                           *tiles = g.strips * g.segs;
+                           return 0;
+                         });
 }
 
 }  // namespace

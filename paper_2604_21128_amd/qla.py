@@ -30,7 +30,8 @@ EXPORTED = (
     "qla_set_index", "qla_set_index_device", "qla_init_packet",
     "qla_set_fields", "qla_advance", "qla_get_fields", "qla_get_fields_device",
     "qla_energy", "qla_energy_device", "qla_get_coefficients", "qla_step_count",
-    "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_destroy", "qla_strerror",
+    "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_set_lane_columns",
+    "qla_get_lane_columns", "qla_destroy", "qla_strerror",
     "qla_last_error", "qla_batch_create", "qla_batch_context", "qla_batch_plan", "qla_batch_run",
     "qla_batch_plan_info", "qla_batch_destroy", "qla_fno_create", "qla_fno_destroy",
     "qla_fno_param_count", "qla_fno_get_params", "qla_fno_set_params", "qla_fno_get_grads",
@@ -93,6 +94,8 @@ def load(path: str = LIB_PATH):
                               ctypes.POINTER(ctypes.c_int)]),
         "qla_get_tuning": (st, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int)]),
+        "qla_set_lane_columns": (st, [vp, ctypes.c_int]),
+        "qla_get_lane_columns": (st, [vp, ctypes.POINTER(ctypes.c_int)]),
         "qla_destroy": (st, [vp]),
         "qla_batch_create": (st, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_int), dp, ctypes.c_int, ctypes.c_int,
@@ -276,6 +279,18 @@ def qla_get_tuning(ctx: int):
     _check(load().qla_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(r), ctypes.byref(p),
                                  ctypes.byref(t)), "qla_get_tuning")
     return r.value, p.value, t.value
+
+
+def qla_set_lane_columns(ctx: int, columns: int = 0) -> None:
+    _check(load().qla_set_lane_columns(ctypes.c_void_p(ctx), int(columns)),
+           "qla_set_lane_columns")
+
+
+def qla_get_lane_columns(ctx: int) -> int:
+    v = ctypes.c_int()
+    _check(load().qla_get_lane_columns(ctypes.c_void_p(ctx), ctypes.byref(v)),
+           "qla_get_lane_columns")
+    return v.value
 
 
 def qla_batch_create(nx, ny, delta, precision: int = QLA_F32,

@@ -141,8 +141,9 @@ def paper_16384() -> Workload:
     """The paper's own 2D lattice (Section V): 16384^2, an elliptical dielectric n = 3 in
     vacuum. The paper gives the ellipse as 1600 x 716 and its boundary layer as 40 x 18
     cells; read here as full axes (semi-axes 800 and 358) with a tanh edge of 20 cells.
-    Packet wavelength 100 cells as in the paper; sigma 150 and the start 4 sigma left of
-    the ellipse's edge are this build's choices. 20000 steps, energy every 1000."""
+    Packet wavelength 100 cells as in the paper, which gives neither a width nor a start:
+    sigma 150 and a start 4 sigma left of the ellipse's edge are chosen here. 20000 steps,
+    energy every 1000."""
     return Workload(
         name="qla_16384_ellipse_20000", nx=16384, ny=16384, delta=DELTA,
         ellipse=Ellipse(8192.0, 8192.0, 800.0, 358.0, 0.0, 3.0, 1.0, 20.0),
