@@ -1,0 +1,89 @@
+"""Parity at the full sizes of the 8192^2 bubble and the 16384^2 paper lattice, in the
+launch configuration the autotuner picks (as the benchmark runs them).
+
+The oracle cannot step these lattices whole, so the GPU result is checked on windows
+whose centre the oracle computes exactly: after s steps an amplitude depends only on
+inputs within 4 s cells along each axis, so the oracle run on a periodic window of
+the same inputs is exact more than 4 s + 1 cells inside its edges. Windows sit on the
+dielectric's edge (strong gradients), on the periodic corners and on tile boundaries.
+Fields are random everywhere (seeded), so every tile does real work. Tolerances as
+for the small lattices: relative L2 <= 1e-12 (FP64) and <= 1e-5 (FP32).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+STEPS = 12
+
+
+@pytest.fixture(scope="module")
+def qla():
+    from paper_2604_21128_amd import qla as q
+    q.load()
+    return q
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _windows(qla, w, prec, centres, seed, cols=None):
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    rng = np.random.default_rng(seed)
+    q = rng.standard_normal((3, w.ny, w.nx), dtype=np.float32).astype(np.float64)
+    with qla.Lattice(w.nx, w.ny, w.delta, precision=prec) as lat:
+        lat.set_index(n)
+        lat.set_fields(q)
+        tuning = qla.qla_autotune(lat.ctx)
+        if cols is not None:
+            qla.qla_set_lane_columns(lat.ctx, cols)
+        used = (tuning, qla.qla_get_lane_columns(lat.ctx))
+        lat.advance(STEPS)
+        got = lat.fields()
+    margin = 4 * STEPS + 2
+    half = margin + 10
+    worst = 0.0
+    for cx, cy in centres:
+        ys = np.arange(cy - half, cy + half + 1) % w.ny
+        xs = np.arange(cx - half, cx + half + 1) % w.nx
+        nw = np.ascontiguousarray(n[np.ix_(ys, xs)])
+        qw = np.zeros((6,) + nw.shape)
+        qw[2:5] = q[:, ys][:, :, xs]
+        out = oracle.advance(qw, nw, w.delta, STEPS)[2:5]
+        inner = slice(margin, 2 * half + 1 - margin)
+        err = rel_l2(got[:, ys[inner]][:, :, xs[inner]], out[:, inner, inner])
+        print(f"{w.name} prec={prec} tuning={used} window=({cx},{cy}) rel_l2={err:.3e}",
+              flush=True)
+        worst = max(worst, err)
+    return worst
+
+
+def _centres(w):
+    e = w.ellipse
+    return [(int(e.xc - e.a), int(e.yc)),              # left vertex: strong x gradient
+            (int(e.xc), int(e.yc - e.b)),              # bottom co-vertex: strong y gradient
+            (int(e.xc + 0.71 * e.a), int(e.yc + 0.71 * e.b)),
+            (0, 0), (w.nx - 1, w.ny - 1),              # periodic corners
+            (112 * 37, 179 * 11), (48 * 61, 56 * 90)]  # strip and segment seams
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_parity_8192_bubble_windows(qla, prec):
+    w = workloads.bubble_8192()
+    assert _windows(qla, w, prec, _centres(w), seed=81) <= TOL[prec]
+
+
+def test_parity_8192_bubble_windows_two_columns(qla):
+    w = workloads.bubble_8192()
+    assert _windows(qla, w, 1, _centres(w), seed=82, cols=2) <= TOL[1]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_parity_16384_paper_windows(qla, prec):
+    w = workloads.paper_16384()
+    assert _windows(qla, w, prec, _centres(w), seed=163) <= TOL[prec]
