@@ -284,11 +284,7 @@ def precision_study(qla, torch, w, snapshot_every):
     for prec, code in (("f64", qla.QLA_F64), ("f32", qla.QLA_F32)):
         c = qla.qla_create(w.nx, w.ny, w.delta, code, qla.QLA_V_SKEW_HALF, sp)
         qla.qla_set_index_device(c, n_dev, w.nx)
-        tun = recorded_tuning(workloads.plain_4096()).get(prec)
-        if tun:
-            apply_tuning(qla, c, tun)
-        else:
-            qla.qla_autotune(c)
+        qla.qla_autotune(c)   # tuned for this lattice (state kept)
         p = w.packet
         qla.qla_init_packet(c, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
         ctxs[prec] = c
@@ -314,11 +310,14 @@ def precision_study(qla, torch, w, snapshot_every):
                       "energy_drift_f64": ed["f64"], "energy_drift_f32": ed["f32"]})
         print(f"[study] step {step}: f32 vs f64 rel L2 {err:.3e}, drift f64 {ed['f64']:.2e} "
               f"f32 {ed['f32']:.2e}", file=sys.stderr, flush=True)
+    tunings = {k: current_tuning(qla, c) for k, c in ctxs.items()}
     for c in ctxs.values():
         qla.qla_destroy(c)
     sites = w.nx * w.ny * w.steps
     return {"workload": w.name, "nx": w.nx, "ny": w.ny, "qla_steps": w.steps,
             "snapshot_every": snapshot_every,
+            "tuning": {k: dict(zip(("rows_per_segment", "prefetch_rows", "steps_per_pass",
+                                    "columns_per_lane"), t)) for k, t in tunings.items()},
             "glups": {k: sites / v / 1e9 for k, v in t_run.items()},
             "seconds": t_run, "snapshots": snaps}
 

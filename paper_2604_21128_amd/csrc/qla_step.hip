@@ -115,21 +115,22 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, u
   }
 }
 
-// Stores carry the non-temporal cache policy (the NT bit of gfx94x/gfx950 buffer
-// instructions): a pass's output is next read by the following pass, long after it
-// has left the caches, while the rows this pass loads are re-read by neighbouring
-// tiles (halo rows and columns) and are worth keeping. Measured 1-4% faster.
-constexpr int kStorePolicy = 2;
+// Cache policy of the amplitude stores. A single lattice's pass writes state that is
+// next read by the following pass, long after it has left the caches, while the rows
+// the pass loads are re-read by neighbouring tiles (halo rows and columns): its stores
+// are non-temporal (the NT bit of gfx94x/gfx950 buffer instructions), measured 1-4%
+// faster on 4096^2-16384^2 lattices and even on 1024^2-3072^2. The batched kernel
+// measured 12% slower with them, so its stores keep the default policy.
+constexpr int kStoreNonTemporal = 2;
+constexpr int kStoreDefault = 0;
 
-template <typename T>
+template <typename T, int SP = kStoreDefault>
 __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, unsigned voff,
                                           unsigned soff) {
   if constexpr (sizeof(T) == 8) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff,
-                                          kStorePolicy);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, SP);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff,
-                                          kStorePolicy);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, SP);
   }
 }
 
@@ -158,7 +159,7 @@ struct StepArgs {
 // share one window: a row keeps its slot from its load until its store. Each
 // stage widens the dependence by 4 cells in x and y, so a pass has 4 TS halo
 // columns on each side of the strip and 4 TS halo rows at each end of a segment.
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL, int SP>
 struct Marcher {
   static_assert(PF + 4 * TS + 2 <= kWin, "a prefetched row must not overwrite a live one");
   using V = typename LaneOf<T, CPL>::type;
@@ -342,9 +343,9 @@ struct Marcher {
     const bool row_ok = yo >= y0 && yo < yend;
     const unsigned soff = row_ok ? static_cast<unsigned>(yo) * row_bytes : 0u;
     const unsigned voff = row_ok ? store_bytes : kDropOffset;
-    buf_store<V>(A[sout], r2o, voff, soff);
-    buf_store<V>(P3[sout], r3o, voff, soff);
-    buf_store<V>(P4[sout], r4o, voff, soff);
+    buf_store<V, SP>(A[sout], r2o, voff, soff);
+    buf_store<V, SP>(P3[sout], r3o, voff, soff);
+    buf_store<V, SP>(P4[sout], r4o, voff, soff);
   }
 };
 
@@ -352,12 +353,12 @@ struct Marcher {
 // two columns per lane the width is even (checked on the host), so a lane's pair
 // (col, col + 1) never straddles the periodic wrap and lies wholly inside or outside
 // the strip's output columns.
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL, int SP>
 __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, int lane) {
   constexpr int halo = 4 * TS;
   constexpr int strip_cols = kWave * CPL - 2 * halo;
-  Marcher<T, VMODE, CLS, kWin, PF, TS, CPL> w;
-  using V = typename Marcher<T, VMODE, CLS, kWin, PF, TS, CPL>::V;
+  Marcher<T, VMODE, CLS, kWin, PF, TS, CPL, SP> w;
+  using V = typename Marcher<T, VMODE, CLS, kWin, PF, TS, CPL, SP>::V;
   const int x0 = strip * strip_cols;
   const int c = CPL * lane - halo;  // the lane's first column, relative to the strip
   int col = (x0 + c) % g.nx;
@@ -392,9 +393,9 @@ __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, 
   for (int k = 0; k < PF; ++k) {
     w.load_row(k, y);
     y = (y + 1 == g.ny) ? 0 : y + 1;
-    buf_store<V>(V(T(0)), w.r2o, kDropOffset, 0u);
-    buf_store<V>(V(T(0)), w.r3o, kDropOffset, 0u);
-    buf_store<V>(V(T(0)), w.r4o, kDropOffset, 0u);
+    buf_store<V, SP>(V(T(0)), w.r2o, kDropOffset, 0u);
+    buf_store<V, SP>(V(T(0)), w.r3o, kDropOffset, 0u);
+    buf_store<V, SP>(V(T(0)), w.r4o, kDropOffset, 0u);
   }
   w.yin = y;
 
@@ -414,7 +415,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
   const int seg = blk / blocks_per_seg;
   const int strip = (blk % blocks_per_seg) * kWavesPerBlock + wib;
   if (seg >= g.segs || strip >= g.strips) return;  // whole wave exits together
-  march<T, VMODE, CLS, kWin, PF, TS, CPL>(g, strip, seg, lane);
+  march<T, VMODE, CLS, kWin, PF, TS, CPL, kStoreNonTemporal>(g, strip, seg, lane);
 }
 
 // Batched passes. `args` holds two entries per instance (parity 0: the buffer that
@@ -439,7 +440,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_batch_kernel(
     const int tile = static_cast<int>(code & 0xFFFFFu);
     const int par = __builtin_amdgcn_readfirstlane(parity[inst]);
     const StepArgs<T> g = args[2 * inst + ((p + par) & 1)];
-    march<T, VMODE, CLS, kWin, PF, TS, 1>(g, tile % g.strips, tile / g.strips, lane);
+    march<T, VMODE, CLS, kWin, PF, TS, 1, kStoreDefault>(g, tile % g.strips, tile / g.strips,
+                                                        lane);
   }
 }
 
