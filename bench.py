@@ -350,6 +350,11 @@ def batched_study(qla, torch, count, seed, error_samples):
     steps = [i.steps for i in inst]
     qla.qla_batch_plan(b, steps, 0)
     info = qla.qla_batch_plan_info(b)
+    heights = {}
+    for i in range(count):
+        h = qla.qla_batch_segment_rows(b, i)
+        heights[h] = heights.get(h, 0) + 1
+    info["segment_rows_histogram"] = {str(h): c for h, c in sorted(heights.items())}
     print(f"[batch] {count} instances set up and planned in {time.perf_counter() - t0:.1f} s: "
           f"{info}", file=sys.stderr, flush=True)
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -652,7 +657,7 @@ def main():
         summarize_counters(*args.summarize_counters)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; the multi-GPU halo-exchange path "
+        print("bench.py: measures one GPU only; the multi-GPU halo-exchange path "
               "is not part of it (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

@@ -255,12 +255,19 @@ qla_status qla_batch_create(int count, const int *nx, const int *ny, const doubl
 qla_status qla_batch_context(qla_batch *batch, int i, qla_ctx **ctx);
 
 /* Plan a run in which lattice i advances steps[i] steps (every index must be set):
- * autotune segment height, prefetch depth and steps per pass on the batch itself
- * (the states are saved and restored), build the tile tables and capture the run
- * (one persistent launch per pass) into a hipGraph. mode: 0 or 1 (one launch per
- * pass); 2 (one cooperative launch per run) is rejected with QLA_EINVAL in this
- * build. Synchronises. */
+ * autotune the segment height (one for all lattices, or fitted to each lattice's
+ * height around it), prefetch depth and steps per pass on the batch itself (the
+ * states are saved and restored), build the tile tables and capture the run (one
+ * persistent launch per pass) into a hipGraph. mode: 0 or 1 (one launch per pass);
+ * 2 (one cooperative launch per run) is not available (QLA_EINVAL). Synchronises. */
 qla_status qla_batch_plan(qla_batch *batch, const int64_t *steps, int mode);
+
+/* As qla_batch_plan with a given tuning instead of the autotuned one: segment
+ * height rows_per_segment (>= 1; fit = 1: fitted to each lattice's height around
+ * it), prefetch_rows 2 or 3, steps_per_pass 1 or 2 (2 needs every step count even).
+ * QLA_EINVAL for values outside these ranges. Synchronises. */
+qla_status qla_batch_plan_fixed(qla_batch *batch, const int64_t *steps, int rows_per_segment,
+                                int prefetch_rows, int steps_per_pass, int fit);
 
 /* Replay the planned run (asynchronous). Runs can be repeated; each continues
  * from the previous one's result. */
@@ -271,6 +278,9 @@ qla_status qla_batch_run(qla_batch *batch);
 qla_status qla_batch_plan_info(const qla_batch *batch, int *rows_per_segment,
                                int *prefetch_rows, int *steps_per_pass, int *mode,
                                int *passes, int64_t *site_updates);
+
+/* The segment height (output rows per wavefront tile) the plan gives lattice i. */
+qla_status qla_batch_segment_rows(const qla_batch *batch, int i, int *rows);
 
 /* Release the batch and every lattice in it (NULL is accepted). Synchronises. */
 qla_status qla_batch_destroy(qla_batch *batch);

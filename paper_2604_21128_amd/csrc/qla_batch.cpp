@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -31,6 +33,7 @@ struct qla_batch {
   bool planned = false;
   std::vector<int64_t> steps;
   int rows = 0, prefetch = 0, fused = 0, mode = 0, passes = 0, angle_class = 0, blocks = 0;
+  bool fit = false;               // segment heights fitted per lattice around `rows`
   int64_t total_updates = 0;
   void* d_args = nullptr;
   unsigned* d_items = nullptr;
@@ -69,15 +72,41 @@ struct Tables {
   int passes = 0;
 };
 
-// Builds the launch tables for one tuning. Returns false if a lattice has more
-// tiles than an item can address.
-bool build_tables(const qla_batch* b, int rows, int prefetch, int fused, Tables* t) {
+// Segment height for one lattice of ny rows. A wavefront marches whole unrolled loop
+// trips of `win` rows (the register window), so the heights it can realise are
+// win k - 2 halo; among those from 3/4 to 3/2 of the target, take the one that
+// covers ny with the fewest marched rows (segments x trips x win), ties to the
+// height closest to the target. A lattice of 300 rows with a 62-row target then
+// takes four 75-row segments (364 marched rows) instead of five of 62 (390).
+int fitted_rows(int ny, int target, int prefetch, int fused) {
+  const int win = prefetch + 4 * fused + 2, halo = 4 * fused;
+  int best = target;
+  int64_t best_cost = INT64_MAX;
+  for (int k = 1; win * k - 2 * halo <= (3 * target) / 2 || k == 1; ++k) {
+    const int rows = win * k - 2 * halo;
+    if (rows < 1 || 4 * rows < 3 * target) continue;
+    const int64_t cost = static_cast<int64_t>((ny + rows - 1) / rows) * win * k;
+    if (cost < best_cost ||
+        (cost == best_cost && std::abs(rows - target) < std::abs(best - target))) {
+      best_cost = cost;
+      best = rows;
+    }
+  }
+  return best;
+}
+
+// Builds the launch tables for one tuning (segment height `rows` for every lattice,
+// or fitted to each lattice's height around it). Returns false if a lattice has
+// more tiles than an item can address.
+bool build_tables(const qla_batch* b, int rows, int prefetch, int fused, bool fit,
+                  Tables* t) {
   const size_t asz = qla::step_args_bytes(b->fp32);
   t->args.assign(2 * b->count * asz, 0);
   std::vector<int> tiles(b->count), passes(b->count);
   for (int i = 0; i < b->count; ++i) {
+    const int r = fit ? fitted_rows(b->ctx[i]->ny, rows, prefetch, fused) : rows;
     for (int dir = 0; dir < 2; ++dir) {
-      const qla::StepLaunch L = qla::step_launch_for(b->ctx[i], rows, prefetch, fused, dir);
+      const qla::StepLaunch L = qla::step_launch_for(b->ctx[i], r, prefetch, fused, dir);
       qla::fill_step_args(L, t->args.data() + (2 * i + dir) * asz, &tiles[i]);
     }
     if (tiles[i] > kMaxTiles) return false;
@@ -179,11 +208,11 @@ qla_status restore_states(qla_batch* b) {
 }
 
 // Time a few passes of the batch under one tuning; returns ns per lattice-site update.
-qla_status time_candidate(qla_batch* b, int rows, int prefetch, int fused,
+qla_status time_candidate(qla_batch* b, int rows, int prefetch, int fused, bool fit,
                           double* ns_per_update) {
   *ns_per_update = 1e300;
   Tables t;
-  if (!build_tables(b, rows, prefetch, fused, &t)) return QLA_OK;
+  if (!build_tables(b, rows, prefetch, fused, fit, &t)) return QLA_OK;
   void* d_args;
   unsigned* d_items;
   int* d_counts;
@@ -281,12 +310,17 @@ qla_status qla_batch_context(qla_batch* b, int i, qla_ctx** ctx) {
   return QLA_OK;
 }
 
-qla_status qla_batch_plan(qla_batch* b, const int64_t* steps, int mode) {
-  if (!b || !steps) return fail(QLA_EINVAL, "NULL argument");
-  if (mode == 2)
-    return fail(QLA_EINVAL, "mode 2 (one cooperative launch per run) is disabled in this "
-                            "build; use 0 or 1");
-  if (mode < 0 || mode > 1) return fail(QLA_EINVAL, "mode must be 0 (auto) or 1");
+}  // extern "C"
+
+namespace {
+
+struct BatchTuning {
+  int rows, prefetch, fused;
+  bool fit;
+};
+
+// Plans the run: with `fixed` NULL the tuning is autotuned on the batch itself.
+qla_status plan_batch(qla_batch* b, const int64_t* steps, const BatchTuning* fixed) {
   bool all_even = true;
   int cls = 0;
   for (int i = 0; i < b->count; ++i) {
@@ -296,6 +330,8 @@ qla_status qla_batch_plan(qla_batch* b, const int64_t* steps, int mode) {
     all_even = all_even && (steps[i] % 2 == 0);
     cls = std::max(cls, b->ctx[i]->angle_class);
   }
+  if (fixed && fixed->fused == 2 && !all_even)
+    return fail(QLA_EINVAL, "two steps per pass need an even step count for every lattice");
   DeviceGuard g(b->device);
   release_plan(b);
   b->steps.assign(steps, steps + b->count);
@@ -312,37 +348,51 @@ qla_status qla_batch_plan(qla_batch* b, const int64_t* steps, int mode) {
     QLA_HIP(hipMemcpyAsync(b->d_parity, b->parity.data(), b->count * sizeof(int),
                            hipMemcpyHostToDevice, b->stream));
   }
-  // --- autotune: tile height, prefetch depth and steps per pass
+  // --- tuning, given or autotuned: tile height (one for all lattices, or fitted to
+  // each lattice's height around it), prefetch depth and steps per pass
   static const int kRows[] = {24, 56, 88, 152};
   static const int kPrefetch[] = {2, 3};
   const int fused_options[2] = {all_even ? 2 : 1, 1};
   const int n_fused = all_even ? 2 : 1;
-  qla_status st = save_states(b);
-  if (st != QLA_OK) return st;
-  double best = 1e300;
   int brows = qla::kDefaultRows, bpf = qla::kDefaultPrefetch, bfused = fused_options[0];
+  bool bfit = false;
   const int bmode = 1;
-  for (int fi = 0; fi < n_fused && st == QLA_OK; ++fi)
-    for (int pf : kPrefetch) {
-      for (int rows : kRows) {
-        double ns = 1e300;
-        st = time_candidate(b, rows, pf, fused_options[fi], &ns);
-        if (st != QLA_OK) break;
-        if (ns < best) {
-          best = ns;
-          brows = rows;
-          bpf = pf;
-          bfused = fused_options[fi];
+  qla_status st = QLA_OK;
+  if (fixed) {
+    brows = fixed->rows;
+    bpf = fixed->prefetch;
+    bfused = fixed->fused;
+    bfit = fixed->fit;
+  } else {
+    st = save_states(b);
+    if (st != QLA_OK) return st;
+    double best = 1e300;
+    for (int fi = 0; fi < n_fused && st == QLA_OK; ++fi) {
+      for (int pf : kPrefetch) {
+        for (int rows : kRows) {
+          for (int fit = 0; fit < 2 && st == QLA_OK; ++fit) {
+            double ns = 1e300;
+            st = time_candidate(b, rows, pf, fused_options[fi], fit != 0, &ns);
+            if (st == QLA_OK && ns < best) {
+              best = ns;
+              brows = rows;
+              bpf = pf;
+              bfused = fused_options[fi];
+              bfit = fit != 0;
+            }
+          }
+          if (st != QLA_OK) break;
         }
+        if (st != QLA_OK) break;
       }
-      if (st != QLA_OK) break;
     }
-  const qla_status rs = restore_states(b);
-  if (st != QLA_OK) return st;
-  if (rs != QLA_OK) return rs;
+    const qla_status rs = restore_states(b);
+    if (st != QLA_OK) return st;
+    if (rs != QLA_OK) return rs;
+  }
   // --- tables and graph for the chosen tuning
   Tables t;
-  if (!build_tables(b, brows, bpf, bfused, &t))
+  if (!build_tables(b, brows, bpf, bfused, bfit, &t))
     return fail(QLA_EINVAL, "a lattice has more than 2^20 wavefront tiles");
   st = upload(b, t, &b->d_args, &b->d_items, &b->d_counts);
   if (st != QLA_OK) return st;
@@ -362,6 +412,7 @@ qla_status qla_batch_plan(qla_batch* b, const int64_t* steps, int mode) {
   b->graph = graph;
   QLA_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   b->rows = brows;
+  b->fit = bfit;
   b->prefetch = bpf;
   b->fused = bfused;
   b->mode = bmode;
@@ -372,6 +423,33 @@ qla_status qla_batch_plan(qla_batch* b, const int64_t* steps, int mode) {
     b->total_updates += static_cast<int64_t>(b->ctx[i]->count()) * (steps[i] / bfused) * bfused;
   b->planned = true;
   return QLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qla_status qla_batch_plan(qla_batch* b, const int64_t* steps, int mode) {
+  if (!b || !steps) return fail(QLA_EINVAL, "NULL argument");
+  if (mode == 2)
+    return fail(QLA_EINVAL, "mode 2 (one cooperative launch per run) is not available; "
+                            "use 0 or 1");
+  if (mode < 0 || mode > 1) return fail(QLA_EINVAL, "mode must be 0 (auto) or 1");
+  return plan_batch(b, steps, nullptr);
+}
+
+qla_status qla_batch_plan_fixed(qla_batch* b, const int64_t* steps, int rows_per_segment,
+                                int prefetch_rows, int steps_per_pass, int fit) {
+  if (!b || !steps) return fail(QLA_EINVAL, "NULL argument");
+  if (rows_per_segment < 1 || rows_per_segment > (1 << 20))
+    return fail(QLA_EINVAL, "rows_per_segment must be in [1, 2^20]");
+  if (prefetch_rows != 2 && prefetch_rows != 3)
+    return fail(QLA_EINVAL, "prefetch_rows must be 2 or 3");
+  if (steps_per_pass != 1 && steps_per_pass != 2)
+    return fail(QLA_EINVAL, "steps_per_pass must be 1 or 2");
+  if (fit != 0 && fit != 1) return fail(QLA_EINVAL, "fit must be 0 or 1");
+  const BatchTuning t{rows_per_segment, prefetch_rows, steps_per_pass, fit != 0};
+  return plan_batch(b, steps, &t);
 }
 
 qla_status qla_batch_run(qla_batch* b) {
@@ -407,6 +485,17 @@ qla_status qla_batch_plan_info(const qla_batch* b, int* rows, int* prefetch, int
   if (mode) *mode = b->mode;
   if (passes) *passes = b->passes;
   if (site_updates) *site_updates = b->total_updates;
+  return QLA_OK;
+}
+
+qla_status qla_batch_segment_rows(const qla_batch* b, int i, int* rows) {
+  if (!b || !rows) return fail(QLA_EINVAL, "NULL argument");
+  if (!b->planned) return fail(QLA_ESTATE, "the batch is not planned");
+  if (i < 0 || i >= b->count) return fail(QLA_EINVAL, "instance index out of range");
+  const int r = b->fit ? fitted_rows(b->ctx[i]->ny, b->rows, b->prefetch, b->fused) : b->rows;
+  // the height the kernel realises: whole loop trips of the register window
+  const int win = b->prefetch + 4 * b->fused + 2, halo = 4 * b->fused;
+  *rows = ((r + 2 * halo + win - 1) / win) * win - 2 * halo;
   return QLA_OK;
 }
 

@@ -33,7 +33,8 @@ EXPORTED = (
     "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_set_lane_columns",
     "qla_get_lane_columns", "qla_destroy", "qla_strerror",
     "qla_last_error", "qla_batch_create", "qla_batch_context", "qla_batch_plan", "qla_batch_run",
-    "qla_batch_plan_info", "qla_batch_destroy", "qla_fno_create", "qla_fno_destroy",
+    "qla_batch_plan_info", "qla_batch_plan_fixed", "qla_batch_segment_rows",
+    "qla_batch_destroy", "qla_fno_create", "qla_fno_destroy",
     "qla_fno_param_count", "qla_fno_get_params", "qla_fno_set_params", "qla_fno_get_grads",
     "qla_fno_forward", "qla_fno_loss_grad", "qla_fno_adam_step", "qla_fno_train_step",
     "qla_fno_output_energy", "qla_fno_pack",
@@ -105,6 +106,8 @@ def load(path: str = LIB_PATH):
         "qla_batch_run": (st, [vp]),
         "qla_batch_plan_info": (st, [vp] + [ctypes.POINTER(ctypes.c_int)] * 5
                                 + [ctypes.POINTER(i64)]),
+        "qla_batch_plan_fixed": (st, [vp, ctypes.POINTER(i64)] + [ctypes.c_int] * 4),
+        "qla_batch_segment_rows": (st, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "qla_batch_destroy": (st, [vp]),
         "qla_fno_create": (st, [ctypes.c_int] * 9 + [ctypes.c_uint64, vp, ctypes.POINTER(vp)]),
         "qla_fno_destroy": (st, [vp]),
@@ -316,6 +319,21 @@ def qla_batch_context(batch: int, i: int) -> int:
 def qla_batch_plan(batch: int, steps, mode: int = 0) -> None:
     arr = (ctypes.c_int64 * len(steps))(*[int(v) for v in steps])
     _check(load().qla_batch_plan(ctypes.c_void_p(batch), arr, int(mode)), "qla_batch_plan")
+
+
+def qla_batch_plan_fixed(batch: int, steps, rows_per_segment: int, prefetch_rows: int,
+                         steps_per_pass: int, fit: bool = False) -> None:
+    arr = (ctypes.c_int64 * len(steps))(*[int(v) for v in steps])
+    _check(load().qla_batch_plan_fixed(ctypes.c_void_p(batch), arr, int(rows_per_segment),
+                                       int(prefetch_rows), int(steps_per_pass), int(bool(fit))),
+           "qla_batch_plan_fixed")
+
+
+def qla_batch_segment_rows(batch: int, i: int) -> int:
+    v = ctypes.c_int()
+    _check(load().qla_batch_segment_rows(ctypes.c_void_p(batch), int(i), ctypes.byref(v)),
+           "qla_batch_segment_rows")
+    return v.value
 
 
 def qla_batch_run(batch: int) -> None:

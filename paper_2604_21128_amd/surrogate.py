@@ -1,4 +1,4 @@
-"""Learned surrogate of long QLA runs, with QLA as its judge and fallback.
+"""Learned surrogate of long QLA runs, with QLA as its reference and fallback.
 
 A Fourier neural operator (the qla_fno_* calls of libqla) maps a lattice's medium
 and initial fields, (n - n_shift, q2, q3, q4), to its fields (q2, q3, q4) a fixed

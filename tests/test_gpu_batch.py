@@ -134,3 +134,48 @@ def test_batch_odd_steps_and_errors(qla):
             np.testing.assert_array_equal(got, _single(qla, *ns[i], 2 * (7, 4)[i], 1))
     finally:
         qla.qla_batch_destroy(b)
+
+
+@pytest.mark.parametrize("fit", [False, True])
+@pytest.mark.parametrize("rows,pf,ts", [(24, 2, 2), (56, 3, 2), (20, 3, 1)])
+def test_batch_fixed_tuning_and_fitted_heights(qla, fit, rows, pf, ts):
+    """Given tunings, with one segment height for all lattices or heights fitted to each
+    lattice: results equal the single-lattice path bit for bit, and every height is one
+    the kernel realises (whole loop trips of its register window)."""
+    sizes = [(64, 300), (57, 90), (130, 40), (96, 128), (8, 8), (40, 161)]
+    steps = [12, 20, 8, 10, 6, 14]
+    b = qla.qla_batch_create([s[0] for s in sizes], [s[1] for s in sizes], [0.25] * len(sizes),
+                             precision=1)
+    try:
+        inputs = []
+        for i, (nx, ny) in enumerate(sizes):
+            n, p = _instance(40 + i, nx, ny)
+            inputs.append((n, p))
+            ctx = qla.qla_batch_context(b, i)
+            qla.qla_set_index(ctx, n)
+            qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam)
+        qla.qla_batch_plan_fixed(b, steps, rows, pf, ts, fit)
+        info = qla.qla_batch_plan_info(b)
+        assert (info["rows_per_segment"], info["prefetch_rows"], info["steps_per_pass"]) == \
+            (rows, pf, ts)
+        win, halo = pf + 4 * ts + 2, 4 * ts
+        heights = [qla.qla_batch_segment_rows(b, i) for i in range(len(sizes))]
+        realised = ((rows + 2 * halo + win - 1) // win) * win - 2 * halo
+        for h in heights:
+            assert h >= 1 and (h + 2 * halo) % win == 0
+            assert 4 * h >= 3 * rows and (2 * h <= 3 * rows or h == realised)
+        if not fit:
+            assert len(set(heights)) == 1
+        qla.qla_batch_run(b)
+        for i, (nx, ny) in enumerate(sizes):
+            got = qla.qla_get_fields(qla.qla_batch_context(b, i), nx, ny)
+            np.testing.assert_array_equal(got, _single(qla, *inputs[i], steps[i], 1),
+                                          err_msg=f"instance {i} {nx}x{ny} heights={heights}")
+        with pytest.raises(qla.QlaError):
+            qla.qla_batch_plan_fixed(b, steps, rows, 4, ts, fit)        # prefetch 4
+        with pytest.raises(qla.QlaError):
+            qla.qla_batch_plan_fixed(b, [7] + steps[1:], rows, pf, 2, fit)  # odd, 2 per pass
+        with pytest.raises(qla.QlaError):
+            qla.qla_batch_segment_rows(b, len(sizes))
+    finally:
+        qla.qla_batch_destroy(b)
