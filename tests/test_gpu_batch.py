@@ -179,3 +179,41 @@ def test_batch_fixed_tuning_and_fitted_heights(qla, fit, rows, pf, ts):
             qla.qla_batch_segment_rows(b, len(sizes))
     finally:
         qla.qla_batch_destroy(b)
+
+
+def test_full_batched_workload_against_the_oracle(qla):
+    """The 512-instance batched workload as the benchmark runs it: sides 256-1024, FP32,
+    4 N steps each, autotuned plan captured in one graph. The two smallest instances are
+    checked whole against the FP64 oracle (FP32 bar, relative L2 <= 1e-5), and every
+    instance's energy stays at its initial value to FP32 rounding (the step is unitary)."""
+    inst = workloads.sample_instances(512, seed=0)
+    b = qla.qla_batch_create([i.n_side for i in inst], [i.n_side for i in inst],
+                             [i.delta for i in inst], precision=1)
+    try:
+        ns, e0 = [], []
+        for k, i in enumerate(inst):
+            n = workloads.ellipse_index(i.n_side, i.n_side, i.ellipse)
+            ns.append(n)
+            ctx = qla.qla_batch_context(b, k)
+            qla.qla_set_index(ctx, n)
+            p = i.packet
+            qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
+            e0.append(qla.qla_energy(ctx))
+        qla.qla_batch_plan(b, [i.steps for i in inst], 0)
+        print("plan", qla.qla_batch_plan_info(b), flush=True)
+        qla.qla_batch_run(b)
+        drift = max(abs(qla.qla_energy(qla.qla_batch_context(b, k)) / e0[k] - 1)
+                    for k in range(len(inst)))
+        print(f"max energy drift over 512 instances {drift:.2e}", flush=True)
+        assert drift <= 2e-5
+        smallest = sorted(range(len(inst)), key=lambda k: inst[k].n_side)[:2]
+        for k in smallest:
+            i = inst[k]
+            got = qla.qla_get_fields(qla.qla_batch_context(b, k), i.n_side, i.n_side)
+            want = oracle.advance(oracle.packet_from(ns[k], i.packet), ns[k], i.delta, i.steps)
+            err = np.linalg.norm(got - want[2:5]) / np.linalg.norm(want[2:5])
+            print(f"instance {k}: side {i.n_side}, {i.steps} steps, rel_l2 {err:.2e}",
+                  flush=True)
+            assert err <= 1e-5
+    finally:
+        qla.qla_batch_destroy(b)
