@@ -110,8 +110,9 @@ typedef struct {
 } qla_packet;
 
 /* Create a context for an nx-by-ny periodic lattice with spacing delta.
- * nx, ny >= 8 (the step reads 4 neighbours on each side); one amplitude plane
- * must fit in 2 GiB (nx * ny <= 2^28 in FP64, 2^29 in FP32),
+ * nx, ny >= 8 (the step reads 4 neighbours on each side), nx < 2^28 (a row below
+ * 2 GiB); the lattice size is bounded only by device memory (80 bytes per site
+ * in FP64, 60 in FP32; planes beyond 2 GiB are addressed row by row),
  * delta > 0 and finite. hip_stream: a hipStream_t to enqueue on, or NULL for a
  * library-owned stream. Allocates the amplitude planes (two buffers), the index
  * planes and small scratch; the state starts at zero with no index set. */
@@ -244,7 +245,8 @@ typedef struct qla_batch qla_batch;
 
 /* Create `count` (1..4095) lattices nx[i] x ny[i] with spacing delta[i], all in one
  * precision and potential mode, on one stream (NULL = library-owned). Each lattice
- * is an ordinary context (see qla_batch_context). */
+ * is an ordinary context (see qla_batch_context); each amplitude plane must fit in
+ * 2 GiB (QLA_EINVAL otherwise). */
 qla_status qla_batch_create(int count, const int *nx, const int *ny, const double *delta,
                             qla_precision precision, qla_potential potential,
                             void *hip_stream, qla_batch **out);

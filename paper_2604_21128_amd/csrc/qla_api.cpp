@@ -202,11 +202,8 @@ qla_status qla_create_triple(int nx, int ny, double delta, qla_precision precisi
   if (!out) return fail(QLA_EINVAL, "out is NULL");
   *out = nullptr;
   if (nx < 8 || ny < 8) return fail(QLA_EINVAL, "nx and ny must be >= 8");
-  const long long sites = static_cast<long long>(nx) * ny;
-  const long long elem = precision == QLA_F32 ? 4 : 8;
-  if (sites * elem > (1ll << 31))
-    return fail(QLA_EINVAL, "one amplitude plane must fit in 2 GiB (nx * ny <= 2^28 in FP64, "
-                            "2^29 in FP32)");
+  if (static_cast<long long>(nx) * sizeof(double) >= (1ll << 31))
+    return fail(QLA_EINVAL, "one row must stay below 2 GiB (nx < 2^28)");
   if (!(delta > 0.0) || !std::isfinite(delta)) return fail(QLA_EINVAL, "delta must be > 0");
   if (precision != QLA_F64 && precision != QLA_F32) return fail(QLA_EINVAL, "bad precision");
   if (potential != QLA_V_SKEW_HALF && potential != QLA_V_PAPER && potential != QLA_V_NONE &&

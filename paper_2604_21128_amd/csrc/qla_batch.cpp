@@ -286,6 +286,16 @@ qla_status qla_batch_create(int count, const int* nx, const int* ny, const doubl
     }
     b->own_stream = true;
   }
+  for (int i = 0; i < count; ++i) {
+    // the batched kernel addresses each plane through one buffer descriptor
+    const long long bytes = static_cast<long long>(nx[i]) * ny[i] * (b->fp32 ? 4 : 8);
+    if (bytes > (1ll << 31)) {
+      if (b->own_stream) (void)hipStreamDestroy(b->stream);
+      delete b;
+      return fail(QLA_EINVAL, "instance " + std::to_string(i) +
+                                  ": a batched lattice's plane must fit in 2 GiB");
+    }
+  }
   b->ctx.assign(count, nullptr);
   for (int i = 0; i < count; ++i) {
     const qla_status st = qla_create(nx[i], ny[i], delta[i], precision, potential, b->stream,

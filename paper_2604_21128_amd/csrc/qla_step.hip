@@ -66,6 +66,9 @@ constexpr int kWavesPerBlock = 4;
 // hardware; stores of halo lanes and of rows outside the segment use this offset
 // instead of a branch, so the memory counters stay static for the compiler.
 constexpr unsigned kDropOffset = 0x80000000u;
+// Largest plane one buffer descriptor addresses with these offsets (and below which
+// kDropOffset is out of range).
+constexpr size_t kMaxPlaneDescriptorBytes = size_t(1) << 31;
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -159,7 +162,12 @@ struct StepArgs {
 // share one window: a row keeps its slot from its load until its store. Each
 // stage widens the dependence by 4 cells in x and y, so a pass has 4 TS halo
 // columns on each side of the strip and 4 TS halo rows at each end of a segment.
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL, int SP>
+// Plane addressing: one buffer descriptor per plane, offsets within it (planes of at
+// most 2^31 bytes), or a descriptor per row, based at the row's 64-bit address in
+// scalar registers (any plane size; the offsets stay within one row).
+enum Addressing : int { kPlaneDescriptors = 0, kRowDescriptors = 1 };
+
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL, int SP, int AM>
 struct Marcher {
   static_assert(PF + 4 * TS + 2 <= kWin, "a prefetched row must not overwrite a live one");
   using V = typename LaneOf<T, CPL>::type;
@@ -177,7 +185,9 @@ struct Marcher {
   // (V = I).
   unsigned umask, emask;
   unsigned long long nb_prev;  // n's bit pattern in lane 0 of the previous row
-  __amdgpu_buffer_rsrc_t r2i, r3i, r4i, rn, r2o, r3o, r4o;
+  __amdgpu_buffer_rsrc_t r2i, r3i, r4i, rn, r2o, r3o, r4o;  // kPlaneDescriptors
+  const char *b2i, *b3i, *b4i, *bn;                          // kRowDescriptors: plane bases
+  char *b2o, *b3o, *b4o;
   unsigned col_bytes;    // this lane's (first) column (wrapped) in bytes
   unsigned store_bytes;  // col_bytes for lanes that own an output column, else kDropOffset
   unsigned row_bytes;    // nx * sizeof(T)
@@ -188,11 +198,35 @@ struct Marcher {
   // y is uniform across the wave: the row offset is a scalar register and every
   // lane adds its fixed column offset.
   __device__ __forceinline__ void load_row(int s, int y) {
-    const unsigned soff = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(y)) * row_bytes;
-    A[s] = buf_load<V>(r2i, col_bytes, soff);
-    P3[s] = buf_load<V>(r3i, col_bytes, soff);
-    P4[s] = buf_load<V>(r4i, col_bytes, soff);
-    N[s] = buf_load<V>(rn, col_bytes, soff);
+    const unsigned yu = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(y));
+    if constexpr (AM == kRowDescriptors) {
+      const size_t off = static_cast<size_t>(yu) * row_bytes;
+      A[s] = buf_load<V>(plane_rsrc(b2i + off, row_bytes), col_bytes, 0u);
+      P3[s] = buf_load<V>(plane_rsrc(b3i + off, row_bytes), col_bytes, 0u);
+      P4[s] = buf_load<V>(plane_rsrc(b4i + off, row_bytes), col_bytes, 0u);
+      N[s] = buf_load<V>(plane_rsrc(bn + off, row_bytes), col_bytes, 0u);
+    } else {
+      const unsigned soff = yu * row_bytes;
+      A[s] = buf_load<V>(r2i, col_bytes, soff);
+      P3[s] = buf_load<V>(r3i, col_bytes, soff);
+      P4[s] = buf_load<V>(r4i, col_bytes, soff);
+      N[s] = buf_load<V>(rn, col_bytes, soff);
+    }
+  }
+
+  // Stores of one output row (discarded for voff = kDropOffset).
+  __device__ __forceinline__ void store_row(int s, unsigned yo, unsigned voff) {
+    if constexpr (AM == kRowDescriptors) {
+      const size_t off = static_cast<size_t>(yo) * row_bytes;
+      buf_store<V, SP>(A[s], plane_rsrc(b2o + off, row_bytes), voff, 0u);
+      buf_store<V, SP>(P3[s], plane_rsrc(b3o + off, row_bytes), voff, 0u);
+      buf_store<V, SP>(P4[s], plane_rsrc(b4o + off, row_bytes), voff, 0u);
+    } else {
+      const unsigned soff = yo * row_bytes;
+      buf_store<V, SP>(A[s], r2o, voff, soff);
+      buf_store<V, SP>(P3[s], r3o, voff, soff);
+      buf_store<V, SP>(P4[s], r4o, voff, soff);
+    }
   }
 
   // U_x on one row (slot s): lanes exchange neighbour values by DPP. In a
@@ -341,11 +375,7 @@ struct Marcher {
     // row r - 4 TS has had all TS steps: output row y0 + r - 8 TS
     const int yo = y0 + r - 8 * TS;
     const bool row_ok = yo >= y0 && yo < yend;
-    const unsigned soff = row_ok ? static_cast<unsigned>(yo) * row_bytes : 0u;
-    const unsigned voff = row_ok ? store_bytes : kDropOffset;
-    buf_store<V, SP>(A[sout], r2o, voff, soff);
-    buf_store<V, SP>(P3[sout], r3o, voff, soff);
-    buf_store<V, SP>(P4[sout], r4o, voff, soff);
+    store_row(sout, row_ok ? static_cast<unsigned>(yo) : 0u, row_ok ? store_bytes : kDropOffset);
   }
 };
 
@@ -353,12 +383,12 @@ struct Marcher {
 // two columns per lane the width is even (checked on the host), so a lane's pair
 // (col, col + 1) never straddles the periodic wrap and lies wholly inside or outside
 // the strip's output columns.
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL, int SP>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL, int SP, int AM>
 __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, int lane) {
   constexpr int halo = 4 * TS;
   constexpr int strip_cols = kWave * CPL - 2 * halo;
-  Marcher<T, VMODE, CLS, kWin, PF, TS, CPL, SP> w;
-  using V = typename Marcher<T, VMODE, CLS, kWin, PF, TS, CPL, SP>::V;
+  Marcher<T, VMODE, CLS, kWin, PF, TS, CPL, SP, AM> w;
+  using V = typename Marcher<T, VMODE, CLS, kWin, PF, TS, CPL, SP, AM>::V;
   const int x0 = strip * strip_cols;
   const int c = CPL * lane - halo;  // the lane's first column, relative to the strip
   int col = (x0 + c) % g.nx;
@@ -367,13 +397,23 @@ __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, 
   w.col_bytes = static_cast<unsigned>(col) * sizeof(T);
   w.store_bytes = store_lane ? w.col_bytes : kDropOffset;
   w.row_bytes = static_cast<unsigned>(g.nx) * sizeof(T);
-  w.r2i = plane_rsrc(g.q2i, g.plane_bytes);
-  w.r3i = plane_rsrc(g.q3i, g.plane_bytes);
-  w.r4i = plane_rsrc(g.q4i, g.plane_bytes);
-  w.rn = plane_rsrc(g.n, g.plane_bytes);
-  w.r2o = plane_rsrc(g.q2o, g.plane_bytes);
-  w.r3o = plane_rsrc(g.q3o, g.plane_bytes);
-  w.r4o = plane_rsrc(g.q4o, g.plane_bytes);
+  if constexpr (AM == kRowDescriptors) {
+    w.b2i = reinterpret_cast<const char*>(g.q2i);
+    w.b3i = reinterpret_cast<const char*>(g.q3i);
+    w.b4i = reinterpret_cast<const char*>(g.q4i);
+    w.bn = reinterpret_cast<const char*>(g.n);
+    w.b2o = reinterpret_cast<char*>(g.q2o);
+    w.b3o = reinterpret_cast<char*>(g.q3o);
+    w.b4o = reinterpret_cast<char*>(g.q4o);
+  } else {
+    w.r2i = plane_rsrc(g.q2i, g.plane_bytes);
+    w.r3i = plane_rsrc(g.q3i, g.plane_bytes);
+    w.r4i = plane_rsrc(g.q4i, g.plane_bytes);
+    w.rn = plane_rsrc(g.n, g.plane_bytes);
+    w.r2o = plane_rsrc(g.q2o, g.plane_bytes);
+    w.r3o = plane_rsrc(g.q3o, g.plane_bytes);
+    w.r4o = plane_rsrc(g.q4o, g.plane_bytes);
+  }
   const int y0 = seg * g.rows_per_seg;
   const int yend = min(y0 + g.rows_per_seg, g.ny);
 #pragma unroll
@@ -393,9 +433,7 @@ __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, 
   for (int k = 0; k < PF; ++k) {
     w.load_row(k, y);
     y = (y + 1 == g.ny) ? 0 : y + 1;
-    buf_store<V, SP>(V(T(0)), w.r2o, kDropOffset, 0u);
-    buf_store<V, SP>(V(T(0)), w.r3o, kDropOffset, 0u);
-    buf_store<V, SP>(V(T(0)), w.r4o, kDropOffset, 0u);
+    w.store_row(0, 0u, kDropOffset);
   }
   w.yin = y;
 
@@ -406,7 +444,7 @@ __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, 
   }
 }
 
-template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL>
+template <typename T, int VMODE, int CLS, int kWin, int PF, int TS, int CPL, int AM>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(StepArgs<T> g) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
@@ -415,7 +453,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_step_ez_kernel(Ste
   const int seg = blk / blocks_per_seg;
   const int strip = (blk % blocks_per_seg) * kWavesPerBlock + wib;
   if (seg >= g.segs || strip >= g.strips) return;  // whole wave exits together
-  march<T, VMODE, CLS, kWin, PF, TS, CPL, kStoreNonTemporal>(g, strip, seg, lane);
+  march<T, VMODE, CLS, kWin, PF, TS, CPL, kStoreNonTemporal, AM>(g, strip, seg, lane);
 }
 
 // Batched passes. `args` holds two entries per instance (parity 0: the buffer that
@@ -440,8 +478,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void qla_batch_kernel(
     const int tile = static_cast<int>(code & 0xFFFFFu);
     const int par = __builtin_amdgcn_readfirstlane(parity[inst]);
     const StepArgs<T> g = args[2 * inst + ((p + par) & 1)];
-    march<T, VMODE, CLS, kWin, PF, TS, 1, kStoreDefault>(g, tile % g.strips, tile / g.strips,
-                                                        lane);
+    march<T, VMODE, CLS, kWin, PF, TS, 1, kStoreDefault, kPlaneDescriptors>(
+        g, tile % g.strips, tile / g.strips, lane);
   }
 }
 
@@ -457,7 +495,9 @@ StepArgs<T> make_args(const StepLaunch& L) {
   g.q2o = static_cast<T*>(L.out[0]);
   g.q3o = static_cast<T*>(L.out[1]);
   g.q4o = static_cast<T*>(L.out[2]);
-  g.plane_bytes = static_cast<unsigned>(static_cast<size_t>(L.nx) * L.ny * sizeof(T));
+  // the descriptor range of a plane (with per-row descriptors only a row's is used)
+  const size_t plane = static_cast<size_t>(L.nx) * L.ny * sizeof(T);
+  g.plane_bytes = static_cast<unsigned>(plane <= kMaxPlaneDescriptorBytes ? plane : 0);
   g.nx = L.nx;
   g.ny = L.ny;
   g.strips = (L.nx + strip_cols - 1) / strip_cols;
@@ -476,8 +516,15 @@ hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
   const StepArgs<T> g = make_args<T, kWin, TS, CPL>(L);
   const int blocks_per_seg = (g.strips + kWavesPerBlock - 1) / kWavesPerBlock;
   const int blocks = blocks_per_seg * g.segs;
-  hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF, TS, CPL>), dim3(blocks),
-                     dim3(kWave * kWavesPerBlock), 0, stream, g);
+  // planes beyond one descriptor's 2^31-byte range are addressed row by row
+  const bool rows = static_cast<size_t>(L.nx) * L.ny * sizeof(T) > kMaxPlaneDescriptorBytes;
+  if (rows) {
+    hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF, TS, CPL, kRowDescriptors>),
+                       dim3(blocks), dim3(kWave * kWavesPerBlock), 0, stream, g);
+  } else {
+    hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF, TS, CPL, kPlaneDescriptors>),
+                       dim3(blocks), dim3(kWave * kWavesPerBlock), 0, stream, g);
+  }
   return hipGetLastError();
 }
 

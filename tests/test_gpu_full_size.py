@@ -32,14 +32,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _windows(qla, w, prec, centres, seed, cols=None):
+def _windows(qla, w, prec, centres, seed, cols=None, autotune=True):
     n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
     rng = np.random.default_rng(seed)
     q = rng.standard_normal((3, w.ny, w.nx), dtype=np.float32).astype(np.float64)
     with qla.Lattice(w.nx, w.ny, w.delta, precision=prec) as lat:
         lat.set_index(n)
         lat.set_fields(q)
-        tuning = qla.qla_autotune(lat.ctx)
+        tuning = qla.qla_autotune(lat.ctx) if autotune else qla.qla_get_tuning(lat.ctx)
         if cols is not None:
             qla.qla_set_lane_columns(lat.ctx, cols)
         used = (tuning, qla.qla_get_lane_columns(lat.ctx))
@@ -87,3 +87,21 @@ def test_parity_8192_bubble_windows_two_columns(qla):
 def test_parity_16384_paper_windows(qla, prec):
     w = workloads.paper_16384()
     assert _windows(qla, w, prec, _centres(w), seed=163) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec,nx,ny", [(0, 16384, 16400), (1, 32768, 16400)])
+def test_parity_planes_beyond_2_gib(qla, prec, nx, ny):
+    """Planes larger than one buffer descriptor's 2^31-byte range (the kernel then
+    addresses them row by row): the paper's ellipse scaled onto the lattice, random
+    fields, windows against the oracle, including rows past the first 2 GiB and the
+    periodic wrap between the last and the first row."""
+    import dataclasses
+    base = workloads.paper_16384()
+    f = nx / 16384
+    e = base.ellipse
+    w = dataclasses.replace(base, name=f"qla_{nx}x{ny}", nx=nx, ny=ny,
+                            ellipse=dataclasses.replace(e, xc=nx / 2, yc=ny / 2, a=e.a * f,
+                                                        b=e.b * f))
+    assert nx * ny * (8 if prec == 0 else 4) > 2 ** 31
+    centres = _centres(w) + [(nx // 3, ny - 3), (5, ny // 2 + 7)]
+    assert _windows(qla, w, prec, centres, seed=7 + prec, autotune=False) <= TOL[prec]
