@@ -507,6 +507,56 @@ def surrogate_study(qla, torch, args):
     return res
 
 
+def size_study(qla, torch, sides, precs, steps):
+    """Lattice size against throughput on one GPU: the paper's ellipse scaled onto square
+    lattices of each side (index generated on the device), the +x packet, the autotuned
+    step, `steps` steps timed with HIP events; up to the sizes that fill HBM (80 B per
+    site in FP64, 60 in FP32; planes beyond 2 GiB use per-row descriptors)."""
+    import workloads
+    base = workloads.paper_16384()
+    sp = torch.cuda.current_stream().cuda_stream
+    free, _ = torch.cuda.mem_get_info()
+    rows = []
+    for prec in precs:
+        code = qla.QLA_F64 if prec == "f64" else qla.QLA_F32
+        per_site = 80 if prec == "f64" else 60
+        for side in sides:
+            if side * side * per_site > 0.9 * free:
+                print(f"[size] {prec} {side}^2 skipped: needs "
+                      f"{side * side * per_site / 1e9:.0f} GB", file=sys.stderr, flush=True)
+                continue
+            f = side / base.nx
+            e, p = base.ellipse, base.packet
+            ctx = qla.qla_create(side, side, base.delta, code, qla.QLA_V_SKEW_HALF, sp)
+            try:
+                qla.qla_set_index_ellipse(ctx, side / 2, side / 2, e.a * f, e.b * f, e.rot,
+                                          e.n_in, e.n_out, e.width)
+                qla.qla_init_packet(ctx, p.x0 * f, side / 2, p.sigma, p.lam)
+                e0 = qla.qla_energy(ctx)
+                qla.qla_autotune(ctx)
+                tuning = current_tuning(qla, ctx)
+                qla.qla_advance(ctx, 2)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                qla.qla_advance(ctx, steps)
+                b.record()
+                torch.cuda.synchronize()
+                sec = a.elapsed_time(b) / 1e3
+                drift = qla.qla_energy(ctx) / e0 - 1
+            finally:
+                qla.qla_destroy(ctx)
+            r = {"precision": prec, "side": side, "sites": side * side,
+                 "device_gb": round(side * side * per_site / 1e9, 1), "steps": steps,
+                 "glups": side * side * steps / sec / 1e9, "seconds": sec,
+                 "energy_rel_drift": drift,
+                 "tuning": dict(zip(("rows_per_segment", "prefetch_rows", "steps_per_pass",
+                                     "columns_per_lane"), tuning))}
+            rows.append(r)
+            print(f"[size] {prec} {side}^2: {r['glups']:.1f} GLUPS ({r['device_gb']} GB), "
+                  f"tuning {tuning}", file=sys.stderr, flush=True)
+    return {"workload": "paper ellipse scaled to square lattices", "steps": steps, "rows": rows}
+
+
 def divergence_study(qla, torch, w, snapshot_every):
     """Both polarisations on one workload (FP64): energy drift and the relative discrete
     divergence ||div|| / ||(dFx/dx, dFy/dy)|| of B (E_z triple) or D (B_z triple) at each
@@ -626,6 +676,11 @@ def main():
                     help="the batched workload (512 instances, FP32); prints its own JSON line")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--error-samples", type=int, default=6)
+    ap.add_argument("--size-study", action="store_true",
+                    help="throughput against lattice size (--sides, --precisions) up to the "
+                         "sizes that fill HBM; prints its own JSON line")
+    ap.add_argument("--sides", default="1024,2048,4096,8192,16384,23170,32768,40960,46340")
+    ap.add_argument("--size-steps", type=int, default=100)
     ap.add_argument("--divergence-study", action="store_true",
                     help="both polarisations on --workload: energy drift and relative "
                          "divergence per snapshot (--snapshot-every); prints its own JSON line")
@@ -679,6 +734,13 @@ def main():
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             out = batched_study(qla, torch, args.instances, 0, args.error_samples)
+        print(json.dumps(out), flush=True)
+        return
+    if args.size_study:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out = size_study(qla, torch, [int(v) for v in args.sides.split(",")],
+                             [p for p in args.precisions.split(",") if p], args.size_steps)
         print(json.dumps(out), flush=True)
         return
     if args.divergence_study:
