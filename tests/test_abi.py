@@ -53,7 +53,7 @@ def test_status_strings():
     (64, 64, 0.25, 7, 0),      # bad precision
     (64, 64, 0.25, 0, 9),      # bad potential mode
     (64, 64, 0.25, 0, 4),
-    (65536, 65536, 0.25, 0, 0),  # nx * ny >= 2^31
+    (1 << 28, 8, 0.25, 0, 0),    # a row of 2 GiB or more
 ])
 def test_create_rejects_bad_arguments_before_touching_the_device(nx, ny, delta, prec, pot):
     qla, lib = _lib()
