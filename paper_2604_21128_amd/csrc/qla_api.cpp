@@ -428,6 +428,22 @@ qla_status qla_autotune(qla_ctx* c, int* rows_out, int* prefetch_out, int* steps
       }
     std::sort(cands.begin(), cands.begin() + top,
               [](const Cand& a, const Cand& b) { return a.per_step < b.per_step; });
+    // Among the candidates within 3% of the fastest, take the one that recomputes the
+    // fewest halo sites. Trials can rank near-equal candidates differently from long
+    // runs (16384^2 FP64: 56-row segments won the trials, 112-row ones ran 8% faster
+    // over 20000 steps), and less redundant arithmetic is the safer choice.
+    auto redundancy = [&](const Cand& k) {
+      const int win = k.pf + 4 * k.fused + 2, halo = 4 * k.fused;
+      const int rows = ((k.rows + 2 * halo + win - 1) / win) * win - 2 * halo;
+      const double wide = 64.0 * k.cols;
+      return (rows + 2.0 * halo) / rows * wide / (wide - 2.0 * halo);
+    };
+    size_t pick = 0;
+    for (size_t k = 1; k < top; ++k)
+      if (cands[k].per_step <= 1.03 * cands[0].per_step &&
+          redundancy(cands[k]) < redundancy(cands[pick]))
+        pick = k;
+    std::swap(cands[0], cands[pick]);
   }
   int brows = c->rows_per_seg, bpf = c->prefetch, bfused = c->fused, bcols = c->cols;
   if (st == QLA_OK && !cands.empty()) {
