@@ -80,13 +80,14 @@ qla_status alloc(void** p, size_t bytes, const char* what) {
 // Validates the index held in the scratch planes (raw input already copied there
 // or readable at src) and installs it.
 qla_status install_index(qla_ctx* c, const double* src, size_t ld) {
-  const size_t N = c->count();
-  double* n_new = c->staging + N;
-  float* n32_new = c->fp32 ? reinterpret_cast<float*>(c->staging + 2 * N) : nullptr;
+  // staging: the packed input in [0, N), the new planes after it (N <= P)
+  const size_t P = c->plane_elems();
+  double* n_new = c->staging + P;
+  float* n32_new = c->fp32 ? reinterpret_cast<float*>(c->staging + 2 * P) : nullptr;
   const unsigned long long init[3] = {0ull, 0x7FF0000000000000ull, 0ull};  // 0, +inf, 0
   QLA_HIP(hipMemcpyAsync(c->stats, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
-  QLA_HIP(qla::launch_index_prepare(src, ld, c->nx, c->ny, c->delta, n_new, n32_new, c->stats,
-                                    c->stream));
+  QLA_HIP(qla::launch_index_prepare(src, ld, c->nx, c->ny, c->pitch, c->delta, n_new, n32_new,
+                                    c->stats, c->stream));
   unsigned long long got[3];
   QLA_HIP(hipMemcpyAsync(got, c->stats, sizeof(got), hipMemcpyDeviceToHost, c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
@@ -107,9 +108,9 @@ qla_status install_index(qla_ctx* c, const double* src, size_t ld) {
                                 std::to_string(theta) + ", max potential half-angle = " +
                                 std::to_string(hb) + " (both must be <= 0.5 rad)");
   }
-  QLA_HIP(hipMemcpyAsync(c->n64, n_new, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  QLA_HIP(hipMemcpyAsync(c->n64, n_new, P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (c->fp32)
-    QLA_HIP(hipMemcpyAsync(c->n32, n32_new, N * sizeof(float), hipMemcpyDeviceToDevice,
+    QLA_HIP(hipMemcpyAsync(c->n32, n32_new, P * sizeof(float), hipMemcpyDeviceToDevice,
                            c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
   c->angle_class = cls;
@@ -128,6 +129,7 @@ qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fuse
   L.n = c->fp32 ? static_cast<const void*>(c->n32) : static_cast<const void*>(c->n64);
   L.nx = c->nx;
   L.ny = c->ny;
+  L.pitch = c->pitch;
   L.rows_per_seg = rows;
   L.prefetch = prefetch;
   L.cols_per_lane = cols;
@@ -157,6 +159,7 @@ qla::StepLaunch step_launch_for(const qla_ctx* c, int rows, int prefetch, int fu
   L.n = c->fp32 ? static_cast<const void*>(c->n32) : static_cast<const void*>(c->n64);
   L.nx = c->nx;
   L.ny = c->ny;
+  L.pitch = c->pitch;
   L.rows_per_seg = rows;
   L.prefetch = prefetch;
   L.fused_steps = fused;
@@ -223,6 +226,10 @@ qla_status qla_create_triple(int nx, int ny, double delta, qla_precision precisi
   c->fp32 = precision == QLA_F32;
   c->vmode = static_cast<int>(potential);
   c->triple = static_cast<int>(triple);
+  {
+    const int line = 128 / static_cast<int>(c->elem());  // elements per cache line
+    c->pitch = (nx + line - 1) / line * line;
+  }
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
     delete c;
@@ -238,7 +245,7 @@ qla_status qla_create_triple(int nx, int ny, double delta, qla_precision precisi
     }
     c->own_stream = true;
   }
-  const size_t N = c->count();
+  const size_t N = c->plane_elems();
   qla_status st = QLA_OK;
   for (int b = 0; b < 2 && st == QLA_OK; ++b)
     for (int k = 0; k < 3 && st == QLA_OK; ++k) st = alloc(&c->q[b][k], N * c->elem(), "amplitudes");
@@ -325,8 +332,8 @@ qla_status qla_init_packet(qla_ctx* c, const qla_packet* p) {
     return fail(QLA_EINVAL, "packet: sigma and lambda must be > 0 and all fields finite");
   DeviceGuard g(c->device);
   qla::PacketArgs a{p->x0, p->y0, p->sigma, p->lambda, p->phi, p->amp, p->planar, c->triple};
-  QLA_HIP(qla::launch_packet(c->n64, c->nx, c->ny, a, c->fp32, c->q[c->cur][0], c->q[c->cur][1],
-                             c->q[c->cur][2], c->stream));
+  QLA_HIP(qla::launch_packet(c->n64, c->nx, c->ny, c->pitch, a, c->fp32, c->q[c->cur][0],
+                             c->q[c->cur][1], c->q[c->cur][2], c->stream));
   c->steps = 0;
   return QLA_OK;
 }
@@ -338,7 +345,8 @@ qla_status qla_set_fields(qla_ctx* c, const double* q_host, int64_t step) {
   const size_t N = c->count();
   QLA_HIP(hipMemcpyAsync(c->staging, q_host, 3 * N * sizeof(double), hipMemcpyHostToDevice,
                          c->stream));
-  QLA_HIP(qla::launch_from_f64(c->staging, N, c->fp32, c->q[c->cur][c->plane(0)],
+  QLA_HIP(qla::launch_from_f64(c->staging, c->nx, c->ny, c->pitch, c->fp32,
+                               c->q[c->cur][c->plane(0)],
                                c->q[c->cur][c->plane(1)], c->q[c->cur][c->plane(2)], c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
   c->steps = step;
@@ -358,13 +366,12 @@ qla_status qla_autotune(qla_ctx* c, int* rows_out, int* prefetch_out, int* steps
   if (!c) return fail(QLA_EINVAL, "NULL context");
   if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
   DeviceGuard g(c->device);
-  const size_t bytes = 3 * c->count() * c->elem();
   // keep the state: the trial launches overwrite both amplitude buffers
+  const size_t plane_bytes = c->plane_elems() * c->elem();
   char* save = reinterpret_cast<char*>(c->staging);
   for (int j = 0; j < 3; ++j)
-    QLA_HIP(hipMemcpyAsync(save + j * c->count() * c->elem(), c->q[c->cur][j],
-                           c->count() * c->elem(), hipMemcpyDeviceToDevice, c->stream));
-  (void)bytes;
+    QLA_HIP(hipMemcpyAsync(save + j * plane_bytes, c->q[c->cur][j], plane_bytes,
+                           hipMemcpyDeviceToDevice, c->stream));
   const int64_t steps_saved = c->steps;
   const int cur_saved = c->cur;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -457,8 +464,8 @@ qla_status qla_autotune(qla_ctx* c, int* rows_out, int* prefetch_out, int* steps
   c->cur = cur_saved;
   c->steps = steps_saved;
   for (int j = 0; j < 3; ++j)
-    QLA_HIP(hipMemcpyAsync(c->q[c->cur][j], save + j * c->count() * c->elem(),
-                           c->count() * c->elem(), hipMemcpyDeviceToDevice, c->stream));
+    QLA_HIP(hipMemcpyAsync(c->q[c->cur][j], save + j * plane_bytes, plane_bytes,
+                           hipMemcpyDeviceToDevice, c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
   if (st != QLA_OK) return st;
   c->rows_per_seg = brows;
@@ -484,8 +491,8 @@ qla_status qla_get_fields_device(qla_ctx* c, double* out, int physical) {
   if (physical && !c->have_index) return fail(QLA_ESTATE, "physical readout needs the index");
   DeviceGuard g(c->device);
   QLA_HIP(qla::launch_readout(c->q[c->cur][c->plane(0)], c->q[c->cur][c->plane(1)],
-                              c->q[c->cur][c->plane(2)], c->n64,
-                              c->count(), c->fp32, divide_mask(c, physical), out, c->stream));
+                              c->q[c->cur][c->plane(2)], c->n64, c->nx, c->ny, c->pitch,
+                              c->fp32, divide_mask(c, physical), out, c->stream));
   return QLA_OK;
 }
 
@@ -494,8 +501,8 @@ qla_status qla_get_fields(qla_ctx* c, double* out_host, int physical) {
   if (physical && !c->have_index) return fail(QLA_ESTATE, "physical readout needs the index");
   DeviceGuard g(c->device);
   QLA_HIP(qla::launch_readout(c->q[c->cur][c->plane(0)], c->q[c->cur][c->plane(1)],
-                              c->q[c->cur][c->plane(2)], c->n64,
-                              c->count(), c->fp32, divide_mask(c, physical), c->staging, c->stream));
+                              c->q[c->cur][c->plane(2)], c->n64, c->nx, c->ny, c->pitch,
+                              c->fp32, divide_mask(c, physical), c->staging, c->stream));
   QLA_HIP(hipMemcpyAsync(out_host, c->staging, 3 * c->count() * sizeof(double),
                          hipMemcpyDeviceToHost, c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
@@ -505,16 +512,16 @@ qla_status qla_get_fields(qla_ctx* c, double* out_host, int physical) {
 qla_status qla_energy_device(qla_ctx* c, double* energy_device) {
   if (!c || !energy_device) return fail(QLA_EINVAL, "NULL argument");
   DeviceGuard g(c->device);
-  QLA_HIP(qla::launch_energy(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->count(),
-                             c->fp32, c->partials, energy_device, c->stream));
+  QLA_HIP(qla::launch_energy(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->nx, c->ny,
+                             c->pitch, c->fp32, c->partials, energy_device, c->stream));
   return QLA_OK;
 }
 
 qla_status qla_energy(qla_ctx* c, double* energy) {
   if (!c || !energy) return fail(QLA_EINVAL, "NULL argument");
   DeviceGuard g(c->device);
-  QLA_HIP(qla::launch_energy(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->count(),
-                             c->fp32, c->partials, c->energy_dev, c->stream));
+  QLA_HIP(qla::launch_energy(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->nx, c->ny,
+                             c->pitch, c->fp32, c->partials, c->energy_dev, c->stream));
   QLA_HIP(hipMemcpyAsync(energy, c->energy_dev, sizeof(double), hipMemcpyDeviceToHost,
                          c->stream));
   QLA_HIP(hipStreamSynchronize(c->stream));
@@ -529,7 +536,7 @@ qla_status qla_divergence(qla_ctx* c, double* l2, double* max_abs, double* scale
   // stored planes (shared, y partner, x partner) = (q2, q3, q4) or (q5, q0, q1): the
   // in-plane field is (stored 1, stored 2), i.e. (Bx, By) or (n Ex, n Ey)
   QLA_HIP(qla::launch_divergence(c->q[c->cur][1], c->q[c->cur][2], c->n64, c->nx, c->ny,
-                                 c->delta, c->fp32, c->triple == 1, c->partials, c->diag,
+                                 c->pitch, c->delta, c->fp32, c->triple == 1, c->partials, c->diag,
                                  c->stream));
   double h[3];
   QLA_HIP(hipMemcpyAsync(h, c->diag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
@@ -546,8 +553,8 @@ qla_status qla_get_coefficients(qla_ctx* c, double* theta, double* beta_x, doubl
   DeviceGuard g(c->device);
   const size_t N = c->count();
   double* s = c->staging;
-  QLA_HIP(qla::launch_coefficients(c->n64, c->nx, c->ny, c->delta, s, s + N, s + 2 * N,
-                                   c->stream));
+  QLA_HIP(qla::launch_coefficients(c->n64, c->nx, c->ny, c->pitch, c->delta, s, s + N,
+                                   s + 2 * N, c->stream));
   double* dst[3] = {theta, beta_x, beta_y};
   for (int k = 0; k < 3; ++k)
     if (dst[k])

@@ -1,6 +1,11 @@
 // Set-up, diagnostic and readout kernels around the fused step: index preparation
 // and checks, the per-site coefficients of Eqs. (2e4) and (2e13), the initial
 // packet, the energy of Eq. (A13) and field readout.
+//
+// Site (x, y) is element y * pitch + x of a lattice plane (rows padded to the pitch)
+// and element y * nx + x of a packed array (host order: staging, readout, inputs).
+// Every kernel deals rows to blocks and the columns of a row to the threads of a
+// block, so accesses along a row are coalesced and no division is needed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -54,22 +59,23 @@ struct AddOp {
 
 __global__ __launch_bounds__(kBlock) void index_copy_kernel(const double* __restrict__ src,
                                                             size_t ld, int nx, int ny,
+                                                            size_t pitch,
                                                             double* __restrict__ n64,
                                                             float* __restrict__ n32,
                                                             unsigned long long* stats) {
   __shared__ unsigned long long lds[kBlock / 64];
-  const size_t count = static_cast<size_t>(nx) * ny;
   unsigned long long bad = 0, nmin = bits(INFINITY);
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const size_t y = i / nx, x = i - y * nx;
-    const double v = src[y * ld + x];
-    n64[i] = v;
-    if (n32) n32[i] = static_cast<float>(v);
-    if (!(v > 0.0) || !isfinite(v)) {
-      ++bad;
-    } else if (bits(v) < nmin) {
-      nmin = bits(v);
+  for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+    for (int x = threadIdx.x; x < nx; x += kBlock) {
+      const double v = src[static_cast<size_t>(y) * ld + x];
+      const size_t i = static_cast<size_t>(y) * pitch + x;
+      n64[i] = v;
+      if (n32) n32[i] = static_cast<float>(v);
+      if (!(v > 0.0) || !isfinite(v)) {
+        ++bad;
+      } else if (bits(v) < nmin) {
+        nmin = bits(v);
+      }
     }
   }
   bad = block_reduce_u64(bad, AddOp{}, lds);
@@ -82,50 +88,50 @@ __global__ __launch_bounds__(kBlock) void index_copy_kernel(const double* __rest
 }
 
 // beta/2 along x and y exactly as the step computes it.
-__device__ __forceinline__ void half_betas(const double* __restrict__ n, int nx, int ny, int x,
-                                           int y, double d4, double& hbx, double& hby,
-                                           double& m) {
-  const size_t row = static_cast<size_t>(y) * nx;
+__device__ __forceinline__ void half_betas(const double* __restrict__ n, int nx, int ny,
+                                           size_t pitch, int x, int y, double d4, double& hbx,
+                                           double& hby, double& m) {
+  const size_t row = static_cast<size_t>(y) * pitch;
   const int xl = x == 0 ? nx - 1 : x - 1, xr = x + 1 == nx ? 0 : x + 1;
   const int yl = y == 0 ? ny - 1 : y - 1, yr = y + 1 == ny ? 0 : y + 1;
   m = recip(n[row + x]);
   const double dm = d4 * m * m;
   hbx = (n[row + xr] - n[row + xl]) * dm;
-  hby = (n[static_cast<size_t>(yr) * nx + x] - n[static_cast<size_t>(yl) * nx + x]) * dm;
+  hby = (n[static_cast<size_t>(yr) * pitch + x] - n[static_cast<size_t>(yl) * pitch + x]) * dm;
 }
 
 __global__ __launch_bounds__(kBlock) void index_beta_max_kernel(const double* __restrict__ n64,
-                                                                int nx, int ny, double d4,
+                                                                int nx, int ny, size_t pitch,
+                                                                double d4,
                                                                 unsigned long long* stats) {
   __shared__ unsigned long long lds[kBlock / 64];
-  const size_t count = static_cast<size_t>(nx) * ny;
   unsigned long long mx = 0;
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
-    double hbx, hby, m;
-    half_betas(n64, nx, ny, x, y, d4, hbx, hby, m);
-    const double a = fmax(fabs(hbx), fabs(hby));
-    const unsigned long long b = isfinite(a) ? bits(a) : bits(INFINITY);
-    mx = b > mx ? b : mx;
+  for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+    for (int x = threadIdx.x; x < nx; x += kBlock) {
+      double hbx, hby, m;
+      half_betas(n64, nx, ny, pitch, x, y, d4, hbx, hby, m);
+      const double a = fmax(fabs(hbx), fabs(hby));
+      const unsigned long long b = isfinite(a) ? bits(a) : bits(INFINITY);
+      mx = b > mx ? b : mx;
+    }
   }
   mx = block_reduce_u64(mx, MaxOp{}, lds);
   if (threadIdx.x == 0) atomicMax(&stats[2], mx);
 }
 
 __global__ __launch_bounds__(kBlock) void coefficients_kernel(const double* __restrict__ n64,
-                                                              int nx, int ny, double d4,
-                                                              double* theta, double* bx,
-                                                              double* by) {
-  const size_t count = static_cast<size_t>(nx) * ny;
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
-    double hbx, hby, m;
-    half_betas(n64, nx, ny, x, y, d4, hbx, hby, m);
-    if (theta) theta[i] = d4 * m;
-    if (bx) bx[i] = hbx + hbx;
-    if (by) by[i] = hby + hby;
+                                                              int nx, int ny, size_t pitch,
+                                                              double d4, double* theta,
+                                                              double* bx, double* by) {
+  for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+    for (int x = threadIdx.x; x < nx; x += kBlock) {
+      double hbx, hby, m;
+      half_betas(n64, nx, ny, pitch, x, y, d4, hbx, hby, m);
+      const size_t i = static_cast<size_t>(y) * nx + x;  // packed outputs
+      if (theta) theta[i] = d4 * m;
+      if (bx) bx[i] = hbx + hbx;
+      if (by) by[i] = hby + hby;
+    }
   }
 }
 
@@ -135,11 +141,10 @@ __global__ __launch_bounds__(kBlock) void coefficients_kernel(const double* __re
 // n = n_out + (n_in - n_out) (1 - tanh(d / width)) / 2 (n_in at the exact centre).
 __global__ __launch_bounds__(kBlock) void ellipse_index_kernel(int nx, int ny, EllipseArgs e,
                                                                double* __restrict__ out) {
-  const size_t count = static_cast<size_t>(nx) * ny;
   const double cr = cos(e.rot), sr = sin(e.rot);
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
+  for (int y = blockIdx.x; y < ny; y += gridDim.x)
+  for (int x = threadIdx.x; x < nx; x += kBlock) {
+    const size_t i = static_cast<size_t>(y) * nx + x;  // packed output
     const double dx = x - e.xc, dy = y - e.yc;
     const double xp = dx * cr + dy * sr, yp = -dx * sr + dy * cr;
     const double u = xp / e.a, v = yp / e.b;
@@ -153,14 +158,13 @@ __global__ __launch_bounds__(kBlock) void ellipse_index_kernel(int nx, int ny, E
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void packet_kernel(const double* __restrict__ n64, int nx,
-                                                        int ny, PacketArgs p, T* q2, T* q3,
-                                                        T* q4) {
-  const size_t count = static_cast<size_t>(nx) * ny;
+                                                        int ny, size_t pitch, PacketArgs p, T* q2,
+                                                        T* q3, T* q4) {
   const double kx = cos(p.phi), ky = sin(p.phi);
   const double two_pi = 6.283185307179586476925286766559;
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
+  for (int y = blockIdx.x; y < ny; y += gridDim.x)
+  for (int x = threadIdx.x; x < nx; x += kBlock) {
+    const size_t i = static_cast<size_t>(y) * pitch + x;
     double dx = x - p.x0, dy = y - p.y0;
     dx -= nx * floor(dx / nx + 0.5);
     dy -= ny * floor(dy / ny + 0.5);
@@ -186,15 +190,18 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void energy_partial_kernel(const T* __restrict__ q2,
                                                                 const T* __restrict__ q3,
                                                                 const T* __restrict__ q4,
-                                                                size_t count, double* partials) {
+                                                                int nx, int ny, size_t pitch,
+                                                                double* partials) {
   __shared__ double lds[kBlock];
   double acc = 0.0;
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const double a = q2[i], b = q3[i], c = q4[i];
-    acc = fma(a, a, acc);
-    acc = fma(b, b, acc);
-    acc = fma(c, c, acc);
+  for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+    for (int x = threadIdx.x; x < nx; x += kBlock) {
+      const size_t i = static_cast<size_t>(y) * pitch + x;
+      const double a = q2[i], b = q3[i], c = q4[i];
+      acc = fma(a, a, acc);
+      acc = fma(b, b, acc);
+      acc = fma(c, c, acc);
+    }
   }
   lds[threadIdx.x] = acc;
   __syncthreads();
@@ -222,14 +229,18 @@ __global__ __launch_bounds__(kBlock) void readout_kernel(const T* __restrict__ q
                                                          const T* __restrict__ q3,
                                                          const T* __restrict__ q4,
                                                          const double* __restrict__ n64,
-                                                         size_t count, int divide_by_n,
+                                                         int nx, int ny, size_t pitch,
+                                                         int divide_by_n,
                                                          double* __restrict__ out) {
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const double a = q2[i], b = q3[i], c = q4[i];
-    out[i] = (divide_by_n & 1) ? a / n64[i] : a;
-    out[count + i] = (divide_by_n & 2) ? b / n64[i] : b;
-    out[2 * count + i] = (divide_by_n & 4) ? c / n64[i] : c;
+  const size_t count = static_cast<size_t>(nx) * ny;
+  for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+    for (int x = threadIdx.x; x < nx; x += kBlock) {
+      const size_t i = static_cast<size_t>(y) * pitch + x, o = static_cast<size_t>(y) * nx + x;
+      const double a = q2[i], b = q3[i], c = q4[i];
+      out[o] = (divide_by_n & 1) ? a / n64[i] : a;
+      out[count + o] = (divide_by_n & 2) ? b / n64[i] : b;
+      out[2 * count + o] = (divide_by_n & 4) ? c / n64[i] : c;
+    }
   }
 }
 
@@ -239,17 +250,15 @@ __global__ __launch_bounds__(kBlock) void readout_kernel(const T* __restrict__ q
 template <typename T>
 __global__ __launch_bounds__(kBlock) void divergence_partial_kernel(
     const T* __restrict__ fx, const T* __restrict__ fy, const double* __restrict__ n64, int nx,
-    int ny, double inv_2d, int weight_n, double* __restrict__ partials) {
+    int ny, size_t pitch, double inv_2d, int weight_n, double* __restrict__ partials) {
   __shared__ double l0[kBlock], l1[kBlock], l2[kBlock];
-  const size_t count = static_cast<size_t>(nx) * ny;
   double s_div = 0.0, s_scale = 0.0, m_div = 0.0;
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    const int y = static_cast<int>(i / nx), x = static_cast<int>(i - static_cast<size_t>(y) * nx);
-    const size_t xl = static_cast<size_t>(y) * nx + (x == 0 ? nx - 1 : x - 1);
-    const size_t xr = static_cast<size_t>(y) * nx + (x == nx - 1 ? 0 : x + 1);
-    const size_t yd = static_cast<size_t>(y == 0 ? ny - 1 : y - 1) * nx + x;
-    const size_t yu = static_cast<size_t>(y == ny - 1 ? 0 : y + 1) * nx + x;
+  for (int y = blockIdx.x; y < ny; y += gridDim.x)
+  for (int x = threadIdx.x; x < nx; x += kBlock) {
+    const size_t xl = static_cast<size_t>(y) * pitch + (x == 0 ? nx - 1 : x - 1);
+    const size_t xr = static_cast<size_t>(y) * pitch + (x == nx - 1 ? 0 : x + 1);
+    const size_t yd = static_cast<size_t>(y == 0 ? ny - 1 : y - 1) * pitch + x;
+    const size_t yu = static_cast<size_t>(y == ny - 1 ? 0 : y + 1) * pitch + x;
     double fxr = fx[xr], fxl = fx[xl], fyu = fy[yu], fyd = fy[yd];
     if (weight_n) {
       fxr *= n64[xr];
@@ -305,77 +314,77 @@ __global__ __launch_bounds__(kEnergyPartials) void divergence_final_kernel(
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void from_f64_kernel(const double* __restrict__ src,
-                                                          size_t count, T* q2, T* q3, T* q4) {
-  for (size_t i = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; i < count;
-       i += static_cast<size_t>(gridDim.x) * kBlock) {
-    q2[i] = static_cast<T>(src[i]);
-    q3[i] = static_cast<T>(src[count + i]);
-    q4[i] = static_cast<T>(src[2 * count + i]);
+__global__ __launch_bounds__(kBlock) void from_f64_kernel(const double* __restrict__ src, int nx,
+                                                          int ny, size_t pitch, T* q2, T* q3,
+                                                          T* q4) {
+  const size_t count = static_cast<size_t>(nx) * ny;
+  for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+    for (int x = threadIdx.x; x < nx; x += kBlock) {
+      const size_t i = static_cast<size_t>(y) * pitch + x, o = static_cast<size_t>(y) * nx + x;
+      q2[i] = static_cast<T>(src[o]);
+      q3[i] = static_cast<T>(src[count + o]);
+      q4[i] = static_cast<T>(src[2 * count + o]);
+    }
   }
 }
 
-unsigned grid_for(size_t count) {
-  const size_t blocks = (count + kBlock - 1) / kBlock;
-  return static_cast<unsigned>(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
-}
+// One block per row (up to 8192 blocks, which then stride over the rows).
+unsigned grid_for(int ny) { return static_cast<unsigned>(ny < 8192 ? (ny > 0 ? ny : 1) : 8192); }
 
 }  // namespace
 
-hipError_t launch_index_prepare(const double* src, size_t ld, int nx, int ny, double delta,
-                                double* n64, float* n32, unsigned long long* stats,
-                                hipStream_t stream) {
-  const size_t count = static_cast<size_t>(nx) * ny;
-  hipLaunchKernelGGL(index_copy_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, src, ld,
-                     nx, ny, n64, n32, stats);
+hipError_t launch_index_prepare(const double* src, size_t ld, int nx, int ny, size_t pitch,
+                                double delta, double* n64, float* n32,
+                                unsigned long long* stats, hipStream_t stream) {
+  hipLaunchKernelGGL(index_copy_kernel, dim3(grid_for(ny)), dim3(kBlock), 0, stream, src, ld,
+                     nx, ny, pitch, n64, n32, stats);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(index_beta_max_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64,
-                     nx, ny, 0.25 * delta, stats);
+  hipLaunchKernelGGL(index_beta_max_kernel, dim3(grid_for(ny)), dim3(kBlock), 0, stream, n64,
+                     nx, ny, pitch, 0.25 * delta, stats);
   return hipGetLastError();
 }
 
-hipError_t launch_coefficients(const double* n64, int nx, int ny, double delta, double* theta,
-                               double* beta_x, double* beta_y, hipStream_t stream) {
-  const size_t count = static_cast<size_t>(nx) * ny;
-  hipLaunchKernelGGL(coefficients_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64, nx,
-                     ny, 0.25 * delta, theta, beta_x, beta_y);
+hipError_t launch_coefficients(const double* n64, int nx, int ny, size_t pitch, double delta,
+                               double* theta, double* beta_x, double* beta_y,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(coefficients_kernel, dim3(grid_for(ny)), dim3(kBlock), 0, stream, n64, nx,
+                     ny, pitch, 0.25 * delta, theta, beta_x, beta_y);
   return hipGetLastError();
 }
 
 hipError_t launch_ellipse_index(int nx, int ny, const EllipseArgs& e, double* out,
                                 hipStream_t stream) {
-  const size_t count = static_cast<size_t>(nx) * ny;
-  hipLaunchKernelGGL(ellipse_index_kernel, dim3(grid_for(count)), dim3(kBlock), 0, stream, nx, ny,
+  hipLaunchKernelGGL(ellipse_index_kernel, dim3(grid_for(ny)), dim3(kBlock), 0, stream, nx, ny,
                      e, out);
   return hipGetLastError();
 }
 
-hipError_t launch_packet(const double* n64, int nx, int ny, const PacketArgs& p, bool fp32,
-                         void* q2, void* q3, void* q4, hipStream_t stream) {
-  const size_t count = static_cast<size_t>(nx) * ny;
+hipError_t launch_packet(const double* n64, int nx, int ny, size_t pitch, const PacketArgs& p,
+                         bool fp32, void* q2, void* q3, void* q4, hipStream_t stream) {
   if (fp32) {
-    hipLaunchKernelGGL(packet_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64,
-                       nx, ny, p, static_cast<float*>(q2), static_cast<float*>(q3),
+    hipLaunchKernelGGL(packet_kernel<float>, dim3(grid_for(ny)), dim3(kBlock), 0, stream, n64,
+                       nx, ny, pitch, p, static_cast<float*>(q2), static_cast<float*>(q3),
                        static_cast<float*>(q4));
   } else {
-    hipLaunchKernelGGL(packet_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, stream, n64,
-                       nx, ny, p, static_cast<double*>(q2), static_cast<double*>(q3),
+    hipLaunchKernelGGL(packet_kernel<double>, dim3(grid_for(ny)), dim3(kBlock), 0, stream, n64,
+                       nx, ny, pitch, p, static_cast<double*>(q2), static_cast<double*>(q3),
                        static_cast<double*>(q4));
   }
   return hipGetLastError();
 }
 
-hipError_t launch_energy(const void* q2, const void* q3, const void* q4, size_t count, bool fp32,
-                         double* partials, double* out, hipStream_t stream) {
+hipError_t launch_energy(const void* q2, const void* q3, const void* q4, int nx, int ny,
+                         size_t pitch, bool fp32, double* partials, double* out,
+                         hipStream_t stream) {
   if (fp32) {
     hipLaunchKernelGGL(energy_partial_kernel<float>, dim3(kEnergyPartials), dim3(kBlock), 0,
                        stream, static_cast<const float*>(q2), static_cast<const float*>(q3),
-                       static_cast<const float*>(q4), count, partials);
+                       static_cast<const float*>(q4), nx, ny, pitch, partials);
   } else {
     hipLaunchKernelGGL(energy_partial_kernel<double>, dim3(kEnergyPartials), dim3(kBlock), 0,
                        stream, static_cast<const double*>(q2), static_cast<const double*>(q3),
-                       static_cast<const double*>(q4), count, partials);
+                       static_cast<const double*>(q4), nx, ny, pitch, partials);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -385,32 +394,32 @@ hipError_t launch_energy(const void* q2, const void* q3, const void* q4, size_t 
 }
 
 hipError_t launch_readout(const void* q2, const void* q3, const void* q4, const double* n64,
-                          size_t count, bool fp32, int divide_by_n, double* out,
+                          int nx, int ny, size_t pitch, bool fp32, int divide_by_n, double* out,
                           hipStream_t stream) {
   if (fp32) {
-    hipLaunchKernelGGL(readout_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
+    hipLaunchKernelGGL(readout_kernel<float>, dim3(grid_for(ny)), dim3(kBlock), 0, stream,
                        static_cast<const float*>(q2), static_cast<const float*>(q3),
-                       static_cast<const float*>(q4), n64, count, divide_by_n, out);
+                       static_cast<const float*>(q4), n64, nx, ny, pitch, divide_by_n, out);
   } else {
-    hipLaunchKernelGGL(readout_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
+    hipLaunchKernelGGL(readout_kernel<double>, dim3(grid_for(ny)), dim3(kBlock), 0, stream,
                        static_cast<const double*>(q2), static_cast<const double*>(q3),
-                       static_cast<const double*>(q4), n64, count, divide_by_n, out);
+                       static_cast<const double*>(q4), n64, nx, ny, pitch, divide_by_n, out);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_divergence(const void* fx, const void* fy, const double* n64, int nx, int ny,
-                             double delta, bool fp32, bool weight_n, double* partials,
-                             double* out, hipStream_t stream) {
+                             size_t pitch, double delta, bool fp32, bool weight_n,
+                             double* partials, double* out, hipStream_t stream) {
   const double inv_2d = 0.5 / delta;
   if (fp32) {
     hipLaunchKernelGGL(divergence_partial_kernel<float>, dim3(kEnergyPartials), dim3(kBlock), 0,
                        stream, static_cast<const float*>(fx), static_cast<const float*>(fy), n64,
-                       nx, ny, inv_2d, weight_n ? 1 : 0, partials);
+                       nx, ny, pitch, inv_2d, weight_n ? 1 : 0, partials);
   } else {
     hipLaunchKernelGGL(divergence_partial_kernel<double>, dim3(kEnergyPartials), dim3(kBlock), 0,
                        stream, static_cast<const double*>(fx), static_cast<const double*>(fy),
-                       n64, nx, ny, inv_2d, weight_n ? 1 : 0, partials);
+                       n64, nx, ny, pitch, inv_2d, weight_n ? 1 : 0, partials);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -419,15 +428,15 @@ hipError_t launch_divergence(const void* fx, const void* fy, const double* n64, 
   return hipGetLastError();
 }
 
-hipError_t launch_from_f64(const double* src, size_t count, bool fp32, void* q2, void* q3,
-                           void* q4, hipStream_t stream) {
+hipError_t launch_from_f64(const double* src, int nx, int ny, size_t pitch, bool fp32, void* q2,
+                           void* q3, void* q4, hipStream_t stream) {
   if (fp32) {
-    hipLaunchKernelGGL(from_f64_kernel<float>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
-                       src, count, static_cast<float*>(q2), static_cast<float*>(q3),
+    hipLaunchKernelGGL(from_f64_kernel<float>, dim3(grid_for(ny)), dim3(kBlock), 0, stream, src,
+                       nx, ny, pitch, static_cast<float*>(q2), static_cast<float*>(q3),
                        static_cast<float*>(q4));
   } else {
-    hipLaunchKernelGGL(from_f64_kernel<double>, dim3(grid_for(count)), dim3(kBlock), 0, stream,
-                       src, count, static_cast<double*>(q2), static_cast<double*>(q3),
+    hipLaunchKernelGGL(from_f64_kernel<double>, dim3(grid_for(ny)), dim3(kBlock), 0, stream, src,
+                       nx, ny, pitch, static_cast<double*>(q2), static_cast<double*>(q3),
                        static_cast<double*>(q4));
   }
   return hipGetLastError();

@@ -192,8 +192,8 @@ qla_status enqueue_passes(qla_batch* b, qla::BatchLaunch B, int p0, int p1) {
 qla_status save_states(qla_batch* b) {
   for (qla_ctx* c : b->ctx)
     for (int j = 0; j < 3; ++j)
-      QLA_HIP(hipMemcpyAsync(reinterpret_cast<char*>(c->staging) + j * c->count() * c->elem(),
-                             c->q[c->cur][j], c->count() * c->elem(), hipMemcpyDeviceToDevice,
+      QLA_HIP(hipMemcpyAsync(reinterpret_cast<char*>(c->staging) + j * c->plane_elems() * c->elem(),
+                             c->q[c->cur][j], c->plane_elems() * c->elem(), hipMemcpyDeviceToDevice,
                              b->stream));
   return QLA_OK;
 }
@@ -202,8 +202,8 @@ qla_status restore_states(qla_batch* b) {
   for (qla_ctx* c : b->ctx)
     for (int j = 0; j < 3; ++j)
       QLA_HIP(hipMemcpyAsync(c->q[c->cur][j],
-                             reinterpret_cast<char*>(c->staging) + j * c->count() * c->elem(),
-                             c->count() * c->elem(), hipMemcpyDeviceToDevice, b->stream));
+                             reinterpret_cast<char*>(c->staging) + j * c->plane_elems() * c->elem(),
+                             c->plane_elems() * c->elem(), hipMemcpyDeviceToDevice, b->stream));
   return QLA_OK;
 }
 
@@ -287,8 +287,10 @@ qla_status qla_batch_create(int count, const int* nx, const int* ny, const doubl
     b->own_stream = true;
   }
   for (int i = 0; i < count; ++i) {
-    // the batched kernel addresses each plane through one buffer descriptor
-    const long long bytes = static_cast<long long>(nx[i]) * ny[i] * (b->fp32 ? 4 : 8);
+    // the batched kernel addresses each plane through one buffer descriptor (rows padded
+    // to whole 128-byte lines)
+    const long long elem = b->fp32 ? 4 : 8, line = 128 / elem;
+    const long long bytes = (nx[i] + line - 1) / line * line * ny[i] * elem;
     if (bytes > (1ll << 31)) {
       if (b->own_stream) (void)hipStreamDestroy(b->stream);
       delete b;

@@ -146,8 +146,8 @@ struct StepArgs {
   T* q2o;
   T* q3o;
   T* q4o;
-  unsigned plane_bytes;  // nx * ny * sizeof(T), at most 2^31
-  int nx, ny, strips, segs, rows_per_seg, iters;
+  unsigned plane_bytes;  // pitch * ny * sizeof(T) (planes of at most 2^31 bytes), else 0
+  int nx, ny, pitch, strips, segs, rows_per_seg, iters;  // pitch: row pitch in elements
   T d4;  // delta / 4
   T dc;  // collision angle over 1/n: +delta/4 (E_z triple) or -delta/4 (B_z triple)
 };
@@ -190,7 +190,7 @@ struct Marcher {
   char *b2o, *b3o, *b4o;
   unsigned col_bytes;    // this lane's (first) column (wrapped) in bytes
   unsigned store_bytes;  // col_bytes for lanes that own an output column, else kDropOffset
-  unsigned row_bytes;    // nx * sizeof(T)
+  unsigned row_bytes;    // pitch * sizeof(T)
   int yin;               // row index of the next row to load (wrapped)
 
   static constexpr int slot(int s, int back) { return ((s - back) % kWin + kWin) % kWin; }
@@ -396,7 +396,7 @@ __device__ __forceinline__ void march(const StepArgs<T>& g, int strip, int seg, 
   const bool store_lane = c >= 0 && c < strip_cols && x0 + c < g.nx;
   w.col_bytes = static_cast<unsigned>(col) * sizeof(T);
   w.store_bytes = store_lane ? w.col_bytes : kDropOffset;
-  w.row_bytes = static_cast<unsigned>(g.nx) * sizeof(T);
+  w.row_bytes = static_cast<unsigned>(g.pitch) * sizeof(T);
   if constexpr (AM == kRowDescriptors) {
     w.b2i = reinterpret_cast<const char*>(g.q2i);
     w.b3i = reinterpret_cast<const char*>(g.q3i);
@@ -496,10 +496,11 @@ StepArgs<T> make_args(const StepLaunch& L) {
   g.q3o = static_cast<T*>(L.out[1]);
   g.q4o = static_cast<T*>(L.out[2]);
   // the descriptor range of a plane (with per-row descriptors only a row's is used)
-  const size_t plane = static_cast<size_t>(L.nx) * L.ny * sizeof(T);
+  const size_t plane = static_cast<size_t>(L.pitch) * L.ny * sizeof(T);
   g.plane_bytes = static_cast<unsigned>(plane <= kMaxPlaneDescriptorBytes ? plane : 0);
   g.nx = L.nx;
   g.ny = L.ny;
+  g.pitch = L.pitch;
   g.strips = (L.nx + strip_cols - 1) / strip_cols;
   // the requested rows plus both halos, rounded up to the unroll depth; the
   // segment then takes every row those iterations produce
@@ -517,7 +518,7 @@ hipError_t launch_typed(const StepLaunch& L, hipStream_t stream) {
   const int blocks_per_seg = (g.strips + kWavesPerBlock - 1) / kWavesPerBlock;
   const int blocks = blocks_per_seg * g.segs;
   // planes beyond one descriptor's 2^31-byte range are addressed row by row
-  const bool rows = static_cast<size_t>(L.nx) * L.ny * sizeof(T) > kMaxPlaneDescriptorBytes;
+  const bool rows = static_cast<size_t>(L.pitch) * L.ny * sizeof(T) > kMaxPlaneDescriptorBytes;
   if (rows) {
     hipLaunchKernelGGL((qla_step_ez_kernel<T, VMODE, CLS, kWin, PF, TS, CPL, kRowDescriptors>),
                        dim3(blocks), dim3(kWave * kWavesPerBlock), 0, stream, g);

@@ -73,7 +73,9 @@ def test_packet_matches_oracle(qla, prec):
             lat.init_packet(p)
             got = lat.fields()
             want = oracle.packet_from(n, p)[2:5]
-            tol = 1e-15 if prec == 0 else 1e-7
+            # FP64: exp and cos of the device library against the host's, each within
+            # about 1 ulp, and their product: a few ulps of the largest value
+            tol = 2e-15 if prec == 0 else 1e-7
             assert np.abs(got - want).max() <= tol * np.abs(want).max()
             phys = lat.fields(physical=True)
             ez, bxf, byf = oracle.physical_fields(oracle.packet_from(n, p), n)
