@@ -221,10 +221,12 @@ qla_status qla_get_lane_columns(const qla_ctx *ctx, int *columns);
 
 /* Pick the tuning of the step kernel for this context's lattice by timing
  * candidate segment heights, prefetch depths, steps per pass and (FP32, even nx)
- * columns per lane on it (tens of milliseconds). The state and step counter are
- * saved and restored, so results are unaffected; the chosen values are kept and
- * returned through the non-NULL pointers (columns per lane: qla_get_lane_columns).
- * Synchronises. QLA_ESTATE if no index is set. */
+ * columns per lane on it (tens of milliseconds to seconds, growing with the
+ * lattice). The fastest four are timed twice more; among those within 3% of the
+ * best, the one that recomputes the fewest halo sites is kept. The state and step
+ * counter are saved and restored, so results are unaffected; the chosen values are
+ * kept and returned through the non-NULL pointers (columns per lane:
+ * qla_get_lane_columns). Synchronises. QLA_ESTATE if no index is set. */
 qla_status qla_autotune(qla_ctx *ctx, int *rows_per_segment, int *prefetch_rows,
                         int *steps_per_pass);
 
