@@ -217,3 +217,48 @@ def test_full_batched_workload_against_the_oracle(qla):
             assert err <= 1e-5
     finally:
         qla.qla_batch_destroy(b)
+
+
+def test_batch_degenerate_cases(qla):
+    """A lattice with no steps is left as it was, a single-lattice batch equals the
+    single-lattice path, and a batch whose step counts are all zero runs nothing."""
+    sizes = [(40, 24), (33, 50), (64, 9)]
+    b = qla.qla_batch_create([s[0] for s in sizes], [s[1] for s in sizes], [0.25] * 3,
+                             precision=0)
+    try:
+        inputs = []
+        for i, (nx, ny) in enumerate(sizes):
+            n, p = _instance(60 + i, nx, ny)
+            inputs.append((n, p))
+            ctx = qla.qla_batch_context(b, i)
+            qla.qla_set_index(ctx, n)
+            qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam)
+        before = qla.qla_get_fields(qla.qla_batch_context(b, 0), 40, 24)
+        qla.qla_batch_plan(b, [0, 6, 3], 0)
+        assert qla.qla_batch_plan_info(b)["passes"] == 6
+        qla.qla_batch_run(b)
+        np.testing.assert_array_equal(qla.qla_get_fields(qla.qla_batch_context(b, 0), 40, 24),
+                                      before)
+        assert qla.qla_step_count(qla.qla_batch_context(b, 0)) == 0
+        for i, s in ((1, 6), (2, 3)):
+            nx, ny = sizes[i]
+            np.testing.assert_array_equal(qla.qla_get_fields(qla.qla_batch_context(b, i), nx, ny),
+                                          _single(qla, *inputs[i], s, 0))
+        qla.qla_batch_plan(b, [0, 0, 0], 0)
+        info = qla.qla_batch_plan_info(b)
+        assert info["passes"] == 0 and info["site_updates"] == 0
+        qla.qla_batch_run(b)
+        assert qla.qla_step_count(qla.qla_batch_context(b, 2)) == 3
+    finally:
+        qla.qla_batch_destroy(b)
+    one = qla.qla_batch_create([72], [40], [0.25], precision=1)
+    try:
+        n, p = _instance(70, 72, 40)
+        ctx = qla.qla_batch_context(one, 0)
+        qla.qla_set_index(ctx, n)
+        qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam)
+        qla.qla_batch_plan(one, [10], 0)
+        qla.qla_batch_run(one)
+        np.testing.assert_array_equal(qla.qla_get_fields(ctx, 72, 40), _single(qla, n, p, 10, 1))
+    finally:
+        qla.qla_batch_destroy(one)
