@@ -104,3 +104,24 @@ def test_bz_triple_rejects_the_printed_potentials_and_bad_triples():
     assert lib.qla_create_triple(64, 64, 0.25, 0, qla.QLA_V_BSTREAM, qla.QLA_TRIPLE_BZ, None,
                                  ctypes.byref(out)) == qla.QLA_EINVAL
     assert lib.qla_divergence(None, None, None, None) == qla.QLA_EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """No CPU fallback: without the built library the binding raises instead of
+    computing anything (checked in a fresh interpreter, the library not yet loaded)."""
+    import subprocess
+    import sys
+    missing = str(tmp_path / "libqla.so")
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2604_21128_amd import qla\n"
+            "qla.LIB_PATH = %r\n"
+            "try:\n"
+            "    qla.load(%r)\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n"
+            "else:\n"
+            "    print('loaded')\n") % (ROOT, missing, missing)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("raised") and "not built" in out.stdout
