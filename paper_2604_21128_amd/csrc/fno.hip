@@ -57,6 +57,143 @@ __global__ void cast_kernel(const float* __restrict__ s, uint16_t* __restrict__ 
     d[i] = f32_to_bf16(s[i]);
 }
 
+// Inference projection in one pass:
+//   out[b][o][p] = bq2[o] + sum_h Q2[o][h] GELU(bq1[h] + sum_c Q1[h][c] v[b][c][p]).
+// The C2-channel hidden layer never leaves the chip (the two-GEMM path writes it to
+// HBM in BF16 and reads it back: 2 x 2 C2 bytes per pixel). Wave w owns hidden rows
+// 32w .. 32w + 31 and keeps their Q1 fragments in registers; bq1 and Q2 sit in LDS.
+// The block then strides over tiles of 64 pixels of one sample: the tile's channels
+// go through LDS 32 at a time (each thread fetches 8 pixels of one channel, 16 bytes,
+// and stores them pixel-major, 8-channel groups XORed with bits 3-4 of the pixel so
+// the transposing stores spread over the banks), the waves multiply with the
+// 32x32x16 BF16 matrix instruction (accumulator 4i + j = hidden row 8i + 4(lane/32)
+// + j, pixel lane % 32), add the bias, apply GELU in FP32 and fold their rows into the
+// Cout output sums, which meet in LDS. Channels, rows and pixels beyond C, C2 and P
+// are zero. Shapes: C <= 64, C2 <= 128, Cout <= 4 (else the two-GEMM path).
+constexpr int kProjPix = 64, kProjK = 32, kProjMaxC = 64, kProjMaxC2 = 128, kProjMaxOut = 4;
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float gelu_f(float x) {
+  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+}
+
+__device__ __forceinline__ int proj_col(int r, int k) {
+  return ((((k >> 3) ^ (r >> 3)) & 3) << 3) | (k & 7);
+}
+
+__global__ __launch_bounds__(256) void projection_fused_kernel(
+    const uint16_t* __restrict__ v, const uint16_t* __restrict__ q1,
+    const float* __restrict__ bq1, const uint16_t* __restrict__ q2,
+    const float* __restrict__ bq2, int C, int C2, int Cout, long long P, int B,
+    float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint16_t vs[kProjPix][kProjK + 8];
+  __shared__ float red[4][kProjMaxOut][kProjPix];
+  __shared__ float sb1[kProjMaxC2], sq2[kProjMaxOut][kProjMaxC2];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int hl = lane & 31, kh = 8 * (lane >> 5);
+  for (int i = t; i < kProjMaxC2; i += 256) sb1[i] = i < C2 ? bq1[i] : 0.f;
+  for (int i = t; i < kProjMaxOut * kProjMaxC2; i += 256) {
+    const int o = i / kProjMaxC2, h = i % kProjMaxC2;
+    sq2[o][h] = (o < Cout && h < C2) ? bf16_to_f32(q2[o * C2 + h]) : 0.f;
+  }
+  // this lane's A fragments: row 32w + hl of Q1, channels kc + kk + kh .. + 7
+  const int hr = 32 * w + hl;
+  bf16x8_t afr[kProjMaxC / 16];
+#pragma unroll
+  for (int f = 0; f < kProjMaxC / 16; ++f) {
+    const int k = 16 * f + kh;
+    uint16_t av[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      av[i] = (hr < C2 && k + i < C) ? q1[static_cast<long long>(hr) * C + k + i] : uint16_t(0);
+    afr[f] = __builtin_bit_cast(bf16x8_t, av);
+  }
+  const int fk = t >> 3, fr = (t & 7) * 8;  // fetch: channel kc + fk, pixels fr .. fr + 7
+  const long long tiles_per_sample = (P + kProjPix - 1) / kProjPix;
+  const long long tiles = tiles_per_sample * B;
+  for (long long tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int b = static_cast<int>(tile / tiles_per_sample);
+    const long long p0 = (tile % tiles_per_sample) * kProjPix;
+    const uint16_t* vb = v + static_cast<long long>(b) * C * P;
+    f32x16_t acc0 = {}, acc1 = {};
+#pragma unroll
+    for (int kc = 0; kc < kProjMaxC; kc += kProjK) {
+      if (kc >= C) break;
+      uint16_t e[8];
+      {
+        const int c = kc + fk;
+        const long long pp = p0 + fr;
+        const uint16_t* src = vb + static_cast<long long>(c) * P + pp;
+        if (c < C && pp + 8 <= P && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+          const uint4 q = *reinterpret_cast<const uint4*>(src);
+          __builtin_memcpy(e, &q, 16);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) e[i] = (c < C && pp + i < P) ? src[i] : uint16_t(0);
+        }
+      }
+      __syncthreads();  // the previous tile has been read
+#pragma unroll
+      for (int i = 0; i < 8; ++i) vs[fr + i][proj_col(fr + i, fk)] = e[i];
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kProjK; kk += 16) {
+        const int kg = kk + kh;
+        const bf16x8_t b0 = *reinterpret_cast<const bf16x8_t*>(&vs[hl][proj_col(hl, kg)]);
+        const bf16x8_t b1 =
+            *reinterpret_cast<const bf16x8_t*>(&vs[32 + hl][proj_col(32 + hl, kg)]);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[(kc + kk) / 16], b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[(kc + kk) / 16], b1, acc1, 0, 0, 0);
+      }
+    }
+    float part[kProjMaxOut][2];
+#pragma unroll
+    for (int o = 0; o < kProjMaxOut; ++o) part[o][0] = part[o][1] = 0.f;
+    if (32 * w < C2) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int h = 32 * w + 8 * i + 4 * (lane >> 5) + j;  // < kProjMaxC2
+          const float bias = sb1[h];
+          const float g0 = gelu_f(acc0[4 * i + j] + bias);
+          const float g1 = gelu_f(acc1[4 * i + j] + bias);
+#pragma unroll
+          for (int o = 0; o < kProjMaxOut; ++o) {
+            const float q = sq2[o][h];  // zero beyond C2 and Cout
+            part[o][0] += q * g0;
+            part[o][1] += q * g1;
+          }
+        }
+      }
+    }
+    // lanes l and l + 32 hold the same pixels (different hidden rows)
+#pragma unroll
+    for (int o = 0; o < kProjMaxOut; ++o) {
+      part[o][0] += __shfl_xor(part[o][0], 32);
+      part[o][1] += __shfl_xor(part[o][1], 32);
+    }
+    if (lane < 32) {
+#pragma unroll
+      for (int o = 0; o < kProjMaxOut; ++o) {
+        red[w][o][lane] = part[o][0];
+        red[w][o][32 + lane] = part[o][1];
+      }
+    }
+    __syncthreads();
+    for (int idx = t; idx < Cout * kProjPix; idx += 256) {
+      const int o = idx / kProjPix, px = idx % kProjPix;
+      const long long pp = p0 + px;
+      if (pp >= P) continue;
+      const float sum = bq2[o] + red[0][o][px] + red[1][o][px] + red[2][o][px] + red[3][o][px];
+      out[(static_cast<long long>(b) * Cout + o) * P + pp] = sum;
+    }
+    // red and vs are rewritten only after the next tile's first barrier
+  }
+}
+
 // S[(b,o)][2kyi+p][kx] = sum_c R[kyi][kx][c][o] (complex) * T[(b,c)][2kyi+p][kx]
 __global__ void mix_forward_kernel(const float* __restrict__ T, const float* __restrict__ R,
                                    uint16_t* __restrict__ S, int B, int C, int m) {
@@ -571,7 +708,17 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
       QLA_GEMM(g);
     }
   }
-  // projection: h = GELU(Q1 v_L + bq1), out = Q2 h + bq2
+  // projection: h = GELU(Q1 v_L + bq1), out = Q2 h + bq2 (inference: in one pass)
+  if (!training && C <= kProjMaxC && f->C2 <= kProjMaxC2 && f->Cout <= kProjMaxOut) {
+    // enough blocks to fill the chip several times over; each strides over tiles
+    const long long tiles = (static_cast<long long>(P) + kProjPix - 1) / kProjPix * B;
+    const dim3 grid(static_cast<unsigned>(tiles < 4096 ? tiles : 4096));
+    hipLaunchKernelGGL(projection_fused_kernel, grid, dim3(256), 0, f->stream, f->v[f->L], f->w16 + f->w16_Q1(), f->p + f->o_bq1,
+                       f->w16 + f->w16_Q2(), f->p + f->o_bq2, C, f->C2, f->Cout,
+                       static_cast<long long>(P), B, f->out);
+    QLA_HIP(hipGetLastError());
+    return QLA_OK;
+  }
   {
     GemmDesc g = pointwise(f->w16 + f->w16_Q1(), false, f->C2, C, f->v[f->L], B, P);
     g.bias = f->p + f->o_bq1;
