@@ -57,6 +57,71 @@ __global__ void cast_kernel(const float* __restrict__ s, uint16_t* __restrict__ 
     d[i] = f32_to_bf16(s[i]);
 }
 
+// Lift, v[b][c][p] = BF16(bp[c] + sum_i Wp[c][i] in[b][i][p]): with few input
+// channels the product is a pure stream (read Cin, write C BF16 values per pixel), so
+// it runs on the vector units: each thread takes 8 consecutive pixels, reads its
+// inputs with 16-byte loads and writes each output channel's 8 values with one
+// 16-byte store (a wavefront covers 1 KB of one channel's row per store).
+// Weights are the BF16 copies the GEMM path uses. Shapes: Cin <= 8, C <= 256.
+constexpr int kLiftMaxIn = 8, kLiftMaxC = 256;
+
+__global__ __launch_bounds__(256) void lift_kernel(const uint16_t* __restrict__ in,
+                                                   const uint16_t* __restrict__ w16,
+                                                   const float* __restrict__ bias, int Cin,
+                                                   int C, long long P, int B,
+                                                   uint16_t* __restrict__ out) {
+  __shared__ float sw[kLiftMaxC][kLiftMaxIn];
+  __shared__ float sb[kLiftMaxC];
+  for (int i = threadIdx.x; i < C * kLiftMaxIn; i += 256) {
+    const int c = i / kLiftMaxIn, k = i % kLiftMaxIn;
+    sw[c][k] = k < Cin ? bf16_to_f32(w16[c * Cin + k]) : 0.f;
+  }
+  for (int c = threadIdx.x; c < C; c += 256) sb[c] = bias[c];
+  __syncthreads();
+  const long long groups = (P + 7) / 8;  // 8-pixel groups per sample
+  for (long long gi = blockIdx.x * 256LL + threadIdx.x; gi < groups * B;
+       gi += static_cast<long long>(gridDim.x) * 256) {
+    const int b = static_cast<int>(gi / groups);
+    const long long p = (gi % groups) * 8;
+    const bool full = p + 8 <= P;
+    float x[kLiftMaxIn][8];
+#pragma unroll
+    for (int i = 0; i < kLiftMaxIn; ++i) {
+      uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (i < Cin) {
+        const uint16_t* src = in + (static_cast<long long>(b) * Cin + i) * P + p;
+        if (full && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+          const uint4 q = *reinterpret_cast<const uint4*>(src);
+          __builtin_memcpy(e, &q, 16);
+        } else {
+          for (int k = 0; k < 8; ++k) e[k] = p + k < P ? src[k] : uint16_t(0);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[i][k] = bf16_to_f32(e[k]);
+    }
+    for (int c = 0; c < C; ++c) {
+      uint16_t o[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        float a = sb[c];
+#pragma unroll
+        for (int i = 0; i < kLiftMaxIn; ++i) a = fmaf(sw[c][i], x[i][k], a);
+        o[k] = f32_to_bf16(a);
+      }
+      uint16_t* dst = out + (static_cast<long long>(b) * C + c) * P + p;
+      if (full && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        uint4 q;
+        __builtin_memcpy(&q, o, 16);
+        *reinterpret_cast<uint4*>(dst) = q;
+      } else {
+        for (int k = 0; k < 8; ++k)
+          if (p + k < P) dst[k] = o[k];
+      }
+    }
+  }
+}
+
 // Inference projection in one pass:
 //   out[b][o][p] = bq2[o] + sum_h Q2[o][h] GELU(bq1[h] + sum_c Q1[h][c] v[b][c][p]).
 // The C2-channel hidden layer never leaves the chip (the two-GEMM path writes it to
@@ -597,7 +662,14 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
   const int C = f->C, H = f->H, W = f->W, m = f->m;
   const long long modes_sz = 4LL * m * m;  // floats per (b, c) in T, S
   // lift
-  {
+  if (f->Cin <= kLiftMaxIn && C <= kLiftMaxC) {
+    const long long threads = (static_cast<long long>(P) + 7) / 8 * B;
+    const long long blocks = (threads + 255) / 256;
+    hipLaunchKernelGGL(lift_kernel, dim3(static_cast<unsigned>(blocks < 8192 ? blocks : 8192)),
+                       dim3(256), 0, f->stream, in, f->w16 + f->w16_Wp(), f->p + f->o_bp, f->Cin,
+                       C, static_cast<long long>(P), B, f->v[0]);
+    QLA_HIP(hipGetLastError());
+  } else {
     GemmDesc g = pointwise(f->w16 + f->w16_Wp(), false, C, f->Cin, in, B, P);
     g.C = f->v[0];
     g.out_bf16 = 1;
