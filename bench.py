@@ -273,7 +273,7 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, tuning_json):
     print("\n".join(lines))
 
 
-def precision_study(qla, torch, w, snapshot_every):
+def precision_study(qla, torch, w, snapshot_every, cpu_steps=3):
     """Run the workload in FP64 and FP32 side by side; at every snapshot compare the
     FP32 fields with the FP64 ones (relative L2 over the three planes) and record both
     energy drifts. Norms are diagnostics computed on the device."""
@@ -311,6 +311,15 @@ def precision_study(qla, torch, w, snapshot_every):
         print(f"[study] step {step}: f32 vs f64 rel L2 {err:.3e}, drift f64 {ed['f64']:.2e} "
               f"f32 {ed['f32']:.2e}", file=sys.stderr, flush=True)
     tunings = {k: current_tuning(qla, c) for k, c in ctxs.items()}
+    if cpu_steps:
+        rate, dt = oracle_rate(w, cpu_steps)
+        cpu = {"value": round(rate, 6), "unit": "GLUPS", "cores": __import__("oracle").threads(),
+               "kind": "oracle", "sample": f"first {cpu_steps} steps of the {w.nx}x{w.ny} "
+                                           f"workload, FP64, {dt:.1f} s"}
+        print(f"[study] CPU oracle: {rate:.4f} GLUPS on {cpu['cores']} threads", file=sys.stderr,
+              flush=True)
+    else:
+        cpu = None
     for c in ctxs.values():
         qla.qla_destroy(c)
     sites = w.nx * w.ny * w.steps
@@ -319,7 +328,7 @@ def precision_study(qla, torch, w, snapshot_every):
             "tuning": {k: dict(zip(("rows_per_segment", "prefetch_rows", "steps_per_pass",
                                     "columns_per_lane"), t)) for k, t in tunings.items()},
             "glups": {k: sites / v / 1e9 for k, v in t_run.items()},
-            "seconds": t_run, "snapshots": snaps}
+            "seconds": t_run, "cpu_baseline": cpu, "snapshots": snaps}
 
 
 def batched_study(qla, torch, count, seed, error_samples):
@@ -589,8 +598,8 @@ def divergence_study(qla, torch, w, snapshot_every):
     return out
 
 
-def cpu_baseline(w, sample_steps):
-    import numpy as np
+def oracle_rate(w, sample_steps):
+    """The CPU oracle on the first `sample_steps` steps of workload w: (GLUPS, seconds)."""
     import oracle
     import workloads
     n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
@@ -598,7 +607,13 @@ def cpu_baseline(w, sample_steps):
     t0 = time.perf_counter()
     oracle.advance(q, n, w.delta, sample_steps)
     dt = time.perf_counter() - t0
-    del q
+    return w.nx * w.ny * sample_steps / dt / 1e9, dt
+
+
+def cpu_baseline(w, sample_steps):
+    import oracle
+    import workloads
+    rate, dt = oracle_rate(w, sample_steps)
     # the small parity workload, all of it
     s = workloads.parity_small()
     ns = workloads.ellipse_index(s.nx, s.ny, s.ellipse)
@@ -606,7 +621,7 @@ def cpu_baseline(w, sample_steps):
     t1 = time.perf_counter()
     oracle.advance(qs, ns, s.delta, s.steps)
     ds = time.perf_counter() - t1
-    return {"value": round(w.nx * w.ny * sample_steps / dt / 1e9, 6), "unit": "GLUPS",
+    return {"value": round(rate, 6), "unit": "GLUPS",
             "cores": oracle.threads(), "kind": "oracle",
             "sample": f"first {sample_steps} steps of the {w.nx}x{w.ny} workload, FP64, "
                       f"{dt:.1f} s",
@@ -764,7 +779,8 @@ def main():
             w = dataclasses.replace(w, steps=args.qla_steps)
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
-            out = precision_study(qla, torch, w, args.snapshot_every)
+            out = precision_study(qla, torch, w, args.snapshot_every,
+                                  0 if args.no_cpu_baseline else 3)
         print(json.dumps(out), flush=True)
         return
     w = workloads.workload_by_name(args.workload)
