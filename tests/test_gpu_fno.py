@@ -293,3 +293,28 @@ def test_full_size_network_forward_and_gradient(qla, net_factory):
         print(f"full size grad {pname}: rel L2 {e:.2e}")
         assert e <= GRAD_TOL, pname
         off += n
+
+
+@pytest.mark.parametrize("name", list(SPECS) + ["full"])
+def test_inference_forward_agrees_with_the_training_forward(qla, net_factory, name):
+    """Inference runs the projection as one fused kernel (hidden layer on chip, GELU in
+    FP32 with the Abramowitz & Stegun 7.1.26 erf); training runs it as two GEMMs with a
+    BF16 hidden layer. Both are the same function to BF16 rounding: the output energies
+    (the acceptance test's quantity) agree to 1e-3 and the outputs to 5e-3."""
+    s = SPECS.get(name) or fno.Spec(H=128, W=128, cin=4, cout=3, C=64, m=12, L=2, C2=128)
+    B = 2
+    net = net_factory(s, B)
+    qla.qla_fno_set_params(net.h, make_params(s, 81))
+    u, t = inputs(s, B, 82)
+    e_inf = torch.zeros(B, dtype=torch.float64, device="cuda")
+    e_trn = torch.zeros(B, dtype=torch.float64, device="cuda")
+    out_inf = gpu_forward(qla, net, u, B)
+    qla.qla_fno_output_energy(net.h, B, e_inf)
+    qla.qla_fno_loss_grad(net.h, to_device(u), to_device(t), B)   # training forward
+    qla.qla_fno_output_energy(net.h, B, e_trn)
+    torch.cuda.synchronize()
+    ratio = e_inf.cpu().numpy() / e_trn.cpu().numpy()
+    print(f"{name}: inference / training output energy {ratio}")
+    assert np.abs(ratio - 1).max() <= 1e-3
+    want = fno.predict(s, make_params(s, 81).astype(np.float64), bf16_value(u))
+    assert rel(out_inf, want) <= FWD_TOL
