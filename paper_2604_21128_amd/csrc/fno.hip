@@ -274,6 +274,161 @@ __global__ __launch_bounds__(256) void projection_fused_kernel(
   }
 }
 
+// Pointwise + spectral part of a Fourier layer for C = 64 channels on rows of a
+// multiple of 256 pixels:
+//   pre[b][o][p] = bias[o] + sum_c Wl[o][c] v[b][c][p] + sum_j U[b][o][y][j] IX[j][x]
+// (p = y W + x; the second sum is the inverse x transform of the spectral branch),
+// stored as BF16 pre-activation (zout, optional) and BF16 GELU(pre) (aout, optional).
+// The generic GEMM does this with 64-pixel tiles, i.e. 128-byte runs per channel row;
+// here a block strides over tiles of 256 pixels of one grid row (512-byte runs, 1 KB
+// per wavefront load or store). The tile's 64 channels go to LDS pixel-major (8-channel
+// groups XORed with bits 3-5 of the pixel), the 256 columns of IX likewise; the 4
+// waves (2 x 2) each compute 32 output channels x 128 pixels with the 32x32x16 BF16
+// matrix instruction, Wl fragments held in registers for the block's lifetime; the
+// next tile's loads are issued before the current tile's products; outputs are staged
+// in LDS and written row by row with 16-byte stores.
+constexpr int kMixC = 64, kMixPix = 256, kMixMaxJ = 32;
+
+__device__ __forceinline__ int mix_col64(int r, int k) {
+  return ((((k >> 3) ^ (r >> 3)) & 7) << 3) | (k & 7);
+}
+__device__ __forceinline__ int mix_col32(int r, int k) {
+  return ((((k >> 3) ^ (r >> 3)) & 3) << 3) | (k & 7);
+}
+
+__global__ __launch_bounds__(256) void layer_mix_kernel(
+    const uint16_t* __restrict__ v, const uint16_t* __restrict__ wl,
+    const float* __restrict__ bias, const uint16_t* __restrict__ U,
+    const uint16_t* __restrict__ IX, int m2, int H, int W, int B,
+    uint16_t* __restrict__ zout, uint16_t* __restrict__ aout) {
+  // v tile [pixel][channel]; after the products the same bytes stage the output rows
+  __shared__ __attribute__((aligned(16))) uint16_t vs[kMixPix * (kMixC + 8)];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[kMixPix][kMixMaxJ + 8];
+  __shared__ float sbias[kMixC];
+  uint16_t(*ost)[kMixPix + 8] = reinterpret_cast<uint16_t(*)[kMixPix + 8]>(vs);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+  const int hl = lane & 31, kh = 8 * (lane >> 5);
+  const long long P = static_cast<long long>(H) * W;
+  if (t < kMixC) sbias[t] = bias[t];
+  // Wl fragments: row 32 wm + hl, channels 16 f + kh .. + 7
+  bf16x8_t afr[kMixC / 16];
+#pragma unroll
+  for (int f = 0; f < kMixC / 16; ++f)
+    afr[f] = *reinterpret_cast<const bf16x8_t*>(wl + (32 * wm + hl) * kMixC + 16 * f + kh);
+  const int per_row = W / kMixPix;
+  const long long tiles = static_cast<long long>(B) * H * per_row;
+  // loads of one tile: 8 x 16 bytes of v per thread (channel idx >> 5, pixels
+  // (idx & 31) * 8 ..), up to 4 x 16 bytes of IX
+  uint4 rv[8], rx[4];
+  auto load_tile = [&](long long tile) {
+    const int b = static_cast<int>(tile / (static_cast<long long>(H) * per_row));
+    const long long rem = tile % (static_cast<long long>(H) * per_row);
+    const int y = static_cast<int>(rem / per_row), x0 = static_cast<int>(rem % per_row) * kMixPix;
+    const uint16_t* vb = v + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = it * 256 + t, c = idx >> 5, seg = idx & 31;
+      rv[it] = *reinterpret_cast<const uint4*>(vb + c * P + seg * 8);
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = it * 256 + t, j = idx >> 5, seg = idx & 31;
+      rx[it] = j < m2 ? *reinterpret_cast<const uint4*>(IX + static_cast<long long>(j) * W + x0 + seg * 8)
+                      : uint4{0, 0, 0, 0};
+    }
+  };
+  long long tile = blockIdx.x;
+  if (tile < tiles) load_tile(tile);
+  for (; tile < tiles; tile += gridDim.x) {
+    const int b = static_cast<int>(tile / (static_cast<long long>(H) * per_row));
+    const long long rem = tile % (static_cast<long long>(H) * per_row);
+    const int y = static_cast<int>(rem / per_row), x0 = static_cast<int>(rem % per_row) * kMixPix;
+    // U fragments of this tile's grid row: row 32 wm + hl, modes kh .. kh + 7 and 16 + kh ..
+    bf16x8_t a2[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      uint16_t e[8];
+      const uint16_t* src = U + ((static_cast<long long>(b) * kMixC + 32 * wm + hl) * H + y) * m2;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int j = 16 * f + kh + i;
+        e[i] = j < m2 ? src[j] : uint16_t(0);
+      }
+      a2[f] = __builtin_bit_cast(bf16x8_t, e);
+    }
+    __syncthreads();  // the previous tile's output staging has been read
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = it * 256 + t, c = idx >> 5, seg = idx & 31;
+      uint16_t e[8];
+      __builtin_memcpy(e, &rv[it], 16);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = seg * 8 + i;
+        vs[r * (kMixC + 8) + mix_col64(r, c)] = e[i];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = it * 256 + t, j = idx >> 5, seg = idx & 31;
+      uint16_t e[8];
+      __builtin_memcpy(e, &rx[it], 16);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = seg * 8 + i;
+        xs[r][mix_col32(r, j)] = e[i];
+      }
+    }
+    __syncthreads();
+    if (tile + gridDim.x < tiles) load_tile(tile + gridDim.x);  // in flight during the products
+    f32x16_t acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      acc[nt] = f32x16_t{};
+      const int r = wn * 128 + nt * 32 + hl;
+#pragma unroll
+      for (int f = 0; f < kMixC / 16; ++f) {
+        const bf16x8_t bb =
+            *reinterpret_cast<const bf16x8_t*>(&vs[r * (kMixC + 8) + mix_col64(r, 16 * f + kh)]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[f], bb, acc[nt], 0, 0, 0);
+      }
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const bf16x8_t bb = *reinterpret_cast<const bf16x8_t*>(&xs[r][mix_col32(r, 16 * f + kh)]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[f], bb, acc[nt], 0, 0, 0);
+      }
+    }
+    // outputs: pre-activation, then GELU, each staged in LDS and stored row by row
+    uint16_t* outs[2] = {zout, aout};
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      uint16_t* dst = outs[pass];
+      if (!dst) continue;
+      __syncthreads();  // the tile (or the previous pass) is no longer read
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int row = 32 * wm + 8 * i + 4 * (lane >> 5) + j;
+            const float val = acc[nt][4 * i + j] + sbias[row];
+            ost[row][wn * 128 + nt * 32 + hl] = f32_to_bf16(pass ? gelu_f(val) : val);
+          }
+        }
+      }
+      __syncthreads();
+      uint16_t* db = dst + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0;
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int idx = it * 256 + t, row = idx >> 5, seg = idx & 31;
+        *reinterpret_cast<uint4*>(db + row * P + seg * 8) =
+            *reinterpret_cast<const uint4*>(&ost[row][seg * 8]);
+      }
+    }
+  }
+}
+
 // S[(b,o)][2kyi+p][kx] = sum_c R[kyi][kx][c][o] (complex) * T[(b,c)][2kyi+p][kx]
 __global__ void mix_forward_kernel(const float* __restrict__ T, const float* __restrict__ R,
                                    uint16_t* __restrict__ S, int B, int C, int m) {
@@ -774,7 +929,17 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
       QLA_GEMM(g);
     }
     // pointwise + spectral + bias, then GELU (not after the last layer)
-    {
+    if (f->fused && C == kMixC && W % kMixPix == 0 && 2 * m <= kMixMaxJ) {
+      const long long tiles = static_cast<long long>(B) * H * (W / kMixPix);
+      const dim3 grid(static_cast<unsigned>(tiles < 1024 ? tiles : 1024));
+      const bool last = l + 1 == f->L;
+      uint16_t* zo = last ? f->v[l + 1] : (training ? f->z[l] : nullptr);
+      uint16_t* ao = last ? nullptr : f->v[l + 1];
+      hipLaunchKernelGGL(layer_mix_kernel, grid, dim3(256), 0, f->stream, vl,
+                         f->w16 + f->w16_W(l), f->p + f->o_b[l], f->Ub, f->IX, 2 * m, H, W, B,
+                         zo, ao);
+      QLA_HIP(hipGetLastError());
+    } else {
       GemmDesc g = pointwise(f->w16 + f->w16_W(l), false, C, C, vl, B, P);
       g.bias = f->p + f->o_b[l];
       if (f->fused) {

@@ -126,11 +126,14 @@ def gpu_forward(qla, net, u_bits, B):
 
 
 # "fused": rows a multiple of 64 cells, where the inverse x transform runs inside the
-# channel-mixing GEMM; the other two take the separate path.
+# channel-mixing GEMM; "small" and "ragged" take the separate path; "mix256" (width 64,
+# rows of 256 cells) runs the dedicated layer kernel.
 SPECS = {
     "small": fno.Spec(H=40, W=72, cin=4, cout=3, C=16, m=6, L=3, C2=24),
     "ragged": fno.Spec(H=33, W=70, cin=4, cout=3, C=10, m=5, L=2, C2=70),
     "fused": fno.Spec(H=24, W=128, cin=4, cout=3, C=16, m=7, L=3, C2=40),
+    # width 64 on rows of 256 cells: the layers run the 256-pixel mixing kernel
+    "mix256": fno.Spec(H=16, W=256, cin=4, cout=3, C=64, m=6, L=2, C2=40),
 }
 
 
