@@ -1291,7 +1291,7 @@ qla_status qla_fno_create(int height, int width, int in_channels, int out_channe
 
 qla_status qla_fno_destroy(qla_fno* f) {
   if (!f) return QLA_OK;
-  DeviceGuard g(f->device);
+  DeviceGuard g(f->device);  // frees what it can even if selecting the device fails
   if (f->stream) (void)hipStreamSynchronize(f->stream);
   release(f);
   delete f;
@@ -1306,7 +1306,7 @@ qla_status qla_fno_param_count(const qla_fno* f, int64_t* count) {
 
 qla_status qla_fno_get_params(qla_fno* f, float* host) {
   if (!f || !host) return fail(QLA_EINVAL, "NULL argument");
-  DeviceGuard g(f->device);
+  QLA_ON_DEVICE(f->device);
   QLA_HIP(hipMemcpyAsync(host, f->p, f->nparam * sizeof(float), hipMemcpyDeviceToHost, f->stream));
   QLA_HIP(hipStreamSynchronize(f->stream));
   return QLA_OK;
@@ -1314,7 +1314,7 @@ qla_status qla_fno_get_params(qla_fno* f, float* host) {
 
 qla_status qla_fno_set_params(qla_fno* f, const float* host) {
   if (!f || !host) return fail(QLA_EINVAL, "NULL argument");
-  DeviceGuard g(f->device);
+  QLA_ON_DEVICE(f->device);
   QLA_HIP(hipMemcpyAsync(f->p, host, f->nparam * sizeof(float), hipMemcpyHostToDevice, f->stream));
   qla_status st = refresh_w16(f);
   if (st != QLA_OK) return st;
@@ -1324,7 +1324,7 @@ qla_status qla_fno_set_params(qla_fno* f, const float* host) {
 
 qla_status qla_fno_get_grads(qla_fno* f, float* host) {
   if (!f || !host) return fail(QLA_EINVAL, "NULL argument");
-  DeviceGuard g(f->device);
+  QLA_ON_DEVICE(f->device);
   QLA_HIP(hipMemcpyAsync(host, f->g, f->nparam * sizeof(float), hipMemcpyDeviceToHost, f->stream));
   QLA_HIP(hipStreamSynchronize(f->stream));
   return QLA_OK;
@@ -1334,7 +1334,7 @@ qla_status qla_fno_forward(qla_fno* f, const uint16_t* input, int batch, float* 
   if (!f || !input || !output) return fail(QLA_EINVAL, "NULL argument");
   qla_status st = check_batch(f, batch);
   if (st != QLA_OK) return st;
-  DeviceGuard g(f->device);
+  QLA_ON_DEVICE(f->device);
   st = forward(f, input, batch, false);
   if (st != QLA_OK) return st;
   QLA_HIP(hipMemcpyAsync(output, f->out, size_t(batch) * f->Cout * f->P * sizeof(float),
@@ -1347,7 +1347,7 @@ qla_status qla_fno_loss_grad(qla_fno* f, const uint16_t* input, const uint16_t* 
   if (!f || !input || !target) return fail(QLA_EINVAL, "NULL argument");
   qla_status st = check_batch(f, batch);
   if (st != QLA_OK) return st;
-  DeviceGuard g(f->device);
+  QLA_ON_DEVICE(f->device);
   QLA_HIP(hipMemsetAsync(f->g, 0, f->nparam * sizeof(float), f->stream));
   st = forward(f, input, batch, true);
   if (st == QLA_OK) st = backward(f, input, target, batch);
@@ -1364,7 +1364,7 @@ qla_status qla_fno_adam_step(qla_fno* f, float lr, float beta1, float beta2, flo
   if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
       !(eps > 0.f))
     return fail(QLA_EINVAL, "bad Adam hyper-parameters");
-  DeviceGuard g(f->device);
+  QLA_ON_DEVICE(f->device);
   ++f->adam_t;
   const float c1 = static_cast<float>(1.0 / (1.0 - std::pow(double(beta1), double(f->adam_t))));
   const float c2 = static_cast<float>(1.0 / (1.0 - std::pow(double(beta2), double(f->adam_t))));
@@ -1379,7 +1379,7 @@ qla_status qla_fno_train_step(qla_fno* f, const uint16_t* input, const uint16_t*
   qla_status st = qla_fno_loss_grad(f, input, target, batch, nullptr);
   if (st != QLA_OK) return st;
   if (loss_device) {
-    DeviceGuard g(f->device);
+    QLA_ON_DEVICE(f->device);
     QLA_HIP(hipMemcpyAsync(loss_device, f->loss, sizeof(float), hipMemcpyDeviceToDevice,
                            f->stream));
   }
@@ -1390,7 +1390,7 @@ qla_status qla_fno_output_energy(qla_fno* f, int batch, double* energy_device) {
   if (!f || !energy_device) return fail(QLA_EINVAL, "NULL argument");
   qla_status st = check_batch(f, batch);
   if (st != QLA_OK) return st;
-  DeviceGuard g(f->device);
+  QLA_ON_DEVICE(f->device);
   QLA_HIP(hipMemsetAsync(energy_device, 0, batch * sizeof(double), f->stream));
   hipLaunchKernelGGL(energy_batch_kernel, dim3(256, batch), dim3(kBlock), 0, f->stream, f->out,
                      energy_device, size_t(f->Cout) * f->P);

@@ -283,7 +283,7 @@ qla_status qla_create_triple(int nx, int ny, double delta, qla_precision precisi
 qla_status qla_destroy(qla_ctx* c) {
   if (!c) return QLA_OK;
   if (c->owned_by_batch) return fail(QLA_EINVAL, "this context belongs to a batch");
-  DeviceGuard g(c->device);
+  DeviceGuard g(c->device);  // frees what it can even if selecting the device fails
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   release(c);
   delete c;
@@ -293,8 +293,7 @@ qla_status qla_destroy(qla_ctx* c) {
 qla_status qla_set_index(qla_ctx* c, const double* n_host, size_t ld) {
   if (!c || !n_host) return fail(QLA_EINVAL, "NULL argument");
   if (ld < static_cast<size_t>(c->nx)) return fail(QLA_EINVAL, "ld < nx");
-  DeviceGuard g(c->device);
-  if (!g.ok()) return fail(QLA_EDEVICE, "cannot select the context's device");
+  QLA_ON_DEVICE(c->device);
   // raw rows into the first staging plane (packed), then validate from there
   QLA_HIP(hipMemcpy2DAsync(c->staging, c->nx * sizeof(double), n_host, ld * sizeof(double),
                            c->nx * sizeof(double), c->ny, hipMemcpyHostToDevice, c->stream));
@@ -308,8 +307,7 @@ qla_status qla_set_index_ellipse(qla_ctx* c, const qla_ellipse* e) {
     if (!std::isfinite(x)) return fail(QLA_EINVAL, "ellipse: every field must be finite");
   if (!(e->a > 0.0) || !(e->b > 0.0) || !(e->width > 0.0))
     return fail(QLA_EINVAL, "ellipse: a, b and width must be > 0");
-  DeviceGuard g(c->device);
-  if (!g.ok()) return fail(QLA_EDEVICE, "cannot select the context's device");
+  QLA_ON_DEVICE(c->device);
   const qla::EllipseArgs a{e->xc, e->yc, e->a, e->b, e->rot, e->n_in, e->n_out, e->width};
   QLA_HIP(qla::launch_ellipse_index(c->nx, c->ny, a, c->staging, c->stream));
   return install_index(c, c->staging, c->nx);
@@ -318,8 +316,7 @@ qla_status qla_set_index_ellipse(qla_ctx* c, const qla_ellipse* e) {
 qla_status qla_set_index_device(qla_ctx* c, const double* n_device, size_t ld) {
   if (!c || !n_device) return fail(QLA_EINVAL, "NULL argument");
   if (ld < static_cast<size_t>(c->nx)) return fail(QLA_EINVAL, "ld < nx");
-  DeviceGuard g(c->device);
-  if (!g.ok()) return fail(QLA_EDEVICE, "cannot select the context's device");
+  QLA_ON_DEVICE(c->device);
   return install_index(c, n_device, ld);
 }
 
@@ -330,7 +327,7 @@ qla_status qla_init_packet(qla_ctx* c, const qla_packet* p) {
       !std::isfinite(p->phi) || !std::isfinite(p->amp) || !std::isfinite(p->sigma) ||
       !std::isfinite(p->lambda))
     return fail(QLA_EINVAL, "packet: sigma and lambda must be > 0 and all fields finite");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   qla::PacketArgs a{p->x0, p->y0, p->sigma, p->lambda, p->phi, p->amp, p->planar, c->triple};
   QLA_HIP(qla::launch_packet(c->n64, c->nx, c->ny, c->pitch, a, c->fp32, c->q[c->cur][0],
                              c->q[c->cur][1], c->q[c->cur][2], c->stream));
@@ -341,7 +338,7 @@ qla_status qla_init_packet(qla_ctx* c, const qla_packet* p) {
 qla_status qla_set_fields(qla_ctx* c, const double* q_host, int64_t step) {
   if (!c || !q_host) return fail(QLA_EINVAL, "NULL argument");
   if (step < 0) return fail(QLA_EINVAL, "step < 0");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   const size_t N = c->count();
   QLA_HIP(hipMemcpyAsync(c->staging, q_host, 3 * N * sizeof(double), hipMemcpyHostToDevice,
                          c->stream));
@@ -358,14 +355,14 @@ qla_status qla_advance(qla_ctx* c, int64_t k) {
   if (!c) return fail(QLA_EINVAL, "NULL context");
   if (k < 0) return fail(QLA_EINVAL, "k < 0");
   if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   return enqueue_steps(c, k, c->rows_per_seg, c->prefetch, c->fused, c->cols);
 }
 
 qla_status qla_autotune(qla_ctx* c, int* rows_out, int* prefetch_out, int* steps_per_pass_out) {
   if (!c) return fail(QLA_EINVAL, "NULL context");
   if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   // keep the state: the trial launches overwrite both amplitude buffers
   const size_t plane_bytes = c->plane_elems() * c->elem();
   char* save = reinterpret_cast<char*>(c->staging);
@@ -489,7 +486,7 @@ qla_status qla_get_tuning(const qla_ctx* c, int* rows, int* prefetch, int* steps
 qla_status qla_get_fields_device(qla_ctx* c, double* out, int physical) {
   if (!c || !out) return fail(QLA_EINVAL, "NULL argument");
   if (physical && !c->have_index) return fail(QLA_ESTATE, "physical readout needs the index");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   QLA_HIP(qla::launch_readout(c->q[c->cur][c->plane(0)], c->q[c->cur][c->plane(1)],
                               c->q[c->cur][c->plane(2)], c->n64, c->nx, c->ny, c->pitch,
                               c->fp32, divide_mask(c, physical), out, c->stream));
@@ -499,7 +496,7 @@ qla_status qla_get_fields_device(qla_ctx* c, double* out, int physical) {
 qla_status qla_get_fields(qla_ctx* c, double* out_host, int physical) {
   if (!c || !out_host) return fail(QLA_EINVAL, "NULL argument");
   if (physical && !c->have_index) return fail(QLA_ESTATE, "physical readout needs the index");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   QLA_HIP(qla::launch_readout(c->q[c->cur][c->plane(0)], c->q[c->cur][c->plane(1)],
                               c->q[c->cur][c->plane(2)], c->n64, c->nx, c->ny, c->pitch,
                               c->fp32, divide_mask(c, physical), c->staging, c->stream));
@@ -511,7 +508,7 @@ qla_status qla_get_fields(qla_ctx* c, double* out_host, int physical) {
 
 qla_status qla_energy_device(qla_ctx* c, double* energy_device) {
   if (!c || !energy_device) return fail(QLA_EINVAL, "NULL argument");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   QLA_HIP(qla::launch_energy(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->nx, c->ny,
                              c->pitch, c->fp32, c->partials, energy_device, c->stream));
   return QLA_OK;
@@ -519,7 +516,7 @@ qla_status qla_energy_device(qla_ctx* c, double* energy_device) {
 
 qla_status qla_energy(qla_ctx* c, double* energy) {
   if (!c || !energy) return fail(QLA_EINVAL, "NULL argument");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   QLA_HIP(qla::launch_energy(c->q[c->cur][0], c->q[c->cur][1], c->q[c->cur][2], c->nx, c->ny,
                              c->pitch, c->fp32, c->partials, c->energy_dev, c->stream));
   QLA_HIP(hipMemcpyAsync(energy, c->energy_dev, sizeof(double), hipMemcpyDeviceToHost,
@@ -532,7 +529,7 @@ qla_status qla_divergence(qla_ctx* c, double* l2, double* max_abs, double* scale
   if (!c) return fail(QLA_EINVAL, "NULL context");
   if (c->triple == 1 && !c->have_index)
     return fail(QLA_ESTATE, "the B_z triple's divergence (of D = n^2 E) needs the index");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   // stored planes (shared, y partner, x partner) = (q2, q3, q4) or (q5, q0, q1): the
   // in-plane field is (stored 1, stored 2), i.e. (Bx, By) or (n Ex, n Ey)
   QLA_HIP(qla::launch_divergence(c->q[c->cur][1], c->q[c->cur][2], c->n64, c->nx, c->ny,
@@ -550,7 +547,7 @@ qla_status qla_divergence(qla_ctx* c, double* l2, double* max_abs, double* scale
 qla_status qla_get_coefficients(qla_ctx* c, double* theta, double* beta_x, double* beta_y) {
   if (!c) return fail(QLA_EINVAL, "NULL context");
   if (!c->have_index) return fail(QLA_ESTATE, "set the refractive index first");
-  DeviceGuard g(c->device);
+  QLA_ON_DEVICE(c->device);
   const size_t N = c->count();
   double* s = c->staging;
   QLA_HIP(qla::launch_coefficients(c->n64, c->nx, c->ny, c->pitch, c->delta, s, s + N,

@@ -344,7 +344,7 @@ qla_status plan_batch(qla_batch* b, const int64_t* steps, const BatchTuning* fix
   }
   if (fixed && fixed->fused == 2 && !all_even)
     return fail(QLA_EINVAL, "two steps per pass need an even step count for every lattice");
-  DeviceGuard g(b->device);
+  QLA_ON_DEVICE(b->device);
   release_plan(b);
   b->steps.assign(steps, steps + b->count);
   b->angle_class = cls;
@@ -467,7 +467,7 @@ qla_status qla_batch_plan_fixed(qla_batch* b, const int64_t* steps, int rows_per
 qla_status qla_batch_run(qla_batch* b) {
   if (!b) return fail(QLA_EINVAL, "NULL batch");
   if (!b->planned) return fail(QLA_ESTATE, "plan the batch first");
-  DeviceGuard g(b->device);
+  QLA_ON_DEVICE(b->device);
   QLA_HIP(hipGraphLaunch(b->exec, b->stream));
   // An odd number of passes leaves a lattice's result in its other buffer: its
   // context follows, and its parity flips for the next run of the same graph.
@@ -513,7 +513,7 @@ qla_status qla_batch_segment_rows(const qla_batch* b, int i, int* rows) {
 
 qla_status qla_batch_destroy(qla_batch* b) {
   if (!b) return QLA_OK;
-  DeviceGuard g(b->device);
+  DeviceGuard g(b->device);  // frees what it can even if selecting the device fails
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   release_plan(b);
   for (qla_ctx* c : b->ctx) {

@@ -79,6 +79,12 @@ class DeviceGuard {
   bool ok_ = false;
 };
 
+// Makes device `dev` current until the enclosing call returns; the call fails with
+// QLA_EDEVICE when the device cannot be selected.
+#define QLA_ON_DEVICE(dev)                                                           \
+  ::qla::DeviceGuard guard_(dev);                                                    \
+  if (!guard_.ok()) return ::qla::fail(QLA_EDEVICE, "cannot select the device")
+
 // Enqueue k steps of one context with the given tuning (no argument checks).
 qla_status enqueue_steps(qla_ctx* c, int64_t k, int rows, int prefetch, int fused, int cols);
 
