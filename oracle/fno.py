@@ -132,3 +132,31 @@ def adam(params, grad, m1, m2, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m1 / (1 - b1 ** t)
     vh = m2 / (1 - b2 ** t)
     return params - lr * mh / (np.sqrt(vh) + eps), m1, m2
+
+
+def kept_mask(H: int, W: int, m: int) -> np.ndarray:
+    """Boolean [H, W] mask of the full 2D spectrum that the truncation touches: the
+    kept half-spectrum modes (ky in [0, m) U [H - m, H), kx in [0, m)) and, for
+    kx > 0, their Hermitian partners (-ky, -kx), which a real field carries with the
+    same magnitude."""
+    mask = np.zeros((H, W), dtype=bool)
+    for ky in kept_rows(Spec(H, W, 1, 1, 1, m, 1, 1)):
+        for kx in range(m):
+            mask[ky, kx] = True
+            if kx > 0:
+                mask[(-ky) % H, (-kx) % W] = True
+    return mask
+
+
+def band_fraction(m: int, u) -> np.ndarray:
+    """Share of each sample's energy sum(u^2) (u: [B, c, H, W]) held by the modes the
+    network's spectral branch keeps: by Parseval, sum over the masked modes of the
+    full 2D DFT of |U|^2 / (H W), over sum u^2 (0 for a zero sample). A sample whose
+    energy lies mostly outside these modes cannot be carried by the Fourier layers."""
+    u = np.asarray(u, dtype=np.float64)
+    B, _, H, W = u.shape
+    X = np.fft.fft2(u)
+    mask = kept_mask(H, W, m)
+    kept = (np.abs(X) ** 2 * mask).reshape(B, -1).sum(axis=1) / (H * W)
+    total = (u ** 2).reshape(B, -1).sum(axis=1)
+    return np.where(total > 0, kept / np.where(total > 0, total, 1.0), 0.0)

@@ -157,3 +157,57 @@ def test_first_adam_step_moves_each_weight_by_lr_against_its_gradient_sign():
     p, m1, m2 = fno.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
     np.testing.assert_allclose(p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
     assert math.isclose(m1[1], -0.2) and math.isclose(m2[1], 0.004)
+
+
+# The band fraction: the share of a field's energy in the modes the spectral branch keeps.
+@pytest.mark.parametrize("ky,kx,expect", [
+    (0, 0, 1.0),            # constant
+    (2, 0, 1.0),            # kept row, kx = 0
+    (16 - 3, 2, 1.0),       # negative ky with positive kx: kept
+    (3, 2, 0.0),            # ky = m is not kept for kx > 0 (its partner is ky = H - m, kx < 0)
+    (0, 3, 0.0),            # kx = m
+    (5, 1, 0.0),            # ky beyond the kept rows
+    (3, 0, 0.5),            # kx = 0 keeps ky = H - m but not ky = m: half the energy of a cosine
+])
+def test_band_fraction_of_single_plane_waves(ky, kx, expect):
+    H, W, m = 16, 12, 3
+    u = _plane_wave(H, W, ky, kx, phase=0.4)[None, None]
+    assert fno.band_fraction(m, u)[0] == pytest.approx(expect, abs=1e-12)
+
+
+def test_band_fraction_of_a_mix_is_the_kept_share_of_the_energy():
+    H, W, m = 16, 12, 3
+    # equal-energy cosines (no mode at kx = 0 or the Nyquist lines): amplitudes set the shares
+    inside, outside = _plane_wave(H, W, 1, 1), _plane_wave(H, W, 4, 5, 1.0)
+    u = np.stack([(2.0 * inside + 1.0 * outside)[None], (0.5 * inside)[None],
+                  np.zeros((1, H, W))])
+    f = fno.band_fraction(m, u)
+    assert f[0] == pytest.approx(4.0 / 5.0, abs=1e-12)
+    assert f[1] == pytest.approx(1.0, abs=1e-12)
+    assert f[2] == 0.0
+
+
+def test_band_fraction_of_a_field_the_truncation_keeps_whole_is_one():
+    """A field built from kept half-spectrum modes only (Hermitian completion, kx = 0
+    column real and symmetric) survives rfft2 -> keep -> irfft2 unchanged and its band
+    fraction is 1; adding a real field with no content on the mask or its mirror image
+    lowers it by that field's energy share."""
+    H, W, m = 16, 12, 3
+    s = fno.Spec(H=H, W=W, cin=1, cout=1, C=1, m=m, L=1, C2=1)
+    rng = np.random.default_rng(5)
+    X = np.zeros((H, W // 2 + 1), dtype=complex)
+    for ky in fno.kept_rows(s):
+        for kx in range(1, m):
+            X[ky, kx] = rng.normal() + 1j * rng.normal()
+    for ky in range(1, m):          # kx = 0: rows ky and -ky both kept, conjugate pair
+        X[ky, 0] = rng.normal() + 1j * rng.normal()
+        X[H - ky, 0] = np.conj(X[ky, 0])
+    X[0, 0] = rng.normal()
+    u = np.fft.irfft2(X, s=(H, W))
+    assert fno.band_fraction(m, u[None, None])[0] == pytest.approx(1.0, abs=1e-12)
+    mask = fno.kept_mask(H, W, m)
+    mirror = np.roll(mask[::-1, ::-1], (1, 1), axis=(0, 1))   # mirror[k] = mask[-k]
+    v = np.real(np.fft.ifft2(np.where(mask | mirror, 0.0, np.fft.fft2(rng.normal(size=(H, W))))))
+    e_u, e_v = (u ** 2).sum(), (v ** 2).sum()
+    got = fno.band_fraction(m, (u + v)[None, None])[0]
+    assert got == pytest.approx(e_u / (e_u + e_v), abs=1e-12)
