@@ -464,9 +464,19 @@ def surrogate_study(qla, torch, args):
                                       packets(test_i), delta, steps, B, args.accept_tol,
                                       args.chunk)
     err_final = field_errors(out)
+    del out
+    # the same held-out set with the band gate in front of the network
+    frac = S.band_fractions(sur, test.inputs, B).cpu().numpy()
+    out_g, ok_g, t_g = S.run_with_fallback(sur, test.inputs, test.e0, index_fn(test_i),
+                                           packets(test_i), delta, steps, B, args.accept_tol,
+                                           args.chunk, band_min=args.band_min)
+    err_gated = field_errors(out_g)
+    ok_g = ok_g.cpu().numpy()
+    del out_g
     n_test = len(test_i)
     t_plain = test.qla_seconds
     t_sur = t["surrogate_s"] + t["fallback_qla_s"]
+    t_gate = t_g["surrogate_s"] + t_g["fallback_qla_s"]
     losses = hist["losses"]
     tail = losses[-max(1, len(losses) // 20):]
     q = lambda a: {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)),
@@ -508,6 +518,18 @@ def surrogate_study(qla, torch, args):
             "fallback_qla_s": t["fallback_qla_s"], "rejected": t["rejected"],
             "plain_qla_s": t_plain, "gain": t_plain / t_sur,
             "surrogate_only_instances_per_s": n_test / t["surrogate_s"],
+        },
+        "band_gate": {
+            "rule": "inputs whose q2, q3, q4 planes hold less than band_min of their energy in "
+                    "the kept Fourier modes go straight to QLA",
+            "band_min": args.band_min,
+            "band_fraction": {"min": float(frac.min()), "median": float(np.median(frac)),
+                              "max": float(frac.max())},
+            "gated_out": t_g["gated_out"],
+            "accepted": int(ok_g.sum()),
+            "field_rel_l2_after_fallback": q(err_gated),
+            "surrogate_and_gate_s": t_g["surrogate_s"], "fallback_qla_s": t_g["fallback_qla_s"],
+            "instances_per_s": n_test / t_gate, "gain": t_plain / t_gate,
         },
     }
     if args.save_params:
@@ -713,6 +735,9 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--train-budget-s", type=float, default=None)
     ap.add_argument("--accept-tol", type=float, default=1e-2)
+    ap.add_argument("--band-min", type=float, default=0.5,
+                    help="surrogate: also report a run that sends inputs with less than this "
+                         "share of their field energy in the kept modes straight to QLA")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--save-params", default="")
     ap.add_argument("--tuning-json", default="",

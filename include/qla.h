@@ -375,6 +375,20 @@ qla_status qla_fno_train_step(qla_fno *fno, const uint16_t *input_device,
  * (q2, q3, q4)). Asynchronous. */
 qla_status qla_fno_output_energy(qla_fno *fno, int batch, double *energy_device);
 
+/* Share of each input sample's energy that the Fourier layers can carry: for the
+ * `channels` input planes from `first_channel` on (0 <= first_channel,
+ * 1 <= channels <= C, first_channel + channels <= Cin) of `batch` BF16 samples laid
+ * out as for qla_fno_forward, the energy in the kept modes of their 2D DFT (ky in
+ * [0, m) U [H - m, H), kx in [0, m), each kx > 0 mode counted with its Hermitian
+ * partner (-ky, -kx)) over the planes' energy sum of squares, by Parseval; 0 for a
+ * zero sample. Written to `batch` device doubles. A caller can send samples whose
+ * fields lie mostly outside the kept band straight to QLA instead of predicting them.
+ * The transforms run in BF16 on the matrix cores (about 1e-2 relative accuracy) and
+ * use the forward pass's scratch, so the call must not overlap another call on the
+ * same surrogate. Asynchronous. */
+qla_status qla_fno_band_fraction(qla_fno *fno, const uint16_t *input_device, int batch,
+                                 int first_channel, int channels, double *fraction_device);
+
 /* Build one sample from a lattice's state: q_device = 3 FP64 planes (q2, q3, q4)
  * (as qla_get_fields_device writes them), n_device = the nx * ny index (FP64).
  * input_device (may be NULL) receives 4 BF16 planes (n - n_shift, q2, q3, q4);

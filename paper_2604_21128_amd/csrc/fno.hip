@@ -607,6 +607,51 @@ __global__ void energy_batch_kernel(const float* __restrict__ out, double* __res
   if (threadIdx.x == 0) atomicAdd(&e[b], r[0]);
 }
 
+// Band sums of sample b (blockIdx.y): sums[2b] += sum over the kept modes of
+// w(kx) |F(ky, kx)|^2, where T[(b,c)][2 kyi + p][kx] holds the re/im parts of the
+// truncated DFT and w = 1 at kx = 0, 2 otherwise (for a real field the mode
+// (-ky, -kx) has the same magnitude and is not among the stored ones);
+// sums[2b + 1] += sum of the squares of the nch input planes at in + b in_stride.
+__global__ void band_sums_kernel(const float* __restrict__ T, const uint16_t* __restrict__ in,
+                                 long long in_stride, int nch, size_t P, int m,
+                                 double* __restrict__ sums) {
+  __shared__ double r0[kBlock], r1[kBlock];
+  const int b = blockIdx.y;
+  const size_t per_t = size_t(nch) * 4 * m * m;
+  const size_t stride = size_t(gridDim.x) * kBlock;
+  double kept = 0.0, total = 0.0;
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < per_t; i += stride) {
+    const double v = T[b * per_t + i];
+    kept += (i % m == 0 ? 1.0 : 2.0) * v * v;
+  }
+  const uint16_t* x = in + b * in_stride;
+  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < size_t(nch) * P; i += stride) {
+    const double v = bf16_to_f32(x[i]);
+    total += v * v;
+  }
+  r0[threadIdx.x] = kept;
+  r1[threadIdx.x] = total;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (static_cast<int>(threadIdx.x) < s) {
+      r0[threadIdx.x] += r0[threadIdx.x + s];
+      r1[threadIdx.x] += r1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&sums[2 * b], r0[0]);
+    atomicAdd(&sums[2 * b + 1], r1[0]);
+  }
+}
+
+// fraction[b] = kept / (H W total) (Parseval), 0 for a zero sample.
+__global__ void band_final_kernel(const double* __restrict__ sums, int B, double hw,
+                                  double* __restrict__ fraction) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) fraction[b] = sums[2 * b + 1] > 0.0 ? sums[2 * b] / (hw * sums[2 * b + 1]) : 0.0;
+}
+
 // Small deterministic generator for the initial weights (splitmix64).
 struct Rng {
   uint64_t s;
@@ -645,6 +690,7 @@ struct qla_fno {
   float *spec = nullptr, *out = nullptr, *dS = nullptr, *dv = nullptr, *loss = nullptr;
   bool fused = false;
   double* sums = nullptr;
+  double* band = nullptr;  // per-sample band sums of qla_fno_band_fraction
   int64_t adam_t = 0;
   std::vector<void*> allocs;
 
@@ -1240,6 +1286,7 @@ qla_status qla_fno_create(int height, int width, int in_channels, int out_channe
   A(&f->dZ, B * C * height * 2 * m);
   A(&f->loss, 1);
   A(&f->sums, 2 * B);
+  A(&f->band, 2 * B);
   if (st == QLA_OK) st = make_bases(f);
   if (st != QLA_OK) {
     release(f);
@@ -1384,6 +1431,70 @@ qla_status qla_fno_train_step(qla_fno* f, const uint16_t* input, const uint16_t*
                            f->stream));
   }
   return qla_fno_adam_step(f, lr, 0.9f, 0.999f, 1e-8f);
+}
+
+qla_status qla_fno_band_fraction(qla_fno* f, const uint16_t* input, int batch, int first_channel,
+                                 int channels, double* fraction_device) {
+  if (!f || !input || !fraction_device) return fail(QLA_EINVAL, "NULL argument");
+  qla_status st = check_batch(f, batch);
+  if (st != QLA_OK) return st;
+  if (first_channel < 0 || channels < 1 || channels > f->C ||
+      first_channel + channels > f->Cin)
+    return fail(QLA_EINVAL, "channels must lie within the input planes (at most C of them)");
+  QLA_ON_DEVICE(f->device);
+  const int H = f->H, W = f->W, m = f->m;
+  const size_t P = f->P;
+  // the truncated transforms of a Fourier layer, applied to the chosen input planes,
+  // into the forward pass's transform scratch (every forward pass rewrites it)
+  {
+    GemmDesc g;
+    g.A = input + size_t(first_channel) * P;
+    g.sAb = static_cast<long long>(f->Cin) * P;
+    g.sAm = W;
+    g.sAk = 1;
+    g.B = f->Fx;
+    g.sBk = 2 * m;
+    g.sBn = 1;
+    g.C = f->Zb;
+    g.sCb = static_cast<long long>(channels) * H * 2 * m;
+    g.sCm = 2 * m;
+    g.sCn = 1;
+    g.M = channels * H;
+    g.N = 2 * m;
+    g.K = W;
+    g.batch = batch;
+    g.out_bf16 = 1;
+    QLA_GEMM(g);
+  }
+  for (int part = 0; part < 2; ++part) {
+    GemmDesc g;
+    g.A = part ? f->A2 : f->A1;
+    g.sAm = H;
+    g.sAk = 1;
+    g.B = f->Zb + part;
+    g.sBb = static_cast<long long>(H) * 2 * m;
+    g.sBk = 2 * m;
+    g.sBn = 2;
+    g.C = f->T[0];
+    g.sCb = 4LL * m * m;
+    g.sCm = m;
+    g.sCn = 1;
+    g.M = 4 * m;
+    g.N = m;
+    g.K = H;
+    g.batch = batch * channels;
+    g.beta = part;
+    QLA_GEMM(g);
+  }
+  QLA_HIP(hipMemsetAsync(f->band, 0, 2 * batch * sizeof(double), f->stream));
+  hipLaunchKernelGGL(band_sums_kernel, dim3(64, batch), dim3(kBlock), 0, f->stream, f->T[0],
+                     input + size_t(first_channel) * P, static_cast<long long>(f->Cin) * P,
+                     channels, P, m, f->band);
+  QLA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(band_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, f->stream, f->band,
+                     batch, double(H) * W, fraction_device);
+  QLA_HIP(hipGetLastError());
+  return QLA_OK;
 }
 
 qla_status qla_fno_output_energy(qla_fno* f, int batch, double* energy_device) {

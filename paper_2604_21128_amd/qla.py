@@ -37,7 +37,7 @@ EXPORTED = (
     "qla_batch_destroy", "qla_fno_create", "qla_fno_destroy",
     "qla_fno_param_count", "qla_fno_get_params", "qla_fno_set_params", "qla_fno_get_grads",
     "qla_fno_forward", "qla_fno_loss_grad", "qla_fno_adam_step", "qla_fno_train_step",
-    "qla_fno_output_energy", "qla_fno_pack",
+    "qla_fno_output_energy", "qla_fno_band_fraction", "qla_fno_pack",
 )
 
 
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH):
         "qla_fno_adam_step": (st, [vp] + [ctypes.c_float] * 4),
         "qla_fno_train_step": (st, [vp, vp, vp, ctypes.c_int, ctypes.c_float, vp]),
         "qla_fno_output_energy": (st, [vp, ctypes.c_int, vp]),
+        "qla_fno_band_fraction": (st, [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]),
         "qla_fno_pack": (st, [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp, vp, vp]),
         "qla_strerror": (ctypes.c_char_p, [st]),
         "qla_last_error": (ctypes.c_char_p, []),
@@ -434,6 +435,15 @@ def qla_fno_output_energy(fno: int, batch: int, energy_device) -> None:
     _check(load().qla_fno_output_energy(ctypes.c_void_p(fno), int(batch),
                                         ctypes.c_void_p(_devptr(energy_device))),
            "qla_fno_output_energy")
+
+
+def qla_fno_band_fraction(fno: int, input_device, batch: int, first_channel: int,
+                          channels: int, fraction_device) -> None:
+    _check(load().qla_fno_band_fraction(ctypes.c_void_p(fno),
+                                        ctypes.c_void_p(_devptr(input_device)), int(batch),
+                                        int(first_channel), int(channels),
+                                        ctypes.c_void_p(_devptr(fraction_device))),
+           "qla_fno_band_fraction")
 
 
 def qla_fno_pack(q_device, n_device, nx: int, ny: int, n_shift: float, input_device=None,

@@ -218,6 +218,19 @@ def predict_all(sur: Surrogate, inputs: torch.Tensor, batch: int):
     return out, energy
 
 
+def band_fractions(sur: Surrogate, inputs: torch.Tensor, batch: int, first_channel: int = 1,
+                   channels: int = 3) -> torch.Tensor:
+    """Share of each input's field energy (planes q2, q3, q4 by default) in the modes the
+    Fourier layers keep, [N] float64 (qla_fno_band_fraction)."""
+    N = inputs.shape[0]
+    frac = torch.zeros(N, dtype=torch.float64, device=inputs.device)
+    for j in range(0, N, batch):
+        k = min(batch, N - j)
+        qla.qla_fno_band_fraction(sur.h, inputs[j:j + k], k, first_channel, channels,
+                                  frac[j:j + k])
+    return frac
+
+
 def accept(energy: torch.Tensor, e0: torch.Tensor, tol: float = 1e-2) -> torch.Tensor:
     """The acceptance test: |E_pred / E_0 - 1| < tol (QLA conserves E exactly)."""
     return (energy / e0 - 1.0).abs() < tol
@@ -226,14 +239,36 @@ def accept(energy: torch.Tensor, e0: torch.Tensor, tol: float = 1e-2) -> torch.T
 def run_with_fallback(sur: Surrogate, inputs: torch.Tensor, e0: torch.Tensor,
                       index_fn: Callable[[int, int], torch.Tensor],
                       packets: Sequence[PacketSpec], delta: float, steps: int, batch: int,
-                      tol: float = 1e-2, chunk: int = 512):
+                      tol: float = 1e-2, chunk: int = 512, band_min: Optional[float] = None):
     """Surrogate first, QLA for every rejected lattice. Returns the fields [N, 3, H, W]
-    (float32), the acceptance mask and the GPU time of each part."""
+    (float32), the acceptance mask and the GPU time of each part.
+
+    With band_min, lattices whose initial fields hold less than that share of their
+    energy in the network's kept modes (band_fractions) skip the network and go
+    straight to QLA: the Fourier layers cannot carry such fields, so their predictions
+    would almost all fail the energy check after costing a forward pass."""
     stream = torch.cuda.current_stream()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record(stream)
-    out, energy = predict_all(sur, inputs, batch)
-    ok = accept(energy, e0, tol)
+    N = inputs.shape[0]
+    gated_out = 0
+    if band_min is None:
+        out, energy = predict_all(sur, inputs, batch)
+        ok = accept(energy, e0, tol)
+    else:
+        frac = band_fractions(sur, inputs, batch)
+        sel = torch.nonzero(frac >= band_min).flatten()
+        gated_out = N - int(sel.numel())
+        out = torch.zeros((N, 3, sur.H, sur.W), dtype=torch.float32, device=inputs.device)
+        ok = torch.zeros(N, dtype=torch.bool, device=inputs.device)
+        part = torch.empty((batch, 3, sur.H, sur.W), dtype=torch.float32, device=inputs.device)
+        energy = torch.zeros(batch, dtype=torch.float64, device=inputs.device)
+        for j in range(0, int(sel.numel()), batch):
+            idx = sel[j:j + batch]
+            k = int(idx.numel())
+            sur.predict(inputs.index_select(0, idx), part[:k], energy[:k])
+            out.index_copy_(0, idx, part[:k])
+            ok.index_copy_(0, idx, accept(energy[:k], e0.index_select(0, idx), tol))
     t1.record(stream)
     t1.synchronize()
     fno_s = t0.elapsed_time(t1) / 1e3
@@ -247,4 +282,4 @@ def run_with_fallback(sur: Surrogate, inputs: torch.Tensor, e0: torch.Tensor,
         out[torch.as_tensor(rejected, device=out.device)] = sub.targets_f32
         qla_s = sub.qla_seconds
     return out, ok, {"surrogate_s": fno_s, "fallback_qla_s": qla_s,
-                     "rejected": int(rejected.size)}
+                     "rejected": int(rejected.size), "gated_out": gated_out}

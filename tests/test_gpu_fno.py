@@ -321,3 +321,71 @@ def test_inference_forward_agrees_with_the_training_forward(qla, net_factory, na
     assert np.abs(ratio - 1).max() <= 1e-3
     want = fno.predict(s, make_params(s, 81).astype(np.float64), bf16_value(u))
     assert rel(out_inf, want) <= FWD_TOL
+
+
+def _band_inputs(H, W, cin, m, seed):
+    """Samples whose band fractions span [0, 1]: plane waves inside and outside the kept
+    modes, their mix, Gaussian packets of short and long wavelength along x, noise and
+    a zero sample; channel 0 is an unrelated medium-like plane."""
+    rng = np.random.default_rng(seed)
+    y, x = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+
+    def wave(ky, kx, ph=0.3):
+        return np.cos(2 * np.pi * (ky * y / H + kx * x / W) + ph)
+
+    def packet(lam, sigma):
+        return np.exp(-0.5 * ((x - W / 3) / sigma) ** 2) * np.cos(2 * np.pi * (x - W / 3) / lam)
+
+    fields = [
+        [wave(1, 2), wave(H - 2, 1), wave(0, m - 1)],
+        [wave(m + 1, 1), wave(2, m), wave(H // 2 - 1, W // 2 - 1)],
+        [wave(1, 1) + 0.7 * wave(m + 2, m + 1), 0.2 * wave(m, 0), rng.normal(size=(H, W))],
+        [packet(W / 3.0, W / 8.0), 0 * x, -packet(W / 3.0, W / 8.0)],
+        [packet(W / (m + 6.0), W / 10.0), 0 * x, -packet(W / (m + 6.0), W / 10.0)],
+        [rng.normal(size=(H, W)) for _ in range(3)],
+        [np.zeros((H, W))] * 3,
+    ]
+    u = np.zeros((len(fields), cin, H, W))
+    for b, f in enumerate(fields[:-1]):     # the last sample stays zero in every plane
+        u[b, 0] = 1.0 + 0.5 * np.tanh(rng.normal(size=(H, W)))
+        for c in range(min(3, cin - 1)):
+            u[b, 1 + c] = f[c]
+    return bf16_bits(u)
+
+
+@pytest.mark.parametrize("H,W,m,first,channels", [
+    (512, 512, 12, 1, 3),     # the surrogate's grid and the packet planes (q2, q3, q4)
+    (40, 24, 5, 1, 3),        # ragged: rows and columns not multiples of the GEMM tiles
+    (40, 24, 5, 0, 4),        # every input plane
+])
+def test_band_fraction_matches_the_reference(qla, stream, H, W, m, first, channels):
+    """qla_fno_band_fraction against the FP64 DFT definition on the same BF16 inputs:
+    the kept-mode energy goes through BF16-stored partial transforms (relative error a
+    few 2^-9 on the kept part), so the fractions agree to 1e-2."""
+    cin = 4
+    bits = _band_inputs(H, W, cin, m, seed=H + first)
+    B = bits.shape[0]
+    h = qla.qla_fno_create(H, W, cin, 3, 8, m, 1, 8, B, 0, stream.cuda_stream)
+    try:
+        frac = torch.full((B,), -1.0, dtype=torch.float64, device="cuda")
+        qla.qla_fno_band_fraction(h, to_device(bits), B, first, channels, frac)
+        got = frac.cpu().numpy()
+    finally:
+        qla.qla_fno_destroy(h)
+    want = fno.band_fraction(m, bf16_value(bits)[:, first:first + channels])
+    print("band fractions", np.round(got, 4), np.round(want, 4))
+    assert np.abs(got - want).max() <= 1e-2
+    assert got[-1] == 0.0                       # zero sample
+    assert want.min() < 0.05 and want.max() > 0.95  # the cases span the range
+
+
+def test_band_fraction_rejects_bad_channels(qla, stream):
+    h = qla.qla_fno_create(40, 24, 4, 3, 8, 5, 1, 8, 2, 0, stream.cuda_stream)
+    try:
+        x = torch.zeros((2, 4, 40, 24), dtype=torch.int16, device="cuda")
+        f = torch.zeros(2, dtype=torch.float64, device="cuda")
+        for first, ch, b in [(-1, 3, 2), (1, 4, 2), (0, 9, 2), (1, 0, 2), (1, 3, 3)]:
+            with pytest.raises(qla.QlaError):
+                qla.qla_fno_band_fraction(h, x, b, first, ch, f)
+    finally:
+        qla.qla_fno_destroy(h)

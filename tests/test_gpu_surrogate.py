@@ -6,7 +6,10 @@ the training pairs, the network trains on the GPU, and the held-out lattices go
 through the surrogate, the energy check (|E/E0 - 1| < 1e-2) and the QLA fallback.
 The untrained network must have every prediction rejected (so its path is slower
 than QLA alone), the trained one must have accepted predictions with small field
-error, and its path must beat QLA alone in lattices per second.
+error, and its path must beat QLA alone in lattices per second. The band gate (inputs
+with little energy in the kept modes skip the network) must pass every one of these
+in-band packets and leave the results unchanged, and must send short-wavelength
+packets (8-32 cells, beyond the kept modes) straight to QLA.
 """
 import numpy as np
 import pytest
@@ -56,6 +59,13 @@ def test_trained_surrogate_beats_plain_qla_at_the_acceptance_tolerance(stream):
         assert np.mean(hist["losses"][-50:]) < 0.5 * np.mean(hist["losses"][:50])
         out, ok, t = S.run_with_fallback(sur, test.inputs, test.e0, index_fn(test_i),
                                          packets(test_i), d, STEPS, 16)
+        # these packets lie inside the kept modes: the band gate lets every one through
+        # and changes nothing
+        frac = S.band_fractions(sur, test.inputs, 16).cpu().numpy()
+        out_g, ok_g, t_g = S.run_with_fallback(sur, test.inputs, test.e0, index_fn(test_i),
+                                               packets(test_i), d, STEPS, 16, band_min=0.5)
+    assert frac.min() >= 0.5 and t_g["gated_out"] == 0
+    assert torch.equal(ok_g, ok) and torch.equal(out_g, out)
     ok = ok.cpu().numpy()
     err = ((out - test.targets_f32).flatten(1).norm(dim=1)
            / test.targets_f32.flatten(1).norm(dim=1)).cpu().numpy()
@@ -67,3 +77,33 @@ def test_trained_surrogate_beats_plain_qla_at_the_acceptance_tolerance(stream):
     assert ok.mean() >= 0.3
     assert np.median(err[ok]) < 0.12
     assert gain > 1.0
+
+
+def test_band_gate_sends_short_wavelength_packets_to_qla(stream):
+    """Packets of 8-32 cells put their carrier at 16-64 cycles per 512 cells, beyond the
+    12 kept modes: their band fractions stay far below 1/2 (an untrained network is
+    enough, the gate does not depend on the weights), while 64-128-cell packets sit
+    above it."""
+    from paper_2604_21128_amd import qla, surrogate as S
+    qla.load()
+    short = workloads.sample_instances(64, seed=31, fixed_side=SIDE, steps=STEPS)
+    long_ = _family(64, 32)
+
+    def inputs(insts):
+        ns = workloads.ellipse_index_batch(SIDE, SIDE, [i.ellipse for i in insts], device="cuda")
+        pk = [S.PacketSpec(i.packet.x0, i.packet.y0, i.packet.sigma, i.packet.lam) for i in insts]
+        x = torch.empty((len(insts), 4, SIDE, SIDE), dtype=torch.int16, device="cuda")
+        stage = torch.empty((3, SIDE, SIDE), dtype=torch.float64, device="cuda")
+        with qla.Lattice(SIDE, SIDE, workloads.DELTA, precision=qla.QLA_F32,
+                         hip_stream=stream.cuda_stream) as lat:
+            for i, p in enumerate(pk):
+                qla.qla_set_index_device(lat.ctx, ns[i], SIDE)
+                qla.qla_init_packet(lat.ctx, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
+                qla.qla_get_fields_device(lat.ctx, stage)
+                qla.qla_fno_pack(stage, ns[i], SIDE, SIDE, 2.0, x[i], None, stream.cuda_stream)
+        return x
+    with S.Surrogate(SIDE, SIDE, max_batch=16, seed=1) as sur:
+        f_short = S.band_fractions(sur, inputs(short), 16).cpu().numpy()
+        f_long = S.band_fractions(sur, inputs(long_), 16).cpu().numpy()
+    print(f"band fractions: short max {f_short.max():.3f}, long min {f_long.min():.3f}")
+    assert f_short.max() < 0.5 <= f_long.min()
