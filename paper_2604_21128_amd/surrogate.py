@@ -259,16 +259,17 @@ def run_with_fallback(sur: Surrogate, inputs: torch.Tensor, e0: torch.Tensor,
         frac = band_fractions(sur, inputs, batch)
         sel = torch.nonzero(frac >= band_min).flatten()
         gated_out = N - int(sel.numel())
-        out = torch.zeros((N, 3, sur.H, sur.W), dtype=torch.float32, device=inputs.device)
-        ok = torch.zeros(N, dtype=torch.bool, device=inputs.device)
-        part = torch.empty((batch, 3, sur.H, sur.W), dtype=torch.float32, device=inputs.device)
-        energy = torch.zeros(batch, dtype=torch.float64, device=inputs.device)
-        for j in range(0, int(sel.numel()), batch):
-            idx = sel[j:j + batch]
-            k = int(idx.numel())
-            sur.predict(inputs.index_select(0, idx), part[:k], energy[:k])
-            out.index_copy_(0, idx, part[:k])
-            ok.index_copy_(0, idx, accept(energy[:k], e0.index_select(0, idx), tol))
+        if gated_out == 0:          # every input passes: predict in place
+            out, energy = predict_all(sur, inputs, batch)
+            ok = accept(energy, e0, tol)
+        else:                       # predict the passing inputs, gathered once
+            out = torch.zeros((N, 3, sur.H, sur.W), dtype=torch.float32, device=inputs.device)
+            ok = torch.zeros(N, dtype=torch.bool, device=inputs.device)
+            if sel.numel():
+                sub_out, sub_e = predict_all(sur, inputs.index_select(0, sel), batch)
+                out.index_copy_(0, sel, sub_out)
+                ok.index_copy_(0, sel, accept(sub_e, e0.index_select(0, sel), tol))
+                del sub_out
     t1.record(stream)
     t1.synchronize()
     fno_s = t0.elapsed_time(t1) / 1e3

@@ -81,29 +81,33 @@ def test_trained_surrogate_beats_plain_qla_at_the_acceptance_tolerance(stream):
 
 def test_band_gate_sends_short_wavelength_packets_to_qla(stream):
     """Packets of 8-32 cells put their carrier at 16-64 cycles per 512 cells, beyond the
-    12 kept modes: their band fractions stay far below 1/2 (an untrained network is
-    enough, the gate does not depend on the weights), while 64-128-cell packets sit
-    above it."""
+    12 kept modes: their band fractions stay far below 1/2 while 64-128-cell packets sit
+    above it (the fraction depends on the inputs only, so an untrained network does).
+    On a mix of both, the gate sends the short ones straight to QLA and predicts the
+    rest; every lattice that is not accepted ends with QLA's own fields."""
     from paper_2604_21128_amd import qla, surrogate as S
     qla.load()
-    short = workloads.sample_instances(64, seed=31, fixed_side=SIDE, steps=STEPS)
-    long_ = _family(64, 32)
+    n_short = 40
+    insts = (workloads.sample_instances(n_short, seed=31, fixed_side=SIDE, steps=STEPS)
+             + _family(40, 32))
 
-    def inputs(insts):
-        ns = workloads.ellipse_index_batch(SIDE, SIDE, [i.ellipse for i in insts], device="cuda")
-        pk = [S.PacketSpec(i.packet.x0, i.packet.y0, i.packet.sigma, i.packet.lam) for i in insts]
-        x = torch.empty((len(insts), 4, SIDE, SIDE), dtype=torch.int16, device="cuda")
-        stage = torch.empty((3, SIDE, SIDE), dtype=torch.float64, device="cuda")
-        with qla.Lattice(SIDE, SIDE, workloads.DELTA, precision=qla.QLA_F32,
-                         hip_stream=stream.cuda_stream) as lat:
-            for i, p in enumerate(pk):
-                qla.qla_set_index_device(lat.ctx, ns[i], SIDE)
-                qla.qla_init_packet(lat.ctx, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
-                qla.qla_get_fields_device(lat.ctx, stage)
-                qla.qla_fno_pack(stage, ns[i], SIDE, SIDE, 2.0, x[i], None, stream.cuda_stream)
-        return x
+    def index_fn(c0, k):
+        return workloads.ellipse_index_batch(SIDE, SIDE, [i.ellipse for i in insts[c0:c0 + k]],
+                                             device="cuda")
+    packets = [S.PacketSpec(i.packet.x0, i.packet.y0, i.packet.sigma, i.packet.lam)
+               for i in insts]
+    d = workloads.DELTA
+    pairs = S.qla_pairs(index_fn, len(insts), packets, d, STEPS, keep_f32=True)
     with S.Surrogate(SIDE, SIDE, max_batch=16, seed=1) as sur:
-        f_short = S.band_fractions(sur, inputs(short), 16).cpu().numpy()
-        f_long = S.band_fractions(sur, inputs(long_), 16).cpu().numpy()
-    print(f"band fractions: short max {f_short.max():.3f}, long min {f_long.min():.3f}")
-    assert f_short.max() < 0.5 <= f_long.min()
+        frac = S.band_fractions(sur, pairs.inputs, 16).cpu().numpy()
+        out, ok, t = S.run_with_fallback(sur, pairs.inputs, pairs.e0, index_fn, packets, d,
+                                         STEPS, 16, band_min=0.5)
+    print(f"band fractions: short max {frac[:n_short].max():.3f}, "
+          f"long min {frac[n_short:].min():.3f}; gated out {t['gated_out']}")
+    assert frac[:n_short].max() < 0.5 <= frac[n_short:].min()
+    assert t["gated_out"] == n_short
+    ok = ok.cpu().numpy()
+    assert not ok[:n_short].any()
+    err = ((out - pairs.targets_f32).flatten(1).norm(dim=1)
+           / pairs.targets_f32.flatten(1).norm(dim=1)).cpu().numpy()
+    assert float(err[~ok].max(initial=0.0)) < 1e-6
