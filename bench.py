@@ -221,17 +221,21 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, tuning_json):
              "Commands (from /tmp with TMPDIR=/tmp; R = repository root; tuning fixed to the "
              "autotuned values below):", "", "```"]
     tj = "'" + json.dumps(tuning) + "'"
-    lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof_trace "
+
+    def shown(d):  # the output folders as given, relative to the repository as $R/...
+        rel = os.path.relpath(os.path.abspath(d), ROOT)
+        return d if rel.startswith("..") else "$R/" + rel
+    tdir, fdir, wdir = shown(trace_dir), shown(fetch_dir), shown(write_dir)
+    lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d {tdir} "
               f"-o trace -- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 2000 "
               f"--no-cpu-baseline --no-extras --tuning-json {tj}",
-              f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/prof_fetch -o fetch "
+              f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fdir} -o fetch "
               f"-- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 100 --no-cpu-baseline "
               f"--no-extras --copy-probe-mib 1024 --tuning-json {tj}",
-              f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/prof_write -o write "
+              f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {wdir} -o write "
               f"-- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 100 --no-cpu-baseline "
               f"--no-extras --copy-probe-mib 1024 --tuning-json {tj}",
-              f"python3 $R/bench.py --summarize-counters $R/gpurun_out/prof_fetch "
-              f"$R/gpurun_out/prof_write $R/gpurun_out/prof_trace {tj}", "```", ""]
+              f"python3 $R/bench.py --summarize-counters {fdir} {wdir} {tdir} {tj}", "```", ""]
     lines += ["## Kernel trace (--stats)", "", "| kernel | calls | average (us) | min (us) | max (us) |",
               "|---|---|---|---|---|"]
     avg_ns = {}
