@@ -92,6 +92,7 @@ def test_surrogate_null_handle_is_rejected():
     assert lib.qla_fno_forward(None, None, 1, None) == qla.QLA_EINVAL
     assert lib.qla_fno_adam_step(None, 1e-3, 0.9, 0.999, 1e-8) == qla.QLA_EINVAL
     assert lib.qla_fno_param_count(None, None) == qla.QLA_EINVAL
+    assert lib.qla_fno_band_fraction(None, None, 1, 1, 3, None) == qla.QLA_EINVAL
     assert lib.qla_fno_destroy(None) == qla.QLA_OK
 
 
