@@ -31,25 +31,52 @@ V_SKEW_HALF, V_PAPER, V_NONE, V_BSTREAM = 0, 1, 2, 3
  OP_S03_PY, OP_S03_MY, OP_S25_PY, OP_S25_MY,
  OP_VX, OP_VY, OP_UX, OP_UY, OP_STEP) = range(17)
 
+_SAN_LIB_PATH = os.path.join(_HERE, "liboracle_san.so")
+# With QLA_ORACLE_SANITIZE=1 in the environment the oracle loads a build instrumented with
+# AddressSanitizer and UndefinedBehaviorSanitizer (the process must preload libasan first;
+# see sanitizer_env()).
+SANITIZE_ENV = "QLA_ORACLE_SANITIZE"
+
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc into liboracle.so next to its source."""
-    if force or not os.path.exists(_LIB_PATH) or \
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp,
-                        _SRC_PATH, "-lm"], check=True)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the C oracle with gcc into liboracle.so next to its source.
+
+    sanitize=True builds liboracle_san.so instead: the same source under
+    -fsanitize=address,undefined, halting on the first undefined-behaviour report."""
+    path = _SAN_LIB_PATH if sanitize else _LIB_PATH
+    if force or not os.path.exists(path) or \
+            os.path.getmtime(path) < os.path.getmtime(_SRC_PATH):
+        tmp = path + ".tmp"
+        flags = ["-O2", "-fopenmp", "-fPIC", "-shared", "-Wall"]
+        if sanitize:
+            flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fopenmp", "-fPIC", "-shared",
+                     "-Wall", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+        subprocess.run(["gcc", *flags, "-o", tmp, _SRC_PATH, "-lm"], check=True)
+        os.replace(tmp, path)
+    return path
+
+
+def sanitizer_env(base=None) -> dict:
+    """Environment for a child process that loads the sanitized oracle: libasan preloaded
+    (it must come before any other library), leak checks off (the interpreter's own
+    allocations are not the oracle's), UBSan halting with a stack trace."""
+    env = dict(os.environ if base is None else base)
+    asan = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True,
+                          text=True, check=True).stdout.strip()
+    env["LD_PRELOAD"] = asan
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0:exitcode=97"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1:exitcode=98"
+    env[SANITIZE_ENV] = "1"
+    return env
 
 
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        sanitize = os.environ.get(SANITIZE_ENV) == "1"
+        lib = ctypes.CDLL(build(sanitize=sanitize))
         dp = ctypes.POINTER(ctypes.c_double)
         lib.qla_oracle_coefficients.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                                 dp, dp, dp, dp]

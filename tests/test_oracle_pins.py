@@ -560,3 +560,115 @@ def test_bstream_normal_incidence_reflectance_is_fresnel():
     r, t = _fresnel_run(oracle.V_BSTREAM)
     assert abs(r / (1.0 / 9.0) - 1) < 0.03, r
     assert abs(r + t - 1) < 1e-6
+
+
+# --------------------------------------------------------------------------------------
+# the packet's conventions (Section V initial conditions) and the physical readout
+# (Eq. 3b3); each against a property the definition or Maxwell's equations fix
+def test_packet_envelope_is_a_gaussian_of_standard_deviation_sigma():
+    # With the carrier flattened (a wavelength far beyond the lattice) the planar packet
+    # is its envelope alone. Read as a distribution over x it has mean x0 and standard
+    # deviation sigma (the meaning of sigma), and at s = +-sigma it is exp(-1/2) of its
+    # peak. An envelope exp(-s^2 / sigma^2) has standard deviation sigma / sqrt(2) and
+    # the value exp(-1) there; a width of 2 sigma fails the other way.
+    nx, x0, sigma, amp = 512, 200.0, 12.0, 1.5
+    n = np.ones((1, nx))
+    ez = oracle.packet(n, x0, 0.0, sigma, 1e12, amp=amp)[2, 0]
+    x = np.arange(nx, dtype=np.float64)
+    w = ez / ez.sum()
+    mean = float((w * x).sum())
+    sd = math.sqrt(float((w * (x - mean) ** 2).sum()))
+    assert abs(mean - x0) < 1e-9
+    assert abs(sd / sigma - 1) < 1e-9
+    assert abs(ez[int(x0)] - amp) < 1e-12
+    for s in (-sigma, sigma):
+        assert abs(ez[int(x0 + s)] / amp - math.exp(-0.5)) < 1e-12
+
+
+def test_packet_carrier_has_period_lambda():
+    # With the envelope flattened the carrier is cos(2 pi s / lambda): +1 at s = 0 and
+    # every whole wavelength, -1 half way, zero a quarter of the way (a period of 2 lambda
+    # or of 2 pi lambda fails). The DFT of the field peaks at nx / lambda cycles.
+    nx, x0, lam = 512, 256.0, 16.0
+    n = np.ones((1, nx))
+    ez = oracle.packet(n, x0, 0.0, 1e9, lam)[2, 0]
+    for m in range(-4, 5):
+        assert abs(ez[int(x0 + m * lam)] - 1.0) < 1e-12
+        assert abs(ez[int(x0 + m * lam + lam / 2)] + 1.0) < 1e-12
+        assert abs(ez[int(x0 + m * lam + lam / 4)]) < 1e-12
+    spec = np.abs(np.fft.rfft(ez))
+    assert int(np.argmax(spec)) == int(nx / lam)
+
+
+def test_packet_travelling_along_y_is_ez_with_bx_only():
+    # The paper's incident packet travels along y with E_z and the corresponding B_x
+    # (Section V initial conditions). For a wave along +y in a uniform medium Maxwell's
+    # equations give B = n k x E = n Ez x-hat (c = 1): Bx = +n Ez, By = 0. The planar
+    # envelope depends on y alone.
+    nx, ny, n_val = 16, 256, 2.0
+    n = np.full((ny, nx), n_val)
+    q = oracle.packet(n, 5.0, 120.0, 10.0, 32.0, phi=math.pi / 2)
+    ez, bx, by = oracle.physical_fields(q, n)
+    assert np.allclose(ez, ez[:, :1], rtol=0, atol=1e-15)       # uniform along x
+    assert abs(float(np.abs(ez).max()) - 1.0) < 1e-12
+    assert np.allclose(bx, n_val * ez, rtol=1e-14, atol=1e-15)
+    assert np.abs(by).max() < 1e-15
+
+
+def test_oblique_planar_packet_is_uniform_across_its_direction():
+    # phi = pi/4: the planar packet depends on s = (dx + dy)/sqrt(2) only, so it is
+    # unchanged by the lattice translation (-1, +1) along its wavefronts (away from the
+    # minimum-image seams), and its magnetic field is n k x E.
+    nx = ny = 128
+    n = np.full((ny, nx), 1.5)
+    phi = math.pi / 4
+    q = oracle.packet(n, 64.0, 64.0, 8.0, 12.0, phi=phi)
+    ez, bx, by = oracle.physical_fields(q, n)
+    core = ez[40:88, 40:88]
+    shifted = ez[41:89, 39:87]
+    assert np.allclose(core, shifted, rtol=0, atol=1e-14)
+    assert np.allclose(bx, 1.5 * math.sin(phi) * ez, rtol=1e-14, atol=1e-15)
+    assert np.allclose(by, -1.5 * math.cos(phi) * ez, rtol=1e-14, atol=1e-15)
+
+
+def test_physical_readout_carries_the_energy_density_of_eq_a13():
+    # Eq. (A13): the energy density is n^2 Ez^2 + Bx^2 + By^2 (E_z triple) and
+    # n^2 (Ex^2 + Ey^2) + Bz^2 (B_z triple), and it equals |Q|^2 site by site. A readout
+    # Ez = n q2 (or q2 alone) breaks it wherever n != 1.
+    rng = np.random.default_rng(5)
+    ny, nx = 48, 64
+    n = 1.0 + 2.0 * rng.random((ny, nx))
+    q = rng.normal(size=(6, ny, nx))
+    ez, bx, by = oracle.physical_fields(q, n)
+    dens = n ** 2 * ez ** 2 + bx ** 2 + by ** 2
+    assert np.allclose(dens, q[2] ** 2 + q[3] ** 2 + q[4] ** 2, rtol=1e-13, atol=0)
+    ex, ey, bz = oracle.physical_fields_bz(q, n)
+    dens = n ** 2 * (ex ** 2 + ey ** 2) + bz ** 2
+    assert np.allclose(dens, q[0] ** 2 + q[1] ** 2 + q[5] ** 2, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("triple", ["ez", "bz"])
+def test_physical_readout_of_a_travelling_wave_has_maxwells_impedance(triple):
+    # A wave travelling along +x in a uniform medium of index n has B = n k x E and
+    # E = -(1/n) k x B (c = 1): By = -n Ez for the E_z polarisation, Ey = Bz / n for the
+    # B_z one. After the oracle has carried a packet 50 cells through n = 2 the physical
+    # fields keep these ratios to the scheme's accuracy; a readout that multiplied by n
+    # instead of dividing would be off by a factor n^2 = 4, a sign slip by -1.
+    nx, n_val, delta, steps = 512, 2.0, 0.25, 400
+    n = np.full((1, nx), n_val)
+    if triple == "ez":
+        q = oracle.packet(n, 150.0, 0.0, 24.0, 32.0)
+    else:
+        q = oracle.packet_bz(n, 150.0, 0.0, 24.0, 32.0)
+    oracle.advance(q, n, delta, steps)
+    if triple == "ez":
+        e, _, b = oracle.physical_fields(q, n)
+        ratio = -float((b * e).sum() / (e * e).sum())           # By = -ratio Ez
+    else:
+        _, e, b = oracle.physical_fields_bz(q, n)
+        ratio = float((b * b).sum() / (e * b).sum())            # Ey = Bz / ratio
+    assert abs(ratio / n_val - 1) < 1e-2, ratio
+    # and the packet did move: its energy centroid advanced by about steps delta / n
+    dens = (q ** 2).sum(axis=(0, 1))
+    shift = _centroid(dens) - 150.0
+    assert abs(shift / (steps * delta / n_val) - 1) < 0.1, shift
