@@ -32,6 +32,39 @@ METRIC = "lattice-site updates/s (GLUPS) + HBM GB/s; batched/surrogate instances
 
 
 POTENTIALS = {"skew_half": 0, "paper": 1, "none": 2, "bstream": 3}
+# The measured job: the largest single-GPU workload, the 8192^2 vacuum bubble in n = 2
+# over 40000 steps, FP64 against FP32 at every snapshot.
+HEADLINE = "qla_8192_bubble_40000"
+
+
+def default_chunk(w):
+    """QLA steps per benchmark step: 2000 on the 40000-step bubble job (20 benchmark steps
+    are the whole job; a snapshot at the end of each), the whole job otherwise."""
+    return 2000 if w.name == HEADLINE else w.steps
+
+
+def default_cpu_steps(w):
+    """Oracle steps for cpu_baseline: about 15 s on 16 host threads (0.02 GLUPS)."""
+    return max(1, round(3e8 / (w.nx * w.ny)))
+
+
+def compare_precisions(torch, w, chunk, precs, snaps, energies):
+    """Per snapshot (end of each chunk of the first timed job): relative L2 distance of
+    the second precision's physical fields (Ez, Bx, By) from the first's, over the three
+    planes, and both energy drifts |E/E0 - 1| at that step."""
+    a, b = precs[0], precs[1]
+    rows = []
+    for c, (sa, sb) in enumerate(zip(snaps[a], snaps[b])):
+        step = min((c + 1) * chunk, w.steps)
+        k = step // w.energy_every
+        rel = float(torch.linalg.vector_norm(sb - sa) / torch.linalg.vector_norm(sa))
+        rows.append({"step": step, "field_rel_l2": rel,
+                     "energy_drift_" + a: float(energies[a][k] / energies[a][0] - 1),
+                     "energy_drift_" + b: float(energies[b][k] / energies[b][0] - 1)})
+    return {"field_rel_l2_final": rows[-1]["field_rel_l2"],
+            "field_rel_l2_max": max(r["field_rel_l2"] for r in rows),
+            "energy_drift_max_" + b: max(abs(r["energy_drift_" + b]) for r in rows),
+            "snapshots": rows}
 
 
 def full_tuning(t):
@@ -51,107 +84,177 @@ def current_tuning(qla, ctx):
     return tuple(qla.qla_get_tuning(ctx)) + (qla.qla_get_lane_columns(ctx),)
 
 
-def run_job(qla, torch, w, n_dev, prec_code, out_dev, energies, stream_ptr, record_kernel,
-            tuning=None, potential=0):
-    """The whole job once; returns (ctx, list of (start, end) events around advances).
-    With tuning=None the context autotunes (untimed warm-up only)."""
-    ctx = qla.qla_create(w.nx, w.ny, w.delta, prec_code, potential, stream_ptr)
-    try:
-        qla.qla_set_index_device(ctx, n_dev, w.nx)
+POTENTIAL_NAMES = {v: k for k, v in POTENTIALS.items()}
+
+
+class Job:
+    """One lattice context running a workload in one precision, chunk by chunk.
+
+    The job: set n(x, y) from device memory (the coefficient checks of Eqs. 2e4 and
+    2e13), initialise the packet, advance w.steps QLA steps recording the FP64 energy
+    on the device every w.energy_every steps, and read the physical fields out to a
+    device buffer at the end of every chunk (the snapshots). A benchmark step is one
+    chunk; the job's set-up falls into its first chunk, and once the last chunk is done
+    the next chunk starts the job again. The context and every buffer are allocated
+    before any timing starts."""
+
+    def __init__(self, qla, torch, w, prec, potential, n_dev, stream_ptr, chunk, jobs,
+                 snapshots):
+        self.qla, self.torch, self.w, self.prec = qla, torch, w, prec
+        self.n_dev, self.chunk = n_dev, chunk
+        self.chunks_per_job = -(-w.steps // chunk)
+        code = qla.QLA_F64 if prec == "f64" else qla.QLA_F32
+        self.ctx = qla.qla_create(w.nx, w.ny, w.delta, code, potential, stream_ptr)
+        n_e = w.steps // w.energy_every + 1
+        self.energies = torch.zeros((jobs, n_e), dtype=torch.float64, device="cuda")
+        self.out = torch.empty((3, w.ny, w.nx), dtype=torch.float64, device="cuda")
+        self.snap = [torch.empty_like(self.out) for _ in range(snapshots)]
+        self.tuning = None
+        self.written = []   # (job row, energy index) written while `pairs` were recorded
+
+    def close(self):
+        self.qla.qla_destroy(self.ctx)
+        self.snap, self.out = [], None
+
+    def tune(self, tuning):
+        """Fix the tuning, or autotune on this lattice (tuning None)."""
+        q = self.qla
+        q.qla_set_index_device(self.ctx, self.n_dev, self.w.nx)
         if tuning is None:
-            qla.qla_autotune(ctx)
+            q.qla_autotune(self.ctx)
         else:
-            apply_tuning(qla, ctx, tuning)
-        p = w.packet
-        qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
-        pairs = []
-        chunks = w.steps // w.energy_every
-        qla.qla_energy_device(ctx, energies[0:1])
-        for c in range(chunks):
-            if record_kernel:
+            apply_tuning(q, self.ctx, tuning)
+        self.tuning = current_tuning(q, self.ctx)
+
+    def run_chunk(self, i, pairs=None):
+        """Benchmark step i: chunk i % chunks_per_job of job i // chunks_per_job.
+        Appends (start, end, qla steps) events around each advance to `pairs`."""
+        q, w, torch = self.qla, self.w, self.torch
+        c, j = i % self.chunks_per_job, i // self.chunks_per_job
+        row = j % self.energies.shape[0]
+        e = self.energies[row]
+        if c == 0:
+            q.qla_set_index_device(self.ctx, self.n_dev, w.nx)
+            p = w.packet
+            q.qla_init_packet(self.ctx, p.x0, p.y0, p.sigma, p.lam, p.phi, p.amp, p.planar)
+            q.qla_energy_device(self.ctx, e[0:1])
+            if pairs is not None:
+                self.written.append((row, 0))
+        s, s1 = c * self.chunk, min((c + 1) * self.chunk, w.steps)
+        while s < s1:
+            nxt = min(s1, (s // w.energy_every + 1) * w.energy_every)
+            if pairs is not None:
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record()
-                qla.qla_advance(ctx, w.energy_every)
+                q.qla_advance(self.ctx, nxt - s)
                 b.record()
-                pairs.append((a, b))
+                pairs.append((a, b, nxt - s))
             else:
-                qla.qla_advance(ctx, w.energy_every)
-            qla.qla_energy_device(ctx, energies[c + 1:c + 2])
-        qla.qla_get_fields_device(ctx, out_dev, 1)
-    except Exception:
-        qla.qla_destroy(ctx)
-        raise
-    return ctx, pairs
+                q.qla_advance(self.ctx, nxt - s)
+            s = nxt
+            if s % w.energy_every == 0:
+                k = s // w.energy_every
+                q.qla_energy_device(self.ctx, e[k:k + 1])
+                if pairs is not None:
+                    self.written.append((row, k))
+        dst = self.snap[c] if j == 0 and c < len(self.snap) else self.out
+        q.qla_get_fields_device(self.ctx, dst, 1)
+        return (s1 - c * self.chunk)
+
+    def qla_steps_of(self, i):
+        c = i % self.chunks_per_job
+        return min((c + 1) * self.chunk, self.w.steps) - c * self.chunk
 
 
-def bench_precision(qla, torch, w, prec, steps, warmup, forced_tuning=None, potential=0):
-    code = qla.QLA_F64 if prec == "f64" else qla.QLA_F32
+def bench_job(qla, torch, w, prec, steps, warmup, chunk, tuning=None, potential=0,
+              snapshots=0, jobs=1):
+    """Time `steps` benchmark steps (chunks of `chunk` QLA steps) of workload w in one
+    precision after `warmup` untimed ones; returns (result dict, Job). The caller closes
+    the Job (its snapshots hold the physical fields at the end of each chunk of the first
+    timed job)."""
     import workloads
-    n_host = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
-    n_dev = torch.from_numpy(n_host).to("cuda")
-    out_dev = torch.empty((3, w.ny, w.nx), dtype=torch.float64, device="cuda")
-    energies = torch.zeros(w.steps // w.energy_every + 1, dtype=torch.float64, device="cuda")
-    # The library enqueues on this stream; torch's events are recorded on it too.
+    n_dev = torch.from_numpy(workloads.ellipse_index(w.nx, w.ny, w.ellipse)).to("cuda")
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
     if not sp:
         raise RuntimeError("bench needs a non-default torch stream")
-    tuning = full_tuning(forced_tuning) if forced_tuning else None
-    for _ in range(max(1, warmup)):
-        ctx, _ = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, False, tuning,
-                         potential)
+    job = Job(qla, torch, w, prec, potential, n_dev, sp, chunk, max(1, jobs), snapshots)
+    try:
+        job.tune(full_tuning(tuning) if tuning else None)
+        for i in range(warmup):
+            job.run_chunk(i)
         torch.cuda.synchronize()
-        if tuning is None:
-            tuning = current_tuning(qla, ctx)
-        qla.qla_destroy(ctx)
-    times, kernel_ms, drift = [], [], []
-    for _ in range(steps):
-        torch.cuda.synchronize()
+        pairs = []
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
         t0.record()
-        ctx, pairs = run_job(qla, torch, w, n_dev, code, out_dev, energies, sp, True, tuning,
-                             potential)
+        qsteps = 0
+        for i in range(steps):
+            qsteps += job.run_chunk(i, pairs)
         t1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
-        qla.qla_destroy(ctx)
-        times.append(max(t0.elapsed_time(t1) / 1e3, 0.0) or wall)
-        adv = sum(a.elapsed_time(b) for a, b in pairs)
-        kernel_ms.append(adv / w.steps)
-        e = energies.cpu().numpy()
-        drift.append(float(abs(e / e[0] - 1).max()))
-        print(f"[bench] {prec} step done: {times[-1]:.3f} s, step kernel "
-              f"{kernel_ms[-1] * 1e3:.1f} us, max |E/E0-1| {drift[-1]:.2e}",
-              file=sys.stderr, flush=True)
-    t = max(times)
-    sites = w.nx * w.ny * w.steps
-    k_s = sum(kernel_ms) / len(kernel_ms) / 1e3          # seconds per QLA step
-    rows, pf, fused, cols = tuning
-    launch_s = k_s * fused                               # one launch applies `fused` steps
+    except Exception:
+        job.close()
+        raise
+    t = t0.elapsed_time(t1) / 1e3 or wall
+    rows, pf, fused, cols = job.tuning
+    adv_s = sum(a.elapsed_time(b) for a, b, _ in pairs) / 1e3
+    launches = sum(k // fused + k % fused for _, _, k in pairs)
+    # every launch but the remainder singles applies `fused` steps
+    launch_s = adv_s / launches
+    k_s = adv_s / sum(k for _, _, k in pairs)           # seconds per QLA step
+    e = job.energies.cpu().numpy()
+    drift = max((abs(e[row, k] / e[row, 0] - 1) for row, k in job.written if k > 0),
+                default=0.0)
+    print(f"[bench] {w.name} {prec}: {steps} steps of {chunk} QLA steps in {t:.3f} s "
+          f"(wall {wall:.3f} s), step kernel {launch_s * 1e6:.1f} us per launch, "
+          f"max |E/E0-1| {drift:.2e}", file=sys.stderr, flush=True)
+    sites = w.nx * w.ny
+    res = {
+        "glups": sites * qsteps / t / 1e9,
+        "seconds": t,
+        "qla_steps_timed": qsteps,
+        "kernel_us": k_s * 1e6,
+        "kernel_glups": sites / k_s / 1e9,
+        "roofline": step_roofline(w, prec, POTENTIAL_NAMES[potential], job.tuning, launch_s),
+        "launch": {"steps_per_launch": fused, "rows_per_segment": rows, "prefetch_rows": pf,
+                   "columns_per_lane": cols, "launch_us": round(launch_s * 1e6, 2),
+                   "launches_timed": launches,
+                   "algorithmic_bytes_per_launch": BYTES_PER_SITE[prec] * sites * fused},
+        "energy_max_rel_drift": drift,
+    }
+    return res, job
+
+
+def step_roofline(w, prec, potential, tuning, launch_s):
+    """Roofline entry of the fused step kernel. `achieved` counts the algorithmic bytes
+    of every step a launch applies (56 B per site update in FP64, 28 B in FP32) over the
+    measured launch time: with two steps per launch it is an effective rate and `frac`
+    may pass 1. `traffic` is the HBM rate from the committed FETCH_SIZE + WRITE_SIZE
+    counters of this kernel, workload, potential mode and tuning (None when the kernel
+    source or the tuning changed since), `hbm_frac` its fraction of peak, and
+    `valu_busy` the share of SIMD issue cycles spent on vector instructions."""
+    fused = full_tuning(tuning)[2]
     algorithmic = BYTES_PER_SITE[prec] * w.nx * w.ny * fused
     achieved = algorithmic / launch_s / 1e9
-    traffic = measured_traffic(w, prec, tuning)
-    return {
-        "glups": sites / t / 1e9,
-        "seconds": t,
-        "kernel_us": k_s * 1e6,
-        "kernel_glups": w.nx * w.ny / k_s / 1e9,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (round(traffic / launch_s / 1e9, 1) if traffic else None)},
-        "launch": {"steps_per_launch": fused, "rows_per_segment": rows, "prefetch_rows": pf,
-                   "columns_per_lane": cols,
-                   "launch_us": round(launch_s * 1e6, 2),
-                   "algorithmic_bytes_per_launch": algorithmic,
-                   "hbm_bytes_per_launch": traffic},
-        "energy_max_rel_drift": max(drift),
-    }
+    rec = counter_entry(w, prec, potential, tuning)
+    traffic = rec["hbm_bytes_per_launch"] / launch_s / 1e9 if rec else None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic, 1) if traffic else None,
+            "frac_kind": f"effective: algorithmic bytes of all {fused} steps of a launch",
+            "hbm_frac": round(traffic / HBM_PEAK_GBS, 4) if traffic else None,
+            "hbm_bytes_per_launch": rec["hbm_bytes_per_launch"] if rec else None,
+            "valu_busy": rec.get("valu_busy") if rec else None,
+            "counters": (os.path.relpath(counter_path(w), ROOT) if rec else None)}
 
 
 STEP_SOURCES = ("paper_2604_21128_amd/csrc/qla_step.hip", "paper_2604_21128_amd/csrc/qla_device.h")
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "qla_step_ez_4096_ellipse.json")
+# committed counter summaries of the step kernel, per workload
+COUNTER_FILES = {"qla_4096_ellipse_20000": "qla_step_ez_4096_ellipse",
+                 "qla_8192_bubble_40000": "qla_step_ez_8192_bubble"}
 
 
 def step_kernel_sha():
@@ -163,118 +266,182 @@ def step_kernel_sha():
     return h.hexdigest()
 
 
-def measured_traffic(w, prec, tuning):
-    """HBM bytes per launch of the step kernel from the committed counter summary,
-    or None if the kernel source or its tuning changed since the counters were taken."""
+def counter_path(w):
+    base = COUNTER_FILES.get(w.name, "qla_step_ez_" + w.name)
+    return os.path.join(ROOT, "profiles", base + ".json")
+
+
+def counter_entry(w, prec, potential, tuning=None):
+    """The committed counter record of the step kernel for workload w, precision and
+    potential mode (and tuning, if given), or None if there is none or the kernel's
+    sources changed since the counters were taken."""
     try:
-        with open(TRAFFIC_JSON) as f:
+        with open(counter_path(w)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if rec.get("kernel_sha256") != step_kernel_sha() or rec.get("workload") != w.name:
         return None
-    r = rec.get(prec)
-    if not r or full_tuning(r.get("tuning", ())) != full_tuning(tuning):
-        return None
-    return r["hbm_bytes_per_launch"]
+    for r in rec.get("records", []):
+        if r["precision"] != prec or r["potential"] != potential:
+            continue
+        if tuning is None or full_tuning(r["tuning"]) == full_tuning(tuning):
+            return r
+    return None
 
 
-def recorded_tuning(w):
-    """The tuning under which the committed counters were taken, if the step kernel is
-    unchanged since (it was the autotuner's choice then); else {} and the run autotunes."""
-    try:
-        with open(TRAFFIC_JSON) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
-        return {}
-    if rec.get("kernel_sha256") != step_kernel_sha() or rec.get("workload") != w.name:
-        return {}
-    return {p: rec[p]["tuning"] for p in ("f64", "f32") if p in rec}
+def recorded_tuning(w, potential):
+    """Per precision, the tuning under which the committed counters were taken (the
+    autotuner's choice then), if the kernel is unchanged since; else the run autotunes."""
+    out = {}
+    for p in ("f64", "f32"):
+        r = counter_entry(w, p, potential)
+        if r:
+            out[p] = r["tuning"]
+    return out
 
 
-def summarize_counters(fetch_dir, write_dir, trace_dir, tuning_json):
-    """Turn rocprofv3 outputs (one FETCH_SIZE run, one WRITE_SIZE run, one kernel trace)
-    into profiles/qla_step_ez_4096_ellipse.{md,json}. The FETCH_SIZE and WRITE_SIZE
-    values of every kernel are scaled by what the counters read for the 1 GiB reference
-    copy in the same run."""
+def summarize_counters(args):
+    """Turn rocprofv3 outputs into profiles/<name>.{md,json} for the step kernel on
+    --workload: one FETCH_SIZE run, one WRITE_SIZE run, one kernel trace and optional
+    SQ counter runs, all of the same command. FETCH_SIZE and WRITE_SIZE of every
+    kernel are scaled by what the counters read for the 1 GiB reference copy of the same
+    run. Kernels are told apart by precision and potential-mode template arguments."""
     import collections
     import csv
     import glob
-    def load(d, ctr):
-        out = collections.defaultdict(list)
-        for fn in glob.glob(os.path.join(d, "*counter_collection.csv")):
-            for r in csv.DictReader(open(fn)):
-                if r["Counter_Name"] == ctr:
-                    out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return out
-    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
-    ref = "__amd_rocclr_copyBuffer"
-    kib = 1048576.0
-    fcopy = max(fe[ref]); wcopy = max(wr[ref])
-    fs, ws = kib / fcopy, kib / wcopy
-    tuning = json.loads(tuning_json)
-    w = __import__("workloads").plain_4096()
-    n = w.nx * w.ny
-    rec = {"workload": w.name, "kernel_sha256": step_kernel_sha(), "fetch_scale": fs,
-           "write_scale": ws}
-    lines = [f"# qla_step_ez_kernel on the {w.nx}x{w.ny} ellipse workload (MI355X, gfx950)", "",
-             "Commands (from /tmp with TMPDIR=/tmp; R = repository root; tuning fixed to the "
-             "autotuned values below):", "", "```"]
-    tj = "'" + json.dumps(tuning) + "'"
+    import workloads
+    fetch_dir, write_dir, trace_dir = args.summarize_counters
+    sq_dirs = args.sq_dirs or []
+    w = workloads.workload_by_name(args.workload)
+    tuning = json.loads(args.tuning_json)
+    potential = args.potential
+    vcode = POTENTIALS[potential]
 
-    def shown(d):  # the output folders as given, relative to the repository as $R/...
-        rel = os.path.relpath(os.path.abspath(d), ROOT)
-        return d if rel.startswith("..") else "$R/" + rel
-    tdir, fdir, wdir = shown(trace_dir), shown(fetch_dir), shown(write_dir)
-    lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d {tdir} "
-              f"-o trace -- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 2000 "
-              f"--no-cpu-baseline --no-extras --tuning-json {tj}",
-              f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fdir} -o fetch "
-              f"-- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 100 --no-cpu-baseline "
-              f"--no-extras --copy-probe-mib 1024 --tuning-json {tj}",
-              f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {wdir} -o write "
-              f"-- python3 $R/bench.py --steps 1 --warmup 1 --qla-steps 100 --no-cpu-baseline "
-              f"--no-extras --copy-probe-mib 1024 --tuning-json {tj}",
-              f"python3 $R/bench.py --summarize-counters {fdir} {wdir} {tdir} {tj}", "```", ""]
-    lines += ["## Kernel trace (--stats)", "", "| kernel | calls | average (us) | min (us) | max (us) |",
-              "|---|---|---|---|---|"]
-    avg_ns = {}
+    def kernel_key(name):
+        if "qla_step_ez_kernel" not in name:
+            return None
+        prec = "f64" if "<double" in name else "f32"
+        # template arguments: <T, VMODE, CLS, ...>
+        args_ = name.split("qla_step_ez_kernel<", 1)[1].split(">", 1)[0].split(",")
+        vm = int(args_[1].strip())
+        return (prec, vm)
+
+    def load(dirs, ctr=None):
+        out = collections.defaultdict(lambda: collections.defaultdict(list))
+        for d in dirs:
+            for fn in glob.glob(os.path.join(d, "*counter_collection.csv")):
+                for r in csv.DictReader(open(fn)):
+                    if ctr and r["Counter_Name"] != ctr:
+                        continue
+                    out[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return out
+    fe, wr = load([fetch_dir], "FETCH_SIZE"), load([write_dir], "WRITE_SIZE")
+    ref = [k for k in fe if "copyBuffer" in k]
+    if not ref:
+        raise SystemExit("no reference copy kernel in the FETCH_SIZE run")
+    kib = 1048576.0
+    fcopy = max(fe[ref[0]]["FETCH_SIZE"])
+    wcopy = max(wr[[k for k in wr if "copyBuffer" in k][0]]["WRITE_SIZE"])
+    fs, ws = kib / fcopy, kib / wcopy
+    sq = load(sq_dirs)
+    n = w.nx * w.ny
+    base = os.path.splitext(counter_path(w))[0]
+    rec = {"workload": w.name, "kernel_sha256": step_kernel_sha(), "fetch_scale": fs,
+           "write_scale": ws, "records": []}
+    # keep the records of other potential modes taken under the same kernel
+    try:
+        old = json.load(open(base + ".json"))
+        if old.get("kernel_sha256") == rec["kernel_sha256"]:
+            rec["records"] = [r for r in old.get("records", []) if r["potential"] != potential]
+    except (OSError, ValueError):
+        pass
+    avg_ns = collections.defaultdict(list)
     for fn in glob.glob(os.path.join(trace_dir, "*kernel_stats.csv")):
         for r in csv.DictReader(open(fn)):
-            name = r["Name"].replace("(anonymous namespace)::", "")
-            short = name.split("(qla::")[0].split("(double")[0].split("(float")[0]
-            avg_ns[name] = float(r["AverageNs"])
-            lines.append(f"| `{short[:80]}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
-                         f"{float(r['MinNs'])/1e3:.1f} | {float(r['MaxNs'])/1e3:.1f} |")
-    lines += ["", "## HBM traffic per dispatch (hardware counters, KiB)", "",
-              f"Reference: a 1 GiB device copy (`{ref}`, 1048576 KiB read and written) reads "
-              f"FETCH_SIZE = {fcopy:.1f} and WRITE_SIZE = {wcopy:.1f}; scale factors "
-              f"{fs:.4f} (fetch) and {ws:.4f} (write).", "",
-              "| kernel | steps/launch | FETCH raw | WRITE raw | read scaled | write scaled | "
-              "algorithmic read | algorithmic write | traffic / algorithmic |",
-              "|---|---|---|---|---|---|---|---|---|"]
+            avg_ns[r["Name"]].append((float(r["AverageNs"]), int(r["Calls"]),
+                                      float(r["MinNs"]), float(r["MaxNs"])))
     for k in fe:
-        if "qla_step_ez_kernel" not in k:
+        key = kernel_key(k)
+        if not key or key[1] != vcode:
             continue
-        prec = "f64" if "<double" in k else "f32"
+        prec = key[0]
         e = 8 if prec == "f64" else 4
-        t = tuning[prec]
-        fused = int(t[2])
-        fr = sum(fe[k]) / len(fe[k]); wv = sum(wr[k]) / len(wr[k])
-        ar, aw = 4 * n * e / 1024, 3 * n * e / 1024
-        hbm = (fr * fs + wv * ws) * 1024
-        rec[prec] = {"tuning": t, "hbm_bytes_per_launch": hbm,
-                     "algorithmic_bytes_per_launch": 7 * n * e * fused}
-        lines.append(f"| step {prec} | {fused} | {fr:.0f} | {wv:.0f} | {fr*fs:.0f} | {wv*ws:.0f} | "
-                     f"{ar:.0f} | {aw:.0f} | {(fr*fs+wv*ws)/(ar+aw):.3f} |")
-    lines += ["", "Algorithmic bytes per launch count every step the launch applies (56 B per site "
-              "update in FP64, 28 B in FP32); the read and write columns are per launch.", ""]
-    base = os.path.join(ROOT, "profiles", "qla_step_ez_4096_ellipse")
-    with open(base + ".md", "w") as f:
-        f.write("\n".join(lines))
+        t = full_tuning(tuning[prec])
+        fused = t[2]
+        fr = sum(fe[k]["FETCH_SIZE"]) / len(fe[k]["FETCH_SIZE"])
+        wk = [x for x in wr if kernel_key(x) == key]
+        wv = sum(wr[wk[0]]["WRITE_SIZE"]) / len(wr[wk[0]]["WRITE_SIZE"])
+        r = {"precision": prec, "potential": potential, "tuning": list(t),
+             "fetch_kib_raw": fr, "write_kib_raw": wv,
+             "hbm_bytes_per_launch": (fr * fs + wv * ws) * 1024,
+             "compulsory_bytes_per_launch": 7 * n * e,
+             "algorithmic_bytes_per_launch": 7 * n * e * fused}
+        for name, rows in avg_ns.items():
+            if kernel_key(name) == key:
+                r["trace_avg_ns"], r["trace_calls"] = rows[0][0], rows[0][1]
+        s = {c: sum(v) / len(v) for x in sq if kernel_key(x) == key for c, v in sq[x].items()}
+        if s:
+            r["sq"] = s
+            if "SQ_ACTIVE_INST_VALU" in s and "GRBM_GUI_ACTIVE" in s:
+                # quad-cycles of VALU issue over the SIMDs' quad-cycles (GRBM_GUI_ACTIVE
+                # is summed over the 8 XCDs)
+                simds, xcds = 1024, 8
+                r["valu_busy"] = round(s["SQ_ACTIVE_INST_VALU"]
+                                       / (simds * s["GRBM_GUI_ACTIVE"] / xcds / 4), 4)
+        rec["records"].append(r)
+    rec["records"].sort(key=lambda r: (r["potential"], r["precision"]))
+    rel = lambda d: "$R/" + os.path.relpath(os.path.abspath(d), ROOT) \
+        if not os.path.relpath(os.path.abspath(d), ROOT).startswith("..") else d
+    cmds = getattr(args, "profile_commands", None) or []
     with open(base + ".json", "w") as f:
         json.dump(rec, f, indent=1)
-    print("\n".join(lines))
+    write_counter_markdown(w, rec, base + ".md", cmds)
+    print(open(base + ".md").read())
+
+
+def write_counter_markdown(w, rec, path, cmds):
+    n = w.nx * w.ny
+    lines = [f"# qla_step_ez_kernel on the {w.nx}x{w.ny} workload `{w.name}` (MI355X, gfx950)",
+             "", f"Step kernel sources sha256 `{rec['kernel_sha256'][:16]}`. A reference 1 GiB "
+             f"device copy in the same runs calibrates the counters: FETCH_SIZE x "
+             f"{rec['fetch_scale']:.4f}, WRITE_SIZE x {rec['write_scale']:.4f}.", ""]
+    if cmds:
+        lines += ["Commands (from /tmp with TMPDIR=/tmp; R = repository root):", "", "```"]
+        lines += cmds + ["```", ""]
+    lines += ["| precision | potential | tuning (rows, prefetch, steps/launch, cols/lane) | "
+              "trace avg (us) | HBM read+write per launch (MB) | compulsory one pass (MB) | "
+              "HBM / compulsory | measured HBM rate (TB/s) | effective rate (TB/s) | "
+              "VALU busy |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for r in rec["records"]:
+        t_us = r.get("trace_avg_ns", 0) / 1e3
+        hbm = r["hbm_bytes_per_launch"]
+        comp = r["compulsory_bytes_per_launch"]
+        rate = hbm / (t_us * 1e-6) / 1e12 if t_us else float("nan")
+        eff = r["algorithmic_bytes_per_launch"] / (t_us * 1e-6) / 1e12 if t_us else float("nan")
+        vb = r.get("valu_busy")
+        lines.append(f"| {r['precision']} | {r['potential']} | {tuple(r['tuning'])} | "
+                     f"{t_us:.1f} | {hbm / 1e6:.1f} | {comp / 1e6:.1f} | {hbm / comp:.3f} | "
+                     f"{rate:.2f} | {eff:.2f} | {vb if vb is not None else '-'} |")
+    lines += ["", "Compulsory bytes are one read of the three amplitude planes and n and one "
+              "write of the amplitude planes (7 planes of n sites), whatever the launch's step "
+              "count; the effective rate charges every step of a launch with them (56 B per "
+              "site update in FP64, 28 B in FP32) and so can exceed the HBM peak with two "
+              "steps per launch. VALU busy: SQ_ACTIVE_INST_VALU quad-cycles over the 1024 "
+              "SIMDs' quad-cycles during the dispatch (GRBM_GUI_ACTIVE / 8 XCDs).", ""]
+    sq_rows = [r for r in rec["records"] if r.get("sq")]
+    if sq_rows:
+        names = sorted({c for r in sq_rows for c in r["sq"]})
+        lines += ["## SQ and GRBM counters per dispatch (device totals)", "",
+                  "| counter | " + " | ".join(f"{r['precision']} {r['potential']}"
+                                               for r in sq_rows) + " |",
+                  "|---|" + "---|" * len(sq_rows)]
+        for c in names:
+            lines.append(f"| {c} | " + " | ".join(f"{r['sq'].get(c, float('nan')):.0f}"
+                                                  for r in sq_rows) + " |")
+        lines.append("")
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
 
 
 def precision_study(qla, torch, w, snapshot_every, cpu_steps=3):
@@ -694,9 +861,14 @@ def paper_mode_drift(qla, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="qla_4096_ellipse_20000")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed benchmark steps: chunks of --chunk-steps QLA steps of the "
+                         "workload's job (20 chunks of 2000 = the whole 40000-step job)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=HEADLINE)
+    ap.add_argument("--chunk-steps", type=int, default=0,
+                    help="QLA steps per benchmark step (default: 2000 on the 8192^2 bubble "
+                         "job, the whole job on the others)")
     ap.add_argument("--qla-steps", type=int, default=0, help="override the QLA step count")
     ap.add_argument("--precisions", default="f64,f32")
     ap.add_argument("--potential", default="skew_half", choices=sorted(POTENTIALS),
@@ -706,9 +878,18 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the copy-bandwidth probe and the potential-mode drift run (for "
                          "profiling runs, whose per-kernel averages must cover the job only)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=12)
-    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR",
-                                                               "TRACE_DIR", "TUNING_JSON"))
+    ap.add_argument("--cpu-sample-steps", type=int, default=0,
+                    help="oracle steps timed for cpu_baseline (default: 5 at 8192^2, 12 at "
+                         "4096^2, about 15 s on 16 host threads)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR",
+                                                               "TRACE_DIR"),
+                    help="write profiles/ counter summaries for --workload, --potential and "
+                         "--tuning-json from rocprofv3 output folders")
+    ap.add_argument("--sq-dirs", nargs="*", default=[],
+                    help="with --summarize-counters: folders of SQ/GRBM counter runs")
+    ap.add_argument("--profile-commands-file", default="",
+                    help="with --summarize-counters: text file of the commands that made the "
+                         "counter runs, copied into the summary")
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32 against FP64 on the 8192^2 bubble workload (field L2, energy drift "
                          "per snapshot); prints its own JSON line")
@@ -753,7 +934,10 @@ def main():
                          "known traffic for hardware counters)")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters)
+        if args.profile_commands_file:
+            with open(args.profile_commands_file) as f:
+                args.profile_commands = [l.rstrip("\n") for l in f if l.strip()]
+        summarize_counters(args)
         return
     if args.gpus != 1:
         print("bench.py: measures one GPU only; the multi-GPU halo-exchange path "
@@ -815,15 +999,26 @@ def main():
     w = workloads.workload_by_name(args.workload)
     if args.qla_steps:
         w = dataclasses.replace(w, steps=args.qla_steps)
+    chunk = args.chunk_steps or default_chunk(w)
     precs = [p for p in args.precisions.split(",") if p]
-    results = {}
+    pot = POTENTIALS[args.potential]
     stream = torch.cuda.Stream()   # default priority
+    cpj = -(-w.steps // chunk)
+    keep = min(args.steps, cpj) if len(precs) > 1 else 0
+    jobs = -(-args.steps // cpj)
+    results, snaps, energies = {}, {}, {}
     with torch.cuda.stream(stream):
-        forced = json.loads(args.tuning_json) if args.tuning_json else (
-            recorded_tuning(w) if args.potential == "skew_half" else {})
+        forced = json.loads(args.tuning_json) if args.tuning_json else \
+            recorded_tuning(w, args.potential)
         for p in precs:
-            results[p] = bench_precision(qla, torch, w, p, args.steps, args.warmup, forced.get(p),
-                                         POTENTIALS[args.potential])
+            r, job = bench_job(qla, torch, w, p, args.steps, args.warmup, chunk, forced.get(p),
+                               pot, snapshots=keep, jobs=jobs)
+            results[p] = r
+            snaps[p], energies[p] = job.snap, job.energies[0].cpu().numpy()
+            qla.qla_destroy(job.ctx)      # the snapshots stay for the comparison
+        comparison = compare_precisions(torch, w, chunk, precs, snaps, energies) \
+            if keep else None
+        snaps.clear()
     main_p = precs[0]
     r = results[main_p]
     line = {
@@ -833,41 +1028,59 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r["seconds"] * 1e3, 3),
+        "ms_per_step": round(r["seconds"] / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": main_p,
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "qla_steps": w.steps,
-                   "energy_every": w.energy_every, "delta": w.delta, "potential": args.potential,
-                   "ellipse": dataclasses.asdict(w.ellipse), "packet": dataclasses.asdict(w.packet)},
+                   "qla_steps_per_bench_step": chunk, "qla_steps_timed": r["qla_steps_timed"],
+                   "energy_every": w.energy_every, "snapshot_every": chunk, "delta": w.delta,
+                   "potential": args.potential,
+                   "ellipse": dataclasses.asdict(w.ellipse),
+                   "packet": dataclasses.asdict(w.packet)},
         "roofline": r["roofline"],
         "launch": r["launch"],
         "step_kernel_us": round(r["kernel_us"], 2),
         "step_kernel_glups": round(r["kernel_glups"], 2),
         "energy_max_rel_drift": r["energy_max_rel_drift"],
     }
+    for p in precs[1:]:
+        rp = results[p]
+        line[p] = {"value": round(rp["glups"], 3), "unit": "GLUPS",
+                   "ms_per_step": round(rp["seconds"] / args.steps * 1e3, 3),
+                   "roofline": rp["roofline"], "launch": rp["launch"],
+                   "step_kernel_us": round(rp["kernel_us"], 2),
+                   "energy_max_rel_drift": rp["energy_max_rel_drift"]}
+    if comparison:
+        line[precs[1]]["vs_" + main_p] = comparison
     if not args.no_extras:
         with torch.cuda.stream(stream):
             line["copy_gbs"] = copy_bandwidth(torch)
             line["potential_modes_small_workload"] = paper_mode_drift(qla, torch)
-            if args.potential == "skew_half" and "f64" in precs:
-                # the same job with the B-streaming scheme (no potentials, fully unitary)
-                rb = bench_precision(qla, torch, w, "f64", 1, 1, None, POTENTIALS["bstream"])
-                line["bstream_f64"] = {"value": round(rb["glups"], 3), "unit": "GLUPS",
-                                       "roofline_frac": rb["roofline"]["frac"],
-                                       "launch": rb["launch"],
-                                       "energy_max_rel_drift": rb["energy_max_rel_drift"]}
-    for p in precs[1:]:
-        rp = results[p]
-        line[p] = {"value": round(rp["glups"], 3), "unit": "GLUPS",
-                   "ms_per_step": round(rp["seconds"] * 1e3, 3), "roofline": rp["roofline"],
-                   "launch": rp["launch"],
-                   "step_kernel_us": round(rp["kernel_us"], 2),
-                   "energy_max_rel_drift": rp["energy_max_rel_drift"]}
+            if w.name == HEADLINE and args.potential == "skew_half":
+                # the 4096^2 ellipse job, whole job per step, both precisions and the
+                # B-streaming scheme
+                w2 = workloads.plain_4096()
+                extra = {}
+                for p in precs:
+                    tun = recorded_tuning(w2, "skew_half").get(p)
+                    rp, job = bench_job(qla, torch, w2, p, 1, 1, w2.steps, tun, pot)
+                    job.close()
+                    extra[p] = {"value": round(rp["glups"], 3), "unit": "GLUPS",
+                                "roofline": rp["roofline"], "launch": rp["launch"],
+                                "energy_max_rel_drift": rp["energy_max_rel_drift"]}
+                tun = recorded_tuning(w2, "bstream").get("f64")
+                rb, job = bench_job(qla, torch, w2, "f64", 1, 1, w2.steps, tun,
+                                    POTENTIALS["bstream"])
+                job.close()
+                extra["bstream_f64"] = {"value": round(rb["glups"], 3), "unit": "GLUPS",
+                                        "roofline": rb["roofline"], "launch": rb["launch"],
+                                        "energy_max_rel_drift": rb["energy_max_rel_drift"]}
+                line[w2.name] = extra
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps or default_cpu_steps(w))
     print(json.dumps(line), flush=True)
 
 

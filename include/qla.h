@@ -274,7 +274,10 @@ qla_status qla_batch_plan_fixed(qla_batch *batch, const int64_t *steps, int rows
                                 int prefetch_rows, int steps_per_pass, int fit);
 
 /* Replay the planned run (asynchronous). Runs can be repeated; each continues
- * from the previous one's result. */
+ * from the previous one's result. A lattice's index may be set again between runs,
+ * but the run evaluates rotation angles with the series range (up to 1/16 rad, or
+ * up to 1/2 rad) of the indices set when it was planned: if a new index needs the
+ * wider range, QLA_ESTATE (plan again) and nothing is launched. */
 qla_status qla_batch_run(qla_batch *batch);
 
 /* The plan's choices: tuning, mode (1), passes, and the lattice-site updates of

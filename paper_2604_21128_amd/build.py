@@ -39,31 +39,57 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def build(verbose: bool = False, extra_flags=None, out: str = LIB) -> str:
-    """Compile all sources and link libqla.so (atomically replaced). Returns its path."""
+def _object_key(src: str, flags) -> str:
+    """Hash of a source, every header it may include and the flags (incremental builds)."""
+    import hashlib
+    h = hashlib.sha256(" ".join(flags).encode())
+    headers = sorted(glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h")))
+    for f in [src] + headers:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:24]
+
+
+def build(verbose: bool = False, extra_flags=None, out: str = LIB,
+          incremental: bool = False) -> str:
+    """Compile all sources and link libqla.so (atomically replaced). Returns its path.
+    incremental=True reuses objects under _build/ whose source, headers and flags are
+    unchanged (a development shortcut; the default always compiles everything)."""
     cc = hipcc()
     flags = HIPCC_FLAGS + list(extra_flags or [])
+    cache = os.path.join(ROOT, "_build")
     with tempfile.TemporaryDirectory(prefix="qla_build_") as tmp:
         objs = []
         procs = []
         for src in sources():
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
-            lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
+            final = obj
+            if incremental:
+                os.makedirs(cache, exist_ok=True)
+                final = os.path.join(cache, os.path.basename(src) + "."
+                                     + _object_key(src, flags) + ".o")
+                if os.path.exists(final):
+                    objs.append(final)
+                    continue
+            lang = ["-x", "hip"]
             cmd = [cc, *flags, "-I", INCLUDE, "-I", CSRC, *lang, "-c", src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
-                                                stderr=subprocess.STDOUT, text=True)))
-            objs.append(obj)
+            procs.append((src, obj, final, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                            stderr=subprocess.STDOUT, text=True)))
+            objs.append(final)
         failed = []
-        for src, p in procs:
+        for src, obj, final, p in procs:
             log, _ = p.communicate()
             text = "\n".join(line for line in log.splitlines()
                              if "packed-fp32-ops" not in line)
             if p.returncode != 0:
                 failed.append((src, text))
-            elif verbose and text.strip():
-                print(text)
+            else:
+                if final != obj:
+                    shutil.move(obj, final)
+                if verbose and text.strip():
+                    print(text)
         if failed:
             msg = "\n".join(f"--- {s}\n{t}" for s, t in failed)
             raise RuntimeError(f"hipcc failed:\n{msg}")
@@ -79,4 +105,4 @@ def build(verbose: bool = False, extra_flags=None, out: str = LIB) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

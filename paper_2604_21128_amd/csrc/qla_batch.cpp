@@ -467,6 +467,14 @@ qla_status qla_batch_plan_fixed(qla_batch* b, const int64_t* steps, int rows_per
 qla_status qla_batch_run(qla_batch* b) {
   if (!b) return fail(QLA_EINVAL, "NULL batch");
   if (!b->planned) return fail(QLA_ESTATE, "plan the batch first");
+  // The captured launches evaluate the rotation angles with the series length of the
+  // indices set when the run was planned; an index set since then with larger angles
+  // needs the longer series, so the run must be planned again.
+  for (int i = 0; i < b->count; ++i)
+    if (b->ctx[i]->angle_class > b->angle_class)
+      return fail(QLA_ESTATE, "instance " + std::to_string(i) +
+                                  ": its index was set after planning and has angles beyond "
+                                  "the planned run's range; plan the batch again");
   QLA_ON_DEVICE(b->device);
   QLA_HIP(hipGraphLaunch(b->exec, b->stream));
   // An odd number of passes leaves a lattice's result in its other buffer: its

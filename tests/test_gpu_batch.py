@@ -262,3 +262,40 @@ def test_batch_degenerate_cases(qla):
         np.testing.assert_array_equal(qla.qla_get_fields(ctx, 72, 40), _single(qla, n, p, 10, 1))
     finally:
         qla.qla_batch_destroy(one)
+
+
+def test_run_refuses_an_index_set_after_planning_with_wider_angles(qla):
+    # A run evaluates rotation angles with the series range fixed when it was planned
+    # (here: every angle up to 1/16 rad). A sharp index set afterwards has potential
+    # half-angles (delta/4)(n+ - n-)/n^2 = 0.125 rad: the run must refuse it (plan again)
+    # rather than use the short series; after a new plan it runs and matches the
+    # single-lattice path.
+    sizes = [(64, 48), (40, 40)]
+    b = qla.qla_batch_create([s[0] for s in sizes], [s[1] for s in sizes], [0.25, 0.25],
+                             precision=1)
+    try:
+        smooth = []
+        for i, (nx, ny) in enumerate(sizes):
+            n, p = _instance(i, nx, ny)
+            smooth.append((n, p))
+            ctx = qla.qla_batch_context(b, i)
+            qla.qla_set_index(ctx, n)
+            qla.qla_init_packet(ctx, p.x0, p.y0, p.sigma, p.lam)
+        steps = [8, 8]
+        qla.qla_batch_plan_fixed(b, steps, 24, 2, 2, 0)
+        sharp = np.ones((48, 64))
+        sharp[:, 20:40] = 3.0
+        ctx0 = qla.qla_batch_context(b, 0)
+        qla.qla_set_index(ctx0, sharp)
+        qla.qla_init_packet(ctx0, 10.0, 24.0, 4.0, 12.0)
+        with pytest.raises(qla.QlaError) as err:
+            qla.qla_batch_run(b)
+        assert err.value.status == qla.QLA_ESTATE
+        qla.qla_batch_plan_fixed(b, steps, 24, 2, 2, 0)
+        qla.qla_batch_run(b)
+        got = qla.qla_get_fields(ctx0, 64, 48)
+        want = _single(qla, sharp, workloads.Packet(x0=10.0, y0=24.0, sigma=4.0, lam=12.0),
+                       8, 1)
+        assert np.array_equal(got, want)
+    finally:
+        qla.qla_batch_destroy(b)

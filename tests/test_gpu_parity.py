@@ -200,6 +200,64 @@ def test_parity_full_size_4096_windows(qla, prec):
     assert _window_parity(qla, w, prec, 20, centres, seed=42) <= TOL[prec]
 
 
+# The benchmark's tuning of the 4096^2 ellipse job (rows per segment, prefetch rows,
+# steps per pass, columns per lane), as recorded with its hardware counters.
+BENCH_TUNING_4096 = {0: (176, 3, 2, 1), 1: (56, 2, 2, 2)}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_parity_4096_job_first_50_steps_at_the_bench_tuning(qla, prec):
+    """The 4096^2 ellipse job as the benchmark runs it: the packet initialised on the
+    GPU, the recorded tuning set explicitly, 50 steps (the span its oracle timing
+    covers). Checked on windows across the packet and at periodic seams against the
+    oracle's own packet advanced 50 steps; then random fields at the same tuning, on
+    windows at the ellipse's strongest gradients, where the packet has not yet arrived."""
+    w = workloads.plain_4096()
+    steps = 50
+    n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
+    rows, pf, ts, cols = BENCH_TUNING_4096[prec]
+    margin = 4 * steps + 2
+    half = margin + 12
+
+    def run(init):
+        with qla.Lattice(w.nx, w.ny, w.delta, precision=prec) as lat:
+            qla.qla_set_tuning(lat.ctx, rows, pf, ts)
+            qla.qla_set_lane_columns(lat.ctx, cols)
+            lat.set_index(n)
+            init(lat)
+            lat.advance(steps)
+            assert tuple(qla.qla_get_tuning(lat.ctx)) == (rows, pf, ts)
+            assert qla.qla_get_lane_columns(lat.ctx) == cols
+            return lat.fields()
+
+    def windows(got, q0, centres, tag):
+        worst = 0.0
+        for cx, cy in centres:
+            ys = np.arange(cy - half, cy + half + 1) % w.ny
+            xs = np.arange(cx - half, cx + half + 1) % w.nx
+            nw = np.ascontiguousarray(n[np.ix_(ys, xs)])
+            qw = np.ascontiguousarray(q0[:, ys][:, :, xs])
+            out = oracle.advance(qw, nw, w.delta, steps)[2:5]
+            inner = slice(margin, 2 * half + 1 - margin)
+            err = rel_l2(got[:, ys[inner]][:, :, xs[inner]], out[:, inner, inner])
+            print(f"4096 job {tag} prec={prec} window=({cx},{cy}) rel_l2={err:.3e}", flush=True)
+            worst = max(worst, err)
+        return worst
+
+    got = run(lambda lat: lat.init_packet(w.packet))
+    q0 = oracle.packet_from(n, w.packet)
+    x0 = int(w.packet.x0)
+    band = [(x0, 100), (x0 - 150, 2048), (x0 + 170, 4000), (x0, 0), (x0 + 60, 4095)]
+    assert windows(got, q0, band, "packet") <= TOL[prec]
+    del q0
+    q = _random_fields((w.ny, w.nx), seed=50 + prec)
+    got = run(lambda lat: lat.set_fields(q))
+    e = w.ellipse
+    edges = [(int(e.xc - e.a), int(e.yc)), (int(e.xc), int(e.yc + e.b)),
+             (int(e.xc + 0.7 * e.a), int(e.yc - 0.7 * e.b)), (w.nx - 1, 0)]
+    assert windows(got, _oracle_state(n, q), edges, "random") <= TOL[prec]
+
+
 # ---------------------------------------------------------------------------------------
 # state handling
 def test_checkpoint_restore_continues_bitwise(qla):
