@@ -237,6 +237,22 @@ qla_status qla_get_tuning(const qla_ctx *ctx, int *rows_per_segment, int *prefet
 /* Release every resource of the context (NULL is accepted). Synchronises. */
 qla_status qla_destroy(qla_ctx *ctx);
 
+/* The energy of Eq. (A13), sum over sites of q_a^2 + q_b^2 + q_c^2 in FP64, of three
+ * caller-owned device planes, WITHOUT ALLOCATING: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it). The same kernels and summation order as qla_energy_device, so on a
+ * context's planes it returns the same bits. Planes: ny rows of nx values of the given
+ * precision (FP64 or FP32), row stride `pitch` >= nx elements, read on hip_stream (NULL:
+ * the null stream); the result is written to the device double energy_device
+ * (asynchronous). nx, ny >= 1; QLA_EINVAL otherwise. Scratch: the 1024 FP64 partial
+ * sums live in a file-scope device array of this library (8 KiB on each GPU it runs on,
+ * held until the process ends), whatever the lattice size; every call overwrites them
+ * all, and calls that overlap on one GPU (two streams, two threads) race on them. The
+ * array's address is looked up once per device on the first call there. */
+qla_status qla_energy_noalloc(const void *q_a, const void *q_b, const void *q_c, int nx, int ny,
+                              size_t pitch, qla_precision precision, double *energy_device,
+                              void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Batches: many independent lattices (sizes, media and packets of their own)
  * advanced together. Each pass (2 steps, or 1 if some step count is odd) is one

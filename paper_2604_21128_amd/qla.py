@@ -29,7 +29,8 @@ EXPORTED = (
     "qla_create", "qla_create_triple", "qla_divergence", "qla_set_index_ellipse",
     "qla_set_index", "qla_set_index_device", "qla_init_packet",
     "qla_set_fields", "qla_advance", "qla_get_fields", "qla_get_fields_device",
-    "qla_energy", "qla_energy_device", "qla_get_coefficients", "qla_step_count",
+    "qla_energy", "qla_energy_device", "qla_energy_noalloc", "qla_get_coefficients",
+    "qla_step_count",
     "qla_set_tuning", "qla_autotune", "qla_get_tuning", "qla_set_lane_columns",
     "qla_get_lane_columns", "qla_destroy", "qla_strerror",
     "qla_last_error", "qla_batch_create", "qla_batch_context", "qla_batch_plan", "qla_batch_run",
@@ -88,6 +89,8 @@ def load(path: str = LIB_PATH):
         "qla_get_fields_device": (st, [vp, vp, ctypes.c_int]),
         "qla_energy": (st, [vp, dp]),
         "qla_energy_device": (st, [vp, vp]),
+        "qla_energy_noalloc": (st, [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                    ctypes.c_int, vp, vp]),
         "qla_get_coefficients": (st, [vp, dp, dp, dp]),
         "qla_step_count": (st, [vp, ctypes.POINTER(i64)]),
         "qla_set_tuning": (st, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
@@ -249,6 +252,17 @@ def qla_energy(ctx: int) -> float:
 def qla_energy_device(ctx: int, out_device) -> None:
     _check(load().qla_energy_device(ctypes.c_void_p(ctx), ctypes.c_void_p(_devptr(out_device))),
            "qla_energy_device")
+
+
+def qla_energy_noalloc(q_a, q_b, q_c, nx: int, ny: int, pitch: int, precision: int,
+                       out_device, stream=None) -> None:
+    """Energy of three caller-owned device planes (pointers or tensors) into one device
+    double, with no allocation (the library's file-scope scratch holds the partials)."""
+    _check(load().qla_energy_noalloc(ctypes.c_void_p(_devptr(q_a)), ctypes.c_void_p(_devptr(q_b)),
+                                     ctypes.c_void_p(_devptr(q_c)), int(nx), int(ny), int(pitch),
+                                     int(precision), ctypes.c_void_p(_devptr(out_device)),
+                                     ctypes.c_void_p(_devptr(stream) if stream else None)),
+           "qla_energy_noalloc")
 
 
 def qla_get_coefficients(ctx: int, nx: int, ny: int):
