@@ -709,6 +709,312 @@ def surrogate_study(qla, torch, args):
     return res
 
 
+def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
+    """The surrogate network's kernel launches for one sample, in launch order: (op, kernel
+    name fragment, algorithmic flops, algorithmic HBM bytes). Bytes count one read of each
+    input tensor and one write of each output tensor an op needs (BF16 activations, FP32
+    spectra, losses and outputs); flops count multiply-adds as two. Inference runs the fused
+    projection; training keeps the two projection GEMMs and the pre-activations."""
+    P = H * W
+    act = C * P * 2                     # one BF16 activation tensor
+    zx = C * H * 2 * m * 2              # x-transformed rows (BF16, re/im interleaved)
+    spec = C * 4 * m * m * 4            # kept modes, FP32 (T, S, dT, dS)
+    ops = [("lift", "lift_kernel", 2 * C * Cin * P, Cin * P * 2 + act)]
+    for l in range(L):
+        last = l + 1 == L
+        ops += [(f"L{l} x transform", "gemm_kernel", 2 * C * H * 2 * m * W, act + zx),
+                (f"L{l} y transform (re)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + spec),
+                (f"L{l} y transform (im)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + 2 * spec),
+                (f"L{l} mode mixing", "mix_forward_kernel", 8 * C * C * 2 * m * m,
+                 spec + 2 * C * C * 2 * m * m * 4 + spec // 2),
+                (f"L{l} inverse y (re)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
+                (f"L{l} inverse y (im)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
+                (f"L{l} pointwise + inverse x + GELU", "layer_mix_kernel",
+                 2 * C * C * P + 2 * C * H * W * 2 * m,
+                 act + zx + act * (2 if training and not last else 1))]
+    if not training:
+        ops += [("projection (fused)", "projection_fused_kernel", 2 * C2 * C * P + 2 * Cout * C2 * P,
+                 act + Cout * P * 4),
+                ("output copy", "copyBuffer", 0, 2 * Cout * P * 4)]
+        return ops
+    hid = C2 * P * 2
+    ops += [("projection 1", "gemm_kernel", 2 * C2 * C * P, act + 2 * hid),
+            ("projection 2", "gemm_kernel", 2 * Cout * C2 * P, hid + Cout * P * 4),
+            ("loss sums", "loss_partial_kernel", 4 * Cout * P, Cout * P * 6),
+            ("loss", "loss_final_kernel", 0, 0),
+            ("loss gradient", "loss_grad_kernel", 3 * Cout * P, Cout * P * (6 + 2)),
+            ("projection 2 weight grad", "gemm_kernel", 2 * Cout * C2 * P, Cout * P * 2 + hid),
+            ("projection 2 input grad", "gemm_kernel", 2 * Cout * C2 * P, Cout * P * 2 + 2 * hid),
+            ("projection 1 weight grad", "gemm_kernel", 2 * C2 * C * P, hid + act),
+            ("projection 1 input grad", "gemm_kernel", 2 * C2 * C * P, hid + act)]
+    for l in reversed(range(L)):
+        ops += [(f"L{l} weight grad", "gemm_kernel", 2 * C * C * P, 2 * act),
+                (f"L{l} dU = dz IX^T", "gemm_kernel", 2 * C * H * W * 2 * m, act + zx),
+                (f"L{l} dS (re)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + spec),
+                (f"L{l} dS (im)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + 2 * spec),
+                (f"L{l} mode-mixing weight grad", "mix_backward_weight_kernel",
+                 8 * C * C * 2 * m * m, 2 * spec),
+                (f"L{l} mode-mixing input grad", "mix_backward_input_kernel",
+                 8 * C * C * 2 * m * m, 2 * spec),
+                (f"L{l} dZ (re)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
+                (f"L{l} dZ (im)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
+                (f"L{l} dv = W^T dz + dZ Fx^T, GELU'", "gemm_kernel",
+                 2 * C * C * P + 2 * C * H * W * 2 * m, act + zx + (act if l > 0 else 0) + act)]
+    ops += [("lift weight grad", "gemm_kernel", 2 * C * Cin * P, act + Cin * P * 2)]
+    return ops
+
+
+FNO_SHAPE = dict(channels=64, modes=12, layers=4, proj_channels=128)
+
+
+def fno_marker(qla, torch, z, e):
+    """A dispatch of a kernel the network never launches (the energy of a tiny plane z,
+    into e), which delimits the measured passes in a kernel trace."""
+    qla.qla_energy_noalloc(z[0], z[1], z[2], 8, 8, 8, qla.QLA_F64, e,
+                           torch.cuda.current_stream().cuda_stream)
+
+
+def fno_kernel_study(qla, torch, args):
+    """The surrogate network's kernels alone at the configured shape (side^2 lattice,
+    width 64, 12 modes per axis, 4 layers, projection 128, batch --batch) on random BF16
+    inputs and targets: --fno-reps forward passes and training steps, each timed with
+    events; per-sample algorithmic flops and bytes from fno_ops. Marker dispatches
+    (fno_marker) bracket the measured forward passes and training steps."""
+    from paper_2604_21128_amd import surrogate as S
+    B, side, reps = args.batch, args.side, args.fno_reps
+    sur = S.Surrogate(side, side, max_batch=B, seed=args.seed, **FNO_SHAPE)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(args.seed)
+    x = torch.randn((B, 4, side, side), device="cuda", generator=gen).to(torch.bfloat16)
+    y = torch.randn((B, 3, side, side), device="cuda", generator=gen).to(torch.bfloat16)
+    x, y = x.view(torch.int16), y.view(torch.int16)
+    out = torch.empty((B, 3, side, side), dtype=torch.float32, device="cuda")
+    mz = torch.zeros((3, 8, 8), dtype=torch.float64, device="cuda")
+    me = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        sur.predict(x, out)
+        sur.train_step(x, y, 1e-5)
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    fno_marker(qla, torch, mz, me)
+    a, b = ev(), ev()
+    a.record()
+    for _ in range(reps):
+        sur.predict(x, out)
+    b.record()
+    fno_marker(qla, torch, mz, me)
+    c, d = ev(), ev()
+    c.record()
+    for _ in range(reps):
+        sur.train_step(x, y, 1e-5)
+    d.record()
+    fno_marker(qla, torch, mz, me)
+    torch.cuda.synchronize()
+    t_fwd = a.elapsed_time(b) / 1e3 / reps
+    t_train = c.elapsed_time(d) / 1e3 / reps
+    nparam = int(qla.qla_fno_param_count(sur.h))
+    sur.close()
+    shape = (side, side, FNO_SHAPE["channels"], FNO_SHAPE["modes"], FNO_SHAPE["layers"], 4, 3,
+             FNO_SHAPE["proj_channels"], nparam)
+    f_ops, t_ops = fno_ops(*shape, training=False), fno_ops(*shape, training=True)
+    ff, fb = sum(o[2] for o in f_ops), sum(o[3] for o in f_ops)
+    tf, tb = sum(o[2] for o in t_ops), sum(o[3] for o in t_ops) + 7 * nparam * 4 / B
+    return {"workload": f"fno_{side}_width64_modes12_layers4_batch{B}", "batch": B,
+            "params": nparam, "reps": reps,
+            "forward": {"seconds_per_batch": t_fwd, "samples_per_s": B / t_fwd,
+                        "gflop_per_sample": ff / 1e9, "gbytes_per_sample": fb / 1e9,
+                        "tflops": ff * B / t_fwd / 1e12, "tbytes_per_s": fb * B / t_fwd / 1e12},
+            "training": {"seconds_per_step": t_train, "samples_per_s": B / t_train,
+                         "gflop_per_sample": tf / 1e9, "gbytes_per_sample": tb / 1e9,
+                         "tflops": tf * B / t_train / 1e12,
+                         "tbytes_per_s": tb * B / t_train / 1e12}}
+
+
+def summarize_fno(args):
+    """profiles/surrogate_fno_kernels.{md,json} from a kernel trace and FETCH_SIZE /
+    WRITE_SIZE runs of `bench.py --fno-kernels`: every dispatch between the last three
+    marker dispatches (one forward pass and one training step when --fno-reps 1) is matched
+    in order to fno_ops; durations from the trace, HBM bytes from the counters (scaled by
+    the reference copy of the same run), algorithmic flops and bytes from the model."""
+    import csv
+    import glob
+    trace_dir, fetch_dir, write_dir = args.summarize_fno
+    B, side = args.batch, args.side
+
+    def dispatches(d, counter=None):
+        rows = []
+        pat = "*kernel_trace.csv" if counter is None else "*counter_collection.csv"
+        for fn in glob.glob(os.path.join(d, pat)):
+            for r in csv.DictReader(open(fn)):
+                if counter is not None and r["Counter_Name"] != counter:
+                    continue
+                key = int(r.get("Dispatch_Id") or r.get("Correlation_Id"))
+                val = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) \
+                    if counter is None else float(r["Counter_Value"])
+                rows.append((key, r["Kernel_Name"], val))
+        rows.sort()
+        return [(n, v) for _, n, v in rows]
+
+    def sections(rows):
+        idx = [i for i, (n, _) in enumerate(rows) if "energy_final_kernel" in n]
+        if len(idx) < 3:
+            raise SystemExit("fewer than three marker dispatches")
+        i0, i1, i2 = idx[-3:]
+        strip = lambda s: [r for r in s if "energy_partial_kernel" not in r[0]]
+        return strip(rows[i0 + 1:i1]), strip(rows[i1 + 1:i2])
+    tr = sections(dispatches(trace_dir))
+    fe_all, wr_all = dispatches(fetch_dir, "FETCH_SIZE"), dispatches(write_dir, "WRITE_SIZE")
+    fcopy = max(v for n, v in fe_all if "copyBuffer" in n)
+    wcopy = max(v for n, v in wr_all if "copyBuffer" in n)
+    fs, ws = 1048576.0 / fcopy, 1048576.0 / wcopy
+    fe, wr = sections(fe_all), sections(wr_all)
+    nparam = args.fno_params
+    shape = (side, side, FNO_SHAPE["channels"], FNO_SHAPE["modes"], FNO_SHAPE["layers"], 4, 3,
+             FNO_SHAPE["proj_channels"], nparam)
+    out = {"batch": B, "side": side, "fetch_scale": fs, "write_scale": ws, "passes": {}}
+    lines = [f"# Surrogate network kernels: roofline per launch (MI355X, gfx950)", "",
+             f"Fourier neural operator on {side}x{side} lattices, width 64, 12 modes per axis, "
+             f"4 layers, projection 128, batch {B}, {nparam} parameters; random BF16 inputs and "
+             "targets (`bench.py --fno-kernels`). Flops and bytes are algorithmic (fno_ops in "
+             "bench.py: multiply-adds count two; one read of every input tensor and one write of "
+             "every output tensor an op needs); HBM bytes are FETCH_SIZE + WRITE_SIZE scaled by "
+             f"the 1 GiB reference copy of the same runs (x {fs:.4f}, x {ws:.4f}). Peaks: BF16 "
+             "dense MFMA 2500 TFLOP/s, HBM 8 TB/s.", ""]
+    cmds = getattr(args, "profile_commands", None) or []
+    if cmds:
+        lines += ["Commands (from /tmp with TMPDIR=/tmp; R = repository root):", "", "```"]
+        lines += cmds + ["```", ""]
+    for pi, name in enumerate(("forward (inference)", "training step")):
+        ops = fno_ops(*shape, training=(pi == 1))
+        rows = tr[pi]
+        j = 0
+        table, tot = [], {"us": 0.0, "flop": 0.0, "bytes": 0.0, "hbm": 0.0}
+        for k, (n, dur) in enumerate(rows):
+            f_b = fe[pi][k][1] * fs * 1024 if k < len(fe[pi]) else float("nan")
+            w_b = wr[pi][k][1] * ws * 1024 if k < len(wr[pi]) else float("nan")
+            short = n.replace("(anonymous namespace)::", "").split("(")[0]
+            if j < len(ops) and ops[j][1] in n:
+                op, _, fl, by = ops[j]
+                fl, by = fl * B, by * B
+                j += 1
+            else:
+                op, fl, by = "(" + short.split("::")[-1][:40] + ")", 0.0, 0.0
+                if "adam_kernel" in n:
+                    op, by = "Adam update", 7 * nparam * 4
+                elif "cast_kernel" in n:
+                    op = "BF16 weight copy"
+            us = dur / 1e3
+            hbm = f_b + w_b
+            table.append({"op": op, "kernel": short[:60], "us": us, "gflop": fl / 1e9,
+                          "mb": by / 1e6, "hbm_mb": hbm / 1e6,
+                          "tflops": fl / (us * 1e-6) / 1e12 if us else 0.0,
+                          "tbs": hbm / (us * 1e-6) / 1e12 if us else 0.0})
+            tot["us"] += us
+            tot["flop"] += fl
+            tot["bytes"] += by
+            tot["hbm"] += hbm
+        if j != len(ops):
+            raise SystemExit(f"{name}: matched {j} of {len(ops)} modelled ops")
+        out["passes"][name] = {"ops": table, "total": tot}
+        lines += [f"## {name}: {len(rows)} dispatches, {tot['us']:.0f} us of kernel time per "
+                  f"batch ({B / (tot['us'] * 1e-6):.0f} samples/s of kernel time)", "",
+                  f"Whole pass: {tot['flop'] / 1e9:.1f} GFLOP, {tot['bytes'] / 1e9:.2f} GB "
+                  f"algorithmic, {tot['hbm'] / 1e9:.2f} GB measured HBM; "
+                  f"{tot['flop'] / (tot['us'] * 1e-6) / 1e12:.1f} TFLOP/s "
+                  f"({tot['flop'] / (tot['us'] * 1e-6) / 2.5e15:.3f} of the MFMA peak), "
+                  f"{tot['hbm'] / (tot['us'] * 1e-6) / 1e12:.2f} TB/s measured "
+                  f"({tot['hbm'] / (tot['us'] * 1e-6) / 8e12:.3f} of peak).", "",
+                  "| op | kernel | us | GFLOP | algorithmic MB | HBM MB | TFLOP/s | HBM TB/s | "
+                  "bound, fraction |", "|---|---|---|---|---|---|---|---|---|"]
+        for r in table:
+            fm, fh = r["tflops"] / 2500.0, r["tbs"] / 8.0
+            bound = f"mfma {fm:.3f}" if fm > fh else f"hbm {fh:.3f}"
+            lines.append(f"| {r['op']} | `{r['kernel']}` | {r['us']:.1f} | {r['gflop']:.2f} | "
+                         f"{r['mb']:.1f} | {r['hbm_mb']:.1f} | {r['tflops']:.1f} | "
+                         f"{r['tbs']:.2f} | {bound} |")
+        lines.append("")
+    base = os.path.join(ROOT, "profiles", "surrogate_fno_kernels")
+    with open(base + ".json", "w") as f:
+        json.dump(out, f, indent=1)
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def summarize_batch(args):
+    """profiles/batched_512_trace.md from a kernel trace of `bench.py --batched`: the last
+    captured run is the last unbroken sequence of batched-kernel dispatches as long as the
+    plan's pass count; per pass its duration, the idle time before it, and the rate of the
+    site updates it applies (every lattice still running advances two steps per pass)."""
+    import csv
+    import glob
+    import numpy as np
+    import workloads
+    trace_dir = args.summarize_batch
+    rows = []
+    for fn in glob.glob(os.path.join(trace_dir, "*kernel_trace.csv")):
+        for r in csv.DictReader(open(fn)):
+            rows.append((int(r.get("Dispatch_Id") or r.get("Correlation_Id")), r["Kernel_Name"],
+                         float(r["Start_Timestamp"]), float(r["End_Timestamp"])))
+    rows.sort()
+    inst = workloads.sample_instances(args.instances, seed=0)
+    fused = args.batch_steps_per_pass
+    sides = np.array([i.n_side for i in inst], dtype=np.float64)
+    passes_of = np.array([i.steps // fused for i in inst])
+    npass = int(passes_of.max())
+    runs, cur = [], []
+    for r in rows:
+        if "qla_batch_kernel" in r[1]:
+            cur.append(r)
+        else:
+            if cur:
+                runs.append(cur)
+            cur = []
+    if cur:
+        runs.append(cur)
+    full = [r for r in runs if len(r) == npass]
+    if not full:
+        raise SystemExit(f"no run of {npass} batched dispatches in the trace")
+    run = full[-1]
+    start = np.array([r[2] for r in run])
+    end = np.array([r[3] for r in run])
+    dur = (end - start) * 1e-9
+    gap = np.concatenate([[0.0], np.maximum(start[1:] - end[:-1], 0.0) * 1e-9])
+    p = np.arange(npass)
+    work = np.array([fused * (sides[passes_of > k] ** 2).sum() for k in p])
+    span = (end[-1] - start[0]) * 1e-9
+    lines = ["# Batched run: where the time goes (MI355X, gfx950)", "",
+             f"Kernel trace of the captured run of {args.instances} lattices (sides 256-1024, "
+             f"4 x side steps each, FP32, {fused} steps per pass): {npass} launches of `{run[0][1].replace('(anonymous namespace)::', '').split('(')[0]}`.", ""]
+    cmds = getattr(args, "profile_commands", None) or []
+    if cmds:
+        lines += ["Commands (from /tmp with TMPDIR=/tmp; R = repository root):", "", "```"]
+        lines += cmds + ["```", ""]
+    total = work.sum()
+    lines += [f"- span of the run: {span * 1e3:.1f} ms; kernels busy {dur.sum() * 1e3:.1f} ms; "
+              f"idle between launches {gap.sum() * 1e3:.1f} ms ({gap.sum() / span:.1%}; median gap "
+              f"{np.median(gap[1:]) * 1e6:.1f} us)",
+              f"- site updates {total:.3e}: {total / span / 1e9:.1f} GLUPS over the span, "
+              f"{total / dur.sum() / 1e9:.1f} GLUPS over kernel time", "",
+              "| passes | lattices running | site updates per pass | mean launch (us) | "
+              "mean gap (us) | GLUPS in these launches | share of the span |",
+              "|---|---|---|---|---|---|---|"]
+    edges = [0, 64, 128, 256, 384, 512, 768, 1024, 1536, npass]
+    for a, b in zip(edges[:-1], edges[1:]):
+        if a >= npass:
+            break
+        sl = slice(a, min(b, npass))
+        running = int((passes_of > a).sum())
+        lines.append(f"| {a}-{min(b, npass) - 1} | {running}-{int((passes_of > min(b, npass) - 1).sum())} | "
+                     f"{work[sl].mean():.3e} | {dur[sl].mean() * 1e6:.1f} | {gap[sl].mean() * 1e6:.1f} | "
+                     f"{work[sl].sum() / dur[sl].sum() / 1e9:.1f} | "
+                     f"{(dur[sl].sum() + gap[sl].sum()) / span:.1%} |")
+    base = os.path.join(ROOT, "profiles", "batched_512_trace")
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def size_study(qla, torch, sides, precs, steps):
     """Lattice size against throughput on one GPU: the paper's ellipse scaled onto square
     lattices of each side (index generated on the device), the +x packet, the autotuned
@@ -923,6 +1229,20 @@ def main():
     ap.add_argument("--band-min", type=float, default=0.5,
                     help="surrogate: also report a run that sends inputs with less than this "
                          "share of their field energy in the kept modes straight to QLA")
+    ap.add_argument("--fno-kernels", action="store_true",
+                    help="the surrogate network's kernels alone (--side, --batch, --fno-reps): "
+                         "forward and training throughput with per-sample flops and bytes; "
+                         "prints its own JSON line")
+    ap.add_argument("--fno-reps", type=int, default=20)
+    ap.add_argument("--summarize-fno", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/surrogate_fno_kernels.{md,json} from a kernel trace and "
+                         "FETCH_SIZE / WRITE_SIZE runs of --fno-kernels --fno-reps 1")
+    ap.add_argument("--summarize-batch", metavar="TRACE_DIR",
+                    help="write profiles/batched_512_trace.md from a kernel trace of --batched")
+    ap.add_argument("--batch-steps-per-pass", type=int, default=2,
+                    help="with --summarize-batch: the plan's steps per pass")
+    ap.add_argument("--fno-params", type=int, default=0,
+                    help="with --summarize-fno: the network's parameter count")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--save-params", default="")
     ap.add_argument("--tuning-json", default="",
@@ -938,6 +1258,18 @@ def main():
             with open(args.profile_commands_file) as f:
                 args.profile_commands = [l.rstrip("\n") for l in f if l.strip()]
         summarize_counters(args)
+        return
+    if args.summarize_batch:
+        if args.profile_commands_file:
+            with open(args.profile_commands_file) as f:
+                args.profile_commands = [l.rstrip("\n") for l in f if l.strip()]
+        summarize_batch(args)
+        return
+    if args.summarize_fno:
+        if args.profile_commands_file:
+            with open(args.profile_commands_file) as f:
+                args.profile_commands = [l.rstrip("\n") for l in f if l.strip()]
+        summarize_fno(args)
         return
     if args.gpus != 1:
         print("bench.py: measures one GPU only; the multi-GPU halo-exchange path "
@@ -978,6 +1310,12 @@ def main():
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             out = divergence_study(qla, torch, w, args.snapshot_every)
+        print(json.dumps(out), flush=True)
+        return
+    if args.fno_kernels:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out = fno_kernel_study(qla, torch, args)
         print(json.dumps(out), flush=True)
         return
     if args.surrogate:

@@ -85,7 +85,10 @@ qla_status install_index(qla_ctx* c, const double* src, size_t ld) {
   double* n_new = c->staging + P;
   float* n32_new = c->fp32 ? reinterpret_cast<float*>(c->staging + 2 * P) : nullptr;
   const unsigned long long init[3] = {0ull, 0x7FF0000000000000ull, 0ull};  // 0, +inf, 0
-  QLA_HIP(hipMemcpyAsync(c->stats, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+  // Host data goes in with blocking copies once the stream is idle, so it has landed
+  // before the kernels below read it whatever path the runtime takes for pageable memory.
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  QLA_HIP(hipMemcpy(c->stats, init, sizeof(init), hipMemcpyHostToDevice));
   QLA_HIP(qla::launch_index_prepare(src, ld, c->nx, c->ny, c->pitch, c->delta, n_new, n32_new,
                                     c->stats, c->stream));
   unsigned long long got[3];
@@ -294,9 +297,11 @@ qla_status qla_set_index(qla_ctx* c, const double* n_host, size_t ld) {
   if (!c || !n_host) return fail(QLA_EINVAL, "NULL argument");
   if (ld < static_cast<size_t>(c->nx)) return fail(QLA_EINVAL, "ld < nx");
   QLA_ON_DEVICE(c->device);
-  // raw rows into the first staging plane (packed), then validate from there
-  QLA_HIP(hipMemcpy2DAsync(c->staging, c->nx * sizeof(double), n_host, ld * sizeof(double),
-                           c->nx * sizeof(double), c->ny, hipMemcpyHostToDevice, c->stream));
+  // raw rows into the first staging plane (packed), then validate from there; a blocking
+  // copy once the stream is idle (nothing queued still reads the staging planes)
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  QLA_HIP(hipMemcpy2D(c->staging, c->nx * sizeof(double), n_host, ld * sizeof(double),
+                      c->nx * sizeof(double), c->ny, hipMemcpyHostToDevice));
   return install_index(c, c->staging, c->nx);
 }
 
@@ -340,8 +345,8 @@ qla_status qla_set_fields(qla_ctx* c, const double* q_host, int64_t step) {
   if (step < 0) return fail(QLA_EINVAL, "step < 0");
   QLA_ON_DEVICE(c->device);
   const size_t N = c->count();
-  QLA_HIP(hipMemcpyAsync(c->staging, q_host, 3 * N * sizeof(double), hipMemcpyHostToDevice,
-                         c->stream));
+  QLA_HIP(hipStreamSynchronize(c->stream));
+  QLA_HIP(hipMemcpy(c->staging, q_host, 3 * N * sizeof(double), hipMemcpyHostToDevice));
   QLA_HIP(qla::launch_from_f64(c->staging, c->nx, c->ny, c->pitch, c->fp32,
                                c->q[c->cur][c->plane(0)],
                                c->q[c->cur][c->plane(1)], c->q[c->cur][c->plane(2)], c->stream));

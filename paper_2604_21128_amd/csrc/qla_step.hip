@@ -175,6 +175,8 @@ struct Marcher {
   // B streaming: every set streams the B-qubit, so each neighbour pair takes the angle
   // of its a site, and there are no potentials
   static constexpr bool kBStream = VMODE == kVBStream;
+  // FP32 (one or two columns per lane): neighbour pairs of U_x split between lanes
+  static constexpr bool kSplitPairs = sizeof(T) == 4;
   // Row window: amplitudes, index, 1/n and the collision shear of each row.
   V A[kWin], P4[kWin], P3[kWin], N[kWin], M[kWin], Tt[kWin], Ts[kWin];
   // Per-row wave-uniform facts, one bit per slot in scalar registers: umask bit s
@@ -230,19 +232,66 @@ struct Marcher {
   }
 
   // U_x on one row (slot s): lanes exchange neighbour values by DPP. In a
-  // uniform row the neighbours' shears are the lane's own and are not exchanged
-  // (the two versions differ only in the end lanes, which are halo).
+  // uniform row the neighbours' shears are the lane's own, and the FP64 form skips
+  // their exchange (the two versions differ only in the end lanes, which are halo).
   __device__ __forceinline__ void ux(int s) {
-    if (umask & (1u << s)) {
+    if constexpr (kSplitPairs) {
+      // One lane shift per neighbour value, in every row: a branch on uniform rows
+      // costs more here (its join copies and the negations it keeps from folding
+      // into the FMAs) than the four shifts it would save.
+      ux_with(s, from_left(Tt[s]), from_left(Ts[s]), from_right(Tt[s]), from_right(Ts[s]));
+    } else if (umask & (1u << s)) {
       ux_with(s, Tt[s], Ts[s], Tt[s], Ts[s]);
     } else {
       ux_with(s, from_left(Tt[s]), from_left(Ts[s]), from_right(Tt[s]), from_right(Ts[s]));
     }
   }
 
+  // The neighbour rotation of U_x on pair (a_i, p_j), j = i - 1 (kLeft) or i + 1,
+  // split between the two lanes holding it: lane i forms a1 = a_i - t p_j, lane j
+  // forms p_j' = p_j + s a1 from that a1, lane i forms a_i' = a1 - t p_j' from that
+  // p_j'. These are the values rotate_first and rotate_second give (they form a1 in
+  // both lanes), with three lane shifts instead of two and two FMAs fewer per pair:
+  // the form used where a lane shift is one instruction (FP32). ta: the t that the
+  // a-lane applies; sp: the s that the p-lane applies.
+  template <bool kLeft>
+  __device__ __forceinline__ void split_pair(V& a, V& p, V ta, V sp) {
+    if constexpr (kLeft) {
+      const V a1 = fma(-ta, from_left(p), a);
+      p = fma(sp, from_right(a1), p);
+      a = fma(-ta, from_left(p), a1);
+    } else {
+      const V a1 = fma(-ta, from_right(p), a);
+      p = fma(sp, from_left(a1), p);
+      a = fma(-ta, from_right(p), a1);
+    }
+  }
+
   __device__ __forceinline__ void ux_with(int s, V tl, V sl, V tr, V sr) {
     V a = A[s], p = P4[s];
     const V t0 = Tt[s], s0 = Ts[s];
+    if constexpr (kSplitPairs) {
+      // the sets below, with each neighbour pair split between its lanes
+      rotate(a, p, -t0, -s0);
+      split_pair<true>(a, p, t0, sr);
+      rotate(a, p, -t0, -s0);
+      if constexpr (kBStream) {
+        split_pair<true>(a, p, t0, sr);
+      } else {
+        split_pair<true>(a, p, tl, s0);
+      }
+      rotate(a, p, t0, s0);
+      split_pair<false>(a, p, -t0, -sl);
+      rotate(a, p, t0, s0);
+      if constexpr (kBStream) {
+        split_pair<false>(a, p, -t0, -sl);
+      } else {
+        split_pair<false>(a, p, -tr, -s0);
+      }
+      A[s] = a;
+      P4[s] = p;
+      return;
+    }
     // set 1: C^T on site; C(th_i) on (a_i, p_{i-1})
     rotate(a, p, -t0, -s0);
     {
