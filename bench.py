@@ -714,7 +714,9 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
     name fragment, algorithmic flops, algorithmic HBM bytes). Bytes count one read of each
     input tensor and one write of each output tensor an op needs (BF16 activations, FP32
     spectra, losses and outputs); flops count multiply-adds as two. Inference runs the fused
-    projection; training keeps the two projection GEMMs and the pre-activations."""
+    projection; training keeps the first projection GEMM, the pre-activations, and runs the
+    narrow second projection (3 output channels) and its input gradient on the vector
+    units."""
     P = H * W
     act = C * P * 2                     # one BF16 activation tensor
     zx = C * H * 2 * m * 2              # x-transformed rows (BF16, re/im interleaved)
@@ -739,12 +741,13 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
         return ops
     hid = C2 * P * 2
     ops += [("projection 1", "gemm_kernel", 2 * C2 * C * P, act + 2 * hid),
-            ("projection 2", "gemm_kernel", 2 * Cout * C2 * P, hid + Cout * P * 4),
+            ("projection 2", "narrow_projection_kernel", 2 * Cout * C2 * P, hid + Cout * P * 4),
             ("loss sums", "loss_partial_kernel", 4 * Cout * P, Cout * P * 6),
             ("loss", "loss_final_kernel", 0, 0),
             ("loss gradient", "loss_grad_kernel", 3 * Cout * P, Cout * P * (6 + 2)),
             ("projection 2 weight grad", "gemm_kernel", 2 * Cout * C2 * P, Cout * P * 2 + hid),
-            ("projection 2 input grad", "gemm_kernel", 2 * Cout * C2 * P, Cout * P * 2 + 2 * hid),
+            ("projection 2 input grad", "narrow_projection_grad_kernel", 2 * Cout * C2 * P,
+             Cout * P * 2 + 2 * hid),
             ("projection 1 weight grad", "gemm_kernel", 2 * C2 * C * P, hid + act),
             ("projection 1 input grad", "gemm_kernel", 2 * C2 * C * P, hid + act)]
     for l in reversed(range(L)):

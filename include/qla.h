@@ -319,7 +319,8 @@ qla_status qla_batch_destroy(qla_batch *batch);
  *   v0 = P u + p                                    (lift, Cin -> C channels)
  *   v_{l+1} = act(IDFT_m[R_l . DFT_m(v_l)] + W_l v_l + b_l),   l = 0 .. L-1
  *   out = Q2 GELU(Q1 v_L + q1) + q2                 (projection C -> C2 -> Cout)
- * act is the exact GELU, x Phi(x), except after the last Fourier layer (identity).
+ * act is GELU, x Phi(x) (erf by Abramowitz & Stegun 7.1.26, |error| <= 1.5e-7), except
+ * after the last Fourier layer (identity).
  * DFT_m keeps the modes ky in [0, m) U [H - m, H), kx in [0, m) of the real 2D
  * transform over the periodic H x W grid; R_l holds a complex C x C matrix per kept
  * mode. Activations are stored in BF16 and every contraction runs on the matrix
@@ -341,8 +342,8 @@ qla_status qla_batch_destroy(qla_batch *batch);
 typedef struct qla_fno qla_fno;
 
 /* Create a surrogate for an H x W grid (2m <= H, 2m <= W) with the given channel
- * counts, m kept modes per axis, L Fourier layers and batches up to max_batch
- * (max_batch * max(C, C2) * H * W < 2^31). Allocates the parameters, optimiser state
+ * counts (width C <= 64), m kept modes per axis, L Fourier layers and batches up to
+ * max_batch (max_batch * max(C, C2) * H * W < 2^31); QLA_EINVAL otherwise. Allocates the parameters, optimiser state
  * and the activations of a max_batch batch. Weights are initialised from `seed`:
  * linear maps uniform in +-1/sqrt(fan_in), spectral weights uniform in [0, 1/C^2).
  * hip_stream: the stream to use, or NULL for a library-owned one. Synchronises. */

@@ -41,11 +41,8 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ float gelu_prime(float x) {
-  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
-  const float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
-  return cdf + x * pdf;
-}
+using qla::fno::gelu_as;
+using qla::fno::gelu_prime_as;
 
 unsigned grid_for(size_t n) {
   const size_t b = (n + kBlock - 1) / kBlock;
@@ -122,6 +119,105 @@ __global__ __launch_bounds__(256) void lift_kernel(const uint16_t* __restrict__ 
   }
 }
 
+// The second projection layer and its input gradient in training, where the product is
+// narrow (Cout <= 4 output channels, C2 hidden ones) and a GEMM pads Cout to its tile:
+// both are streams on the vector units, 8 consecutive pixels per thread (16-byte loads and
+// stores), the weights (BF16 copies, as the GEMM path uses) and bias in LDS.
+//   forward:  out[b][o][p] = bq2[o] + sum_h Q2[o][h] h[b][h][p]                 (FP32)
+//   backward: dzq[b][h][p] = (sum_o Q2[o][h] dout[b][o][p]) GELU'(zq[b][h][p])  (BF16)
+// Shapes: Cout <= kNarrowOut, C2 <= kNarrowC2, P a multiple of 8 (else the GEMM path).
+constexpr int kNarrowOut = 4, kNarrowC2 = 256;
+
+__device__ __forceinline__ void load8_bf16(const uint16_t* src, float* x) {
+  const uint4 q = *reinterpret_cast<const uint4*>(src);
+  uint16_t e[8];
+  __builtin_memcpy(e, &q, 16);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = bf16_to_f32(e[k]);
+}
+
+__global__ __launch_bounds__(256) void narrow_projection_kernel(
+    const uint16_t* __restrict__ h, const uint16_t* __restrict__ q2,
+    const float* __restrict__ bias, int C2, int Cout, long long P, int B,
+    float* __restrict__ out) {
+  __shared__ float sw[kNarrowOut][kNarrowC2];
+  for (int i = threadIdx.x; i < kNarrowOut * kNarrowC2; i += 256) {
+    const int o = i / kNarrowC2, c = i % kNarrowC2;
+    sw[o][c] = (o < Cout && c < C2) ? bf16_to_f32(q2[o * C2 + c]) : 0.f;
+  }
+  __syncthreads();
+  const long long groups = P / 8;
+  for (long long gi = blockIdx.x * 256LL + threadIdx.x; gi < groups * B;
+       gi += static_cast<long long>(gridDim.x) * 256) {
+    const int b = static_cast<int>(gi / groups);
+    const long long p = (gi % groups) * 8;
+    float acc[kNarrowOut][8];
+#pragma unroll
+    for (int o = 0; o < kNarrowOut; ++o)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[o][k] = o < Cout ? bias[o] : 0.f;
+    const uint16_t* src = h + static_cast<long long>(b) * C2 * P + p;
+    for (int c = 0; c < C2; ++c) {
+      float x[8];
+      load8_bf16(src + static_cast<long long>(c) * P, x);
+#pragma unroll
+      for (int o = 0; o < kNarrowOut; ++o)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[o][k] = fmaf(sw[o][c], x[k], acc[o][k]);
+    }
+    for (int o = 0; o < Cout; ++o) {
+      float* dst = out + (static_cast<long long>(b) * Cout + o) * P + p;
+      *reinterpret_cast<float4*>(dst) = make_float4(acc[o][0], acc[o][1], acc[o][2], acc[o][3]);
+      *reinterpret_cast<float4*>(dst + 4) =
+          make_float4(acc[o][4], acc[o][5], acc[o][6], acc[o][7]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void narrow_projection_grad_kernel(
+    const uint16_t* __restrict__ dout, const uint16_t* __restrict__ q2,
+    const uint16_t* __restrict__ zq, int C2, int Cout, long long P, int B,
+    uint16_t* __restrict__ dzq) {
+  __shared__ float sw[kNarrowC2][kNarrowOut];
+  for (int i = threadIdx.x; i < kNarrowOut * kNarrowC2; i += 256) {
+    const int c = i / kNarrowOut, o = i % kNarrowOut;
+    sw[c][o] = (o < Cout && c < C2) ? bf16_to_f32(q2[o * C2 + c]) : 0.f;
+  }
+  __syncthreads();
+  const long long groups = P / 8;
+  for (long long gi = blockIdx.x * 256LL + threadIdx.x; gi < groups * B;
+       gi += static_cast<long long>(gridDim.x) * 256) {
+    const int b = static_cast<int>(gi / groups);
+    const long long p = (gi % groups) * 8;
+    float d[kNarrowOut][8];
+#pragma unroll
+    for (int o = 0; o < kNarrowOut; ++o) {
+      if (o < Cout) {
+        load8_bf16(dout + (static_cast<long long>(b) * Cout + o) * P + p, d[o]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d[o][k] = 0.f;
+      }
+    }
+    const long long base = static_cast<long long>(b) * C2 * P + p;
+    for (int c = 0; c < C2; ++c) {
+      float z[8];
+      load8_bf16(zq + base + static_cast<long long>(c) * P, z);
+      uint16_t e[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        float v = 0.f;
+#pragma unroll
+        for (int o = 0; o < kNarrowOut; ++o) v = fmaf(sw[c][o], d[o][k], v);
+        e[k] = f32_to_bf16(v * gelu_prime_as(z[k]));
+      }
+      uint4 q;
+      __builtin_memcpy(&q, e, 16);
+      *reinterpret_cast<uint4*>(dzq + base + static_cast<long long>(c) * P) = q;
+    }
+  }
+}
+
 // Inference projection in one pass:
 //   out[b][o][p] = bq2[o] + sum_h Q2[o][h] GELU(bq1[h] + sum_c Q1[h][c] v[b][c][p]).
 // The C2-channel hidden layer never leaves the chip (the two-GEMM path writes it to
@@ -140,24 +236,10 @@ constexpr int kProjPix = 64, kProjK = 32, kProjMaxC = 64, kProjMaxC2 = 128, kPro
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-// GELU(x) = x Phi(x) = (x / 2) (1 + erf(x / sqrt 2)), with erf from Abramowitz & Stegun,
-// Handbook of Mathematical Functions, formula 7.1.26 (|error| <= 1.5e-7, far below the
-// BF16 rounding of the inputs): erf(z) = 1 - t (a1 + t (a2 + ... + t a5)) exp(-z^2),
-// t = 1 / (1 + p z) for z >= 0, odd in z; the sum is formed from 1 - erf(|z|) directly,
-// so the negative tail keeps its relative accuracy. With the library erff the GELUs
-// were half of this kernel's time (every hidden value of every pixel).
-__device__ __forceinline__ float gelu_f(float x) {
-  const float z = fabsf(x) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.0f));
-  float poly = 1.061405429f;
-  poly = fmaf(poly, t, -1.453152027f);
-  poly = fmaf(poly, t, 1.421413741f);
-  poly = fmaf(poly, t, -0.284496736f);
-  poly = fmaf(poly, t, 0.254829592f);
-  const float e = __builtin_amdgcn_exp2f(-z * z * 1.4426950408889634f);  // exp(-z^2)
-  const float c = poly * t * e;  // 1 - erf(z), without cancellation in either tail
-  return x >= 0.0f ? fmaf(-0.5f * x, c, x) : 0.5f * x * c;
-}
+// GELU in the fused kernels: the Abramowitz & Stegun form of fno_internal.h (with the
+// library erff the GELUs were half of the projection kernel's time: every hidden value
+// of every pixel).
+__device__ __forceinline__ float gelu_f(float x) { return gelu_as(x); }
 
 __device__ __forceinline__ int proj_col(int r, int k) {
   return ((((k >> 3) ^ (r >> 3)) & 3) << 3) | (k & 7);
@@ -429,81 +511,141 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
   }
 }
 
-// S[(b,o)][2kyi+p][kx] = sum_c R[kyi][kx][c][o] (complex) * T[(b,c)][2kyi+p][kx]
-__global__ void mix_forward_kernel(const float* __restrict__ T, const float* __restrict__ R,
-                                   uint16_t* __restrict__ S, int B, int C, int m) {
-  const int modes = 2 * m * m;
-  const size_t total = size_t(B) * C * modes;
-  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < total;
-       i += size_t(gridDim.x) * kBlock) {
-    const int o = static_cast<int>(i % C);
-    const int mode = static_cast<int>((i / C) % modes);
-    const int b = static_cast<int>(i / (size_t(C) * modes));
-    const int kyi = mode / m, kx = mode % m;
-    float sr = 0.f, si = 0.f;
-    for (int c = 0; c < C; ++c) {
-      const size_t tb = (size_t(b) * C + c) * (4 * m * m);
-      const float tr = T[tb + (2 * kyi) * m + kx], ti = T[tb + (2 * kyi + 1) * m + kx];
-      const size_t ri = ((size_t(mode) * C + c) * C + o) * 2;
-      const float rr = R[ri], rim = R[ri + 1];
-      sr += rr * tr - rim * ti;
-      si += rr * ti + rim * tr;
+// Mode mixing of a Fourier layer and its two backward products. Spectra are
+// [(b, c)][2 kyi + p][kx] (p = 0: real part, 1: imaginary part), R is [mode][c][o][2]
+// with mode = kyi m + kx. One block per mode: its spectral values of every (b, c) (4-byte
+// words 2 m apart in memory) are gathered into LDS once, R's C x C block of the mode is read
+// contiguously, and the products run out of LDS (sample b in chunks of kModeRows / C).
+// The complex products are written as real pairs:
+//   S    = sum_c R[c][o] T[c]:       (rr tr - ri ti, rr ti + ri tr)
+//   dT   = sum_o conj(R[c][o]) dS[o]: (rr dr + ri di, rr di - ri dr)
+//   dR  += sum_b conj(T[b][c]) dS[b][o]: (tr dr + ti di, tr di - ti dr)
+constexpr int kModeC = 64;        // channel limit of the per-mode kernels
+constexpr int kModeRows = 1024;   // (b, c) pairs staged per chunk
+
+__device__ __forceinline__ size_t spec_at(int b, int c, int C, int m, int kyi, int kx) {
+  return (static_cast<size_t>(b) * C + c) * (4 * m * m) + static_cast<size_t>(2 * kyi) * m + kx;
+}
+
+// S[(b,o)] at one mode = sum_c R[mode][c][o] T[(b,c)] (complex), stored BF16.
+__global__ __launch_bounds__(256) void mix_forward_kernel(const float* __restrict__ T,
+                                                          const float* __restrict__ R,
+                                                          uint16_t* __restrict__ S, int B, int C,
+                                                          int m) {
+  __shared__ float rs[kModeC * kModeC * 2];  // R[c][o][2] of this mode
+  __shared__ float tre[kModeRows], tim[kModeRows];
+  const int mode = blockIdx.x, kyi = mode / m, kx = mode % m, t = threadIdx.x;
+  const float* rm = R + static_cast<size_t>(mode) * C * C * 2;
+  for (int i = t; i < C * C * 2; i += 256) rs[i] = rm[i];
+  const int per = kModeRows / C;  // samples per chunk
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int nb = min(per, B - b0);
+    __syncthreads();
+    for (int i = t; i < nb * C; i += 256) {
+      const size_t at = spec_at(b0 + i / C, i % C, C, m, kyi, kx);
+      tre[i] = T[at];
+      tim[i] = T[at + m];
     }
-    const size_t sb = (size_t(b) * C + o) * (4 * m * m);
-    S[sb + (2 * kyi) * m + kx] = f32_to_bf16(sr);
-    S[sb + (2 * kyi + 1) * m + kx] = f32_to_bf16(si);
+    __syncthreads();
+    for (int i = t; i < nb * C; i += 256) {  // output (b, o): consecutive threads, consecutive o
+      const int bl = i / C, o = i % C;
+      float sr = 0.f, si = 0.f;
+      for (int c = 0; c < C; ++c) {
+        const float rr = rs[(c * C + o) * 2], ri = rs[(c * C + o) * 2 + 1];
+        const float tr = tre[bl * C + c], ti = tim[bl * C + c];
+        sr = fmaf(rr, tr, fmaf(-ri, ti, sr));
+        si = fmaf(rr, ti, fmaf(ri, tr, si));
+      }
+      const size_t at = spec_at(b0 + bl, o, C, m, kyi, kx);
+      S[at] = f32_to_bf16(sr);
+      S[at + m] = f32_to_bf16(si);
+    }
   }
 }
 
-// dT[(b,c)] = sum_o conj-transposed R applied to dS (real-pair calculus of the above)
-__global__ void mix_backward_input_kernel(const float* __restrict__ dS, const float* __restrict__ R,
-                                          uint16_t* __restrict__ dT, int B, int C, int m) {
-  const int modes = 2 * m * m;
-  const size_t total = size_t(B) * C * modes;
-  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < total;
-       i += size_t(gridDim.x) * kBlock) {
-    const int c = static_cast<int>(i % C);
-    const int mode = static_cast<int>((i / C) % modes);
-    const int b = static_cast<int>(i / (size_t(C) * modes));
-    const int kyi = mode / m, kx = mode % m;
-    float gr = 0.f, gi = 0.f;
-    for (int o = 0; o < C; ++o) {
-      const size_t sb = (size_t(b) * C + o) * (4 * m * m);
-      const float dr = dS[sb + (2 * kyi) * m + kx], di = dS[sb + (2 * kyi + 1) * m + kx];
-      const size_t ri = ((size_t(mode) * C + c) * C + o) * 2;
-      const float rr = R[ri], rim = R[ri + 1];
-      gr += dr * rr + di * rim;
-      gi += -dr * rim + di * rr;
+// dT[(b,c)] at one mode = sum_o conj(R[mode][c][o]) dS[(b,o)], stored BF16.
+__global__ __launch_bounds__(256) void mix_backward_input_kernel(const float* __restrict__ dS,
+                                                                 const float* __restrict__ R,
+                                                                 uint16_t* __restrict__ dT,
+                                                                 int B, int C, int m) {
+  __shared__ float rs[kModeC * kModeC * 2];  // R[o][c][2] of this mode (transposed)
+  __shared__ float dre[kModeRows], dim_[kModeRows];
+  const int mode = blockIdx.x, kyi = mode / m, kx = mode % m, t = threadIdx.x;
+  const float* rm = R + static_cast<size_t>(mode) * C * C * 2;
+  for (int i = t; i < C * C; i += 256) {  // i = c C + o, read contiguously
+    const int c = i / C, o = i % C;
+    rs[(o * C + c) * 2] = rm[2 * i];
+    rs[(o * C + c) * 2 + 1] = rm[2 * i + 1];
+  }
+  const int per = kModeRows / C;
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int nb = min(per, B - b0);
+    __syncthreads();
+    for (int i = t; i < nb * C; i += 256) {
+      const size_t at = spec_at(b0 + i / C, i % C, C, m, kyi, kx);
+      dre[i] = dS[at];
+      dim_[i] = dS[at + m];
     }
-    const size_t tb = (size_t(b) * C + c) * (4 * m * m);
-    dT[tb + (2 * kyi) * m + kx] = f32_to_bf16(gr);
-    dT[tb + (2 * kyi + 1) * m + kx] = f32_to_bf16(gi);
+    __syncthreads();
+    for (int i = t; i < nb * C; i += 256) {  // output (b, c): consecutive threads, consecutive c
+      const int bl = i / C, c = i % C;
+      float gr = 0.f, gi = 0.f;
+      for (int o = 0; o < C; ++o) {
+        const float rr = rs[(o * C + c) * 2], ri = rs[(o * C + c) * 2 + 1];
+        const float dr = dre[bl * C + o], di = dim_[bl * C + o];
+        gr = fmaf(rr, dr, fmaf(ri, di, gr));
+        gi = fmaf(rr, di, fmaf(-ri, dr, gi));
+      }
+      const size_t at = spec_at(b0 + bl, c, C, m, kyi, kx);
+      dT[at] = f32_to_bf16(gr);
+      dT[at + m] = f32_to_bf16(gi);
+    }
   }
 }
 
-// dR[mode][c][o] += sum_b (dS_r T_r + dS_i T_i, -dS_r T_i + dS_i T_r)
-__global__ void mix_backward_weight_kernel(const float* __restrict__ dS,
-                                           const float* __restrict__ T, float* __restrict__ dR,
-                                           int B, int C, int m) {
-  const int modes = 2 * m * m;
-  const size_t total = size_t(modes) * C * C;
-  for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < total;
-       i += size_t(gridDim.x) * kBlock) {
-    const int o = static_cast<int>(i % C);
-    const int c = static_cast<int>((i / C) % C);
-    const int mode = static_cast<int>(i / (size_t(C) * C));
-    const int kyi = mode / m, kx = mode % m;
-    float ar = 0.f, ai = 0.f;
-    for (int b = 0; b < B; ++b) {
-      const size_t tb = (size_t(b) * C + c) * (4 * m * m);
-      const size_t sb = (size_t(b) * C + o) * (4 * m * m);
-      const float tr = T[tb + (2 * kyi) * m + kx], ti = T[tb + (2 * kyi + 1) * m + kx];
-      const float dr = dS[sb + (2 * kyi) * m + kx], di = dS[sb + (2 * kyi + 1) * m + kx];
-      ar += dr * tr + di * ti;
-      ai += -dr * ti + di * tr;
+// dR[mode][c][o] += sum_b conj(T[(b,c)]) dS[(b,o)] at one mode.
+__global__ __launch_bounds__(256) void mix_backward_weight_kernel(const float* __restrict__ dS,
+                                                                  const float* __restrict__ T,
+                                                                  float* __restrict__ dR, int B,
+                                                                  int C, int m) {
+  __shared__ float tre[kModeRows], tim[kModeRows], dre[kModeRows], dim_[kModeRows];
+  constexpr int kOut = kModeC * kModeC / 256;  // outputs per thread
+  const int mode = blockIdx.x, kyi = mode / m, kx = mode % m, t = threadIdx.x;
+  float ar[kOut], ai[kOut];
+#pragma unroll
+  for (int k = 0; k < kOut; ++k) ar[k] = ai[k] = 0.f;
+  const int per = kModeRows / C;
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int nb = min(per, B - b0);
+    __syncthreads();
+    for (int i = t; i < nb * C; i += 256) {
+      const size_t at = spec_at(b0 + i / C, i % C, C, m, kyi, kx);
+      tre[i] = T[at];
+      tim[i] = T[at + m];
+      dre[i] = dS[at];
+      dim_[i] = dS[at + m];
     }
-    dR[2 * i] += ar;
-    dR[2 * i + 1] += ai;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) {  // output j = c C + o: consecutive threads, consecutive o
+      const int j = t + 256 * k;
+      if (j >= C * C) break;
+      const int c = j / C, o = j % C;
+      for (int bl = 0; bl < nb; ++bl) {
+        const float tr = tre[bl * C + c], ti = tim[bl * C + c];
+        const float dr = dre[bl * C + o], di = dim_[bl * C + o];
+        ar[k] = fmaf(tr, dr, fmaf(ti, di, ar[k]));
+        ai[k] = fmaf(tr, di, fmaf(-ti, dr, ai[k]));
+      }
+    }
+  }
+  float* rm = dR + static_cast<size_t>(mode) * C * C * 2;
+#pragma unroll
+  for (int k = 0; k < kOut; ++k) {
+    const int j = t + 256 * k;
+    if (j >= C * C) break;
+    rm[2 * j] += ar[k];
+    rm[2 * j + 1] += ai[k];
   }
 }
 
@@ -511,7 +653,7 @@ __global__ void mix_backward_weight_kernel(const float* __restrict__ dS,
 __global__ void gelu_grad_kernel(const float* __restrict__ dv, const uint16_t* __restrict__ z,
                                  uint16_t* __restrict__ dz, size_t n) {
   for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock)
-    dz[i] = f32_to_bf16(dv[i] * gelu_prime(bf16_to_f32(z[i])));
+    dz[i] = f32_to_bf16(dv[i] * gelu_prime_as(bf16_to_f32(z[i])));
 }
 
 // sums[2b] += sum (out - target)^2, sums[2b+1] += sum target^2 over sample b
@@ -933,8 +1075,8 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
       g.beta = part;
       QLA_GEMM(g);
     }
-    hipLaunchKernelGGL(mix_forward_kernel, dim3(grid_for(size_t(B) * C * 2 * m * m)),
-                       dim3(kBlock), 0, f->stream, f->T[l], f->p + f->o_R[l], f->Sb, B, C, m);
+    hipLaunchKernelGGL(mix_forward_kernel, dim3(2 * m * m), dim3(256), 0, f->stream, f->T[l],
+                       f->p + f->o_R[l], f->Sb, B, C, m);
     QLA_HIP(hipGetLastError());
     // inverse y: U[(b,o)][y][2kx+p] = IY_p S
     for (int part = 0; part < 2; ++part) {
@@ -1025,7 +1167,15 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
     g.act = f->h;
     QLA_GEMM(g);
   }
-  {
+  if (f->Cout <= kNarrowOut && f->C2 <= kNarrowC2 && P % 8 == 0) {
+    const long long threads = static_cast<long long>(P) / 8 * B;
+    const long long blocks = (threads + 255) / 256;
+    hipLaunchKernelGGL(narrow_projection_kernel,
+                       dim3(static_cast<unsigned>(blocks < 8192 ? blocks : 8192)), dim3(256), 0,
+                       f->stream, f->h, f->w16 + f->w16_Q2(), f->p + f->o_bq2, f->C2, f->Cout,
+                       static_cast<long long>(P), B, f->out);
+    QLA_HIP(hipGetLastError());
+  } else {
     GemmDesc g = pointwise(f->w16 + f->w16_Q2(), false, f->Cout, f->C2, f->h, B, P);
     g.bias = f->p + f->o_bq2;
     g.C = f->out;
@@ -1052,7 +1202,15 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
   QLA_HIP(hipGetLastError());
   // projection 2, then dzq = (Q2^T dout) GELU'(zq)
   QLA_GEMM(weight_grad(f->dout, f->Cout, f->h, C2, B, P, f->g + f->o_Q2, f->g + f->o_bq2));
-  {
+  if (f->Cout <= kNarrowOut && C2 <= kNarrowC2 && P % 8 == 0) {
+    const long long threads = static_cast<long long>(P) / 8 * B;
+    const long long blocks = (threads + 255) / 256;
+    hipLaunchKernelGGL(narrow_projection_grad_kernel,
+                       dim3(static_cast<unsigned>(blocks < 8192 ? blocks : 8192)), dim3(256), 0,
+                       f->stream, f->dout, f->w16 + f->w16_Q2(), f->zq, C2, f->Cout,
+                       static_cast<long long>(P), B, f->dzq);
+    QLA_HIP(hipGetLastError());
+  } else {
     GemmDesc g = pointwise(f->w16 + f->w16_Q2(), true, C2, f->Cout, f->dout, B, P);
     g.C = f->dzq;
     g.out_bf16 = 1;
@@ -1111,11 +1269,11 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
       g.beta = part;
       QLA_GEMM(g);
     }
-    hipLaunchKernelGGL(mix_backward_weight_kernel, dim3(grid_for(size_t(2 * m * m) * C * C)),
-                       dim3(kBlock), 0, f->stream, f->dS, f->T[l], f->g + f->o_R[l], B, C, m);
+    hipLaunchKernelGGL(mix_backward_weight_kernel, dim3(2 * m * m), dim3(256), 0, f->stream,
+                       f->dS, f->T[l], f->g + f->o_R[l], B, C, m);
     QLA_HIP(hipGetLastError());
-    hipLaunchKernelGGL(mix_backward_input_kernel, dim3(grid_for(size_t(B) * C * 2 * m * m)),
-                       dim3(kBlock), 0, f->stream, f->dS, f->p + f->o_R[l], f->dT, B, C, m);
+    hipLaunchKernelGGL(mix_backward_input_kernel, dim3(2 * m * m), dim3(256), 0, f->stream,
+                       f->dS, f->p + f->o_R[l], f->dT, B, C, m);
     QLA_HIP(hipGetLastError());
     // dZ_p = A_p^T dT  (p = re, im)
     for (int part = 0; part < 2; ++part) {
@@ -1201,6 +1359,8 @@ qla_status qla_fno_create(int height, int width, int in_channels, int out_channe
     return fail(QLA_EINVAL, "sizes must be positive");
   if (2 * modes > height || 2 * modes > width)
     return fail(QLA_EINVAL, "need 2 * modes <= height and 2 * modes <= width");
+  if (channels > kModeC)
+    return fail(QLA_EINVAL, "channels must be <= " + std::to_string(kModeC));
   if (static_cast<long long>(max_batch) * std::max(channels, proj_channels) * height * width >=
       (1ll << 31))
     return fail(QLA_EINVAL, "max_batch * channels * height * width must be < 2^31");

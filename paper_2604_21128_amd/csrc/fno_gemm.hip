@@ -33,15 +33,11 @@ constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ float gelu(float x) {
-  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
-}
-
-__device__ __forceinline__ float gelu_prime(float x) {
-  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
-  const float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
-  return cdf + x * pdf;
-}
+// GELU and its derivative in the epilogues: the Abramowitz & Stegun 7.1.26 forms of
+// fno_internal.h (with the library erff and expf they took most of the time of the
+// epilogues that apply them to every element).
+__device__ __forceinline__ float gelu(float x) { return gelu_as(x); }
+__device__ __forceinline__ float gelu_prime(float x) { return gelu_prime_as(x); }
 
 // One operand seen as rows r (A: m; B: n) by k: element (r, k) at p[r * sr + k * sk].
 // Its access mode (a template argument where it is used) is 0 when k is contiguous,

@@ -18,6 +18,39 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
   return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16);
 }
 
+// GELU(x) = x Phi(x) = (x / 2)(1 + erf(x / sqrt 2)) and GELU'(x) = Phi(x) + x phi(x), with
+// erf from Abramowitz & Stegun, Handbook of Mathematical Functions, formula 7.1.26
+// (|error| <= 1.5e-7, far below the BF16 rounding around them):
+//   1 - erf(z) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-z^2), t = 1 / (1 + p z), z >= 0,
+// odd in z. With z = |x| / sqrt 2 the same exp(-z^2) = exp(-x^2 / 2) gives the normal
+// density phi(x) = exp(-x^2 / 2) / sqrt(2 pi), so the derivative costs one exponential (the
+// hardware exp2) and one reciprocal. 1 - erf(|z|) is formed directly, so neither tail
+// loses its relative accuracy to cancellation.
+struct ErfTail {
+  float c;  // 1 - erf(|x| / sqrt 2)
+  float e;  // exp(-x^2 / 2)
+};
+__device__ __forceinline__ ErfTail erf_tail(float x) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.0f));
+  float poly = 1.061405429f;
+  poly = fmaf(poly, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  const float e = __builtin_amdgcn_exp2f(-z * z * 1.4426950408889634f);
+  return {poly * t * e, e};
+}
+__device__ __forceinline__ float gelu_as(float x) {
+  const float c = erf_tail(x).c;
+  return x >= 0.0f ? fmaf(-0.5f * x, c, x) : 0.5f * x * c;
+}
+__device__ __forceinline__ float gelu_prime_as(float x) {
+  const ErfTail r = erf_tail(x);
+  const float cdf = x >= 0.0f ? fmaf(-0.5f, r.c, 1.0f) : 0.5f * r.c;  // Phi(x)
+  return fmaf(x * 0.39894228040143268f, r.e, cdf);
+}
+
 // C[b][m][n] = alpha * (sum_k A[b][m][k] B[b][k][n] + seg2) (+ bias[m]) (+ res[b][m][n])
 //              (+ C if beta), then times GELU'(gz[b][m][n]) if gz;
 // stored at C (BF16 or FP32) if C is set; if act, GELU of the value is also stored

@@ -77,6 +77,7 @@ def test_null_context_is_rejected():
     (32, 32, 0, 3, 16, 4, 2, 32, 2),      # no input channels
     (32, 32, 4, 3, 16, 4, 0, 32, 2),      # no layers
     (32, 32, 4, 3, 16, 4, 2, 32, 0),      # no batch
+    (32, 32, 4, 3, 65, 4, 2, 32, 2),      # width beyond 64
     (8192, 8192, 4, 3, 64, 12, 4, 128, 4),  # activations beyond 2^31 elements
 ])
 def test_surrogate_create_rejects_bad_sizes_before_touching_the_device(args):

@@ -7,6 +7,9 @@ exactly: after s steps an amplitude depends only on inputs within 4 s cells alon
 each axis (U_x and U_y each reach 4 cells, the potentials 1 for n), so the oracle
 run on a periodic window is exact more than 4 s + 1 cells inside its edges.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -200,22 +203,34 @@ def test_parity_full_size_4096_windows(qla, prec):
     assert _window_parity(qla, w, prec, 20, centres, seed=42) <= TOL[prec]
 
 
-# The benchmark's tuning of the 4096^2 ellipse job (rows per segment, prefetch rows,
-# steps per pass, columns per lane), as recorded with its hardware counters.
-BENCH_TUNING_4096 = {0: (176, 3, 2, 1), 1: (56, 2, 2, 2)}
+# The benchmark's tunings (rows per segment, prefetch rows, steps per pass, columns per
+# lane): the ones recorded with the step kernel's hardware counters, which bench.py runs.
+PROFILES = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles")
+
+
+def _bench_tuning(name, prec):
+    with open(os.path.join(PROFILES, name)) as f:
+        rec = json.load(f)
+    key = "f64" if prec == 0 else "f32"
+    for r in rec["records"]:
+        if r["precision"] == key and r["potential"] == "skew_half":
+            t = tuple(r["tuning"])
+            return t if len(t) == 4 else t + (1,)
+    raise KeyError((name, key))
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_parity_4096_job_first_50_steps_at_the_bench_tuning(qla, prec):
-    """The 4096^2 ellipse job as the benchmark runs it: the packet initialised on the
-    GPU, the recorded tuning set explicitly, 50 steps (the span its oracle timing
-    covers). Checked on windows across the packet and at periodic seams against the
-    oracle's own packet advanced 50 steps; then random fields at the same tuning, on
-    windows at the ellipse's strongest gradients, where the packet has not yet arrived."""
-    w = workloads.plain_4096()
+@pytest.mark.parametrize("which", ["4096_ellipse", "8192_bubble"])
+def test_parity_job_first_50_steps_at_the_bench_tuning(qla, prec, which):
+    """A benchmark job as bench.py runs it: the packet initialised on the GPU, the recorded
+    tuning set explicitly, 50 steps. Checked on windows across the packet and at periodic
+    seams against the oracle's own packet advanced 50 steps; then random fields at the same
+    tuning, on windows at the medium's strongest gradients, where the packet has not yet
+    arrived."""
+    w = workloads.plain_4096() if which == "4096_ellipse" else workloads.bubble_8192()
     steps = 50
     n = workloads.ellipse_index(w.nx, w.ny, w.ellipse)
-    rows, pf, ts, cols = BENCH_TUNING_4096[prec]
+    rows, pf, ts, cols = _bench_tuning(f"qla_step_ez_{which}.json", prec)
     margin = 4 * steps + 2
     half = margin + 12
 
@@ -240,14 +255,16 @@ def test_parity_4096_job_first_50_steps_at_the_bench_tuning(qla, prec):
             out = oracle.advance(qw, nw, w.delta, steps)[2:5]
             inner = slice(margin, 2 * half + 1 - margin)
             err = rel_l2(got[:, ys[inner]][:, :, xs[inner]], out[:, inner, inner])
-            print(f"4096 job {tag} prec={prec} window=({cx},{cy}) rel_l2={err:.3e}", flush=True)
+            print(f"{w.name} {tag} prec={prec} tuning={(rows, pf, ts, cols)} "
+                  f"window=({cx},{cy}) rel_l2={err:.3e}", flush=True)
             worst = max(worst, err)
         return worst
 
     got = run(lambda lat: lat.init_packet(w.packet))
     q0 = oracle.packet_from(n, w.packet)
     x0 = int(w.packet.x0)
-    band = [(x0, 100), (x0 - 150, 2048), (x0 + 170, 4000), (x0, 0), (x0 + 60, 4095)]
+    band = [(x0, 100), (x0 - 150, w.ny // 2), (x0 + 170, w.ny - 96), (x0, 0),
+            (x0 + 60, w.ny - 1)]
     assert windows(got, q0, band, "packet") <= TOL[prec]
     del q0
     q = _random_fields((w.ny, w.nx), seed=50 + prec)
