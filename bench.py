@@ -714,8 +714,8 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
     name fragment, algorithmic flops, algorithmic HBM bytes). Bytes count one read of each
     input tensor and one write of each output tensor an op needs (BF16 activations, FP32
     spectra, losses and outputs); flops count multiply-adds as two. Inference runs the fused
-    projection; training keeps the first projection GEMM, the pre-activations, and runs the
-    narrow second projection (3 output channels) and its input gradient on the vector
+    projection; training keeps the first projection GEMM and the pre-activations, and runs
+    the narrow second projection (3 output channels) and its input gradient on the vector
     units."""
     P = H * W
     act = C * P * 2                     # one BF16 activation tensor

@@ -399,9 +399,28 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
     afr[f] = *reinterpret_cast<const bf16x8_t*>(wl + (32 * wm + hl) * kMixC + 16 * f + kh);
   const int per_row = W / kMixPix;
   const long long tiles = static_cast<long long>(B) * H * per_row;
+  // The grid is a multiple of per_row (the launch makes it so), so all of this block's
+  // tiles start at the same column x0: its 256 columns of the inverse x basis go into LDS
+  // once.
+  {
+    const int x0 = static_cast<int>(blockIdx.x % per_row) * kMixPix;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = it * 256 + t, j = idx >> 5, seg = idx & 31;
+      const uint4 q = j < m2 ? *reinterpret_cast<const uint4*>(IX + static_cast<long long>(j) * W + x0 + seg * 8)
+                             : uint4{0, 0, 0, 0};
+      uint16_t e[8];
+      __builtin_memcpy(e, &q, 16);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = seg * 8 + i;
+        xs[r][mix_col32(r, j)] = e[i];
+      }
+    }
+  }
   // loads of one tile: 8 x 16 bytes of v per thread (channel idx >> 5, pixels
-  // (idx & 31) * 8 ..), up to 4 x 16 bytes of IX
-  uint4 rv[8], rx[4];
+  // (idx & 31) * 8 ..)
+  uint4 rv[8];
   auto load_tile = [&](long long tile) {
     const int b = static_cast<int>(tile / (static_cast<long long>(H) * per_row));
     const long long rem = tile % (static_cast<long long>(H) * per_row);
@@ -411,12 +430,6 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
     for (int it = 0; it < 8; ++it) {
       const int idx = it * 256 + t, c = idx >> 5, seg = idx & 31;
       rv[it] = *reinterpret_cast<const uint4*>(vb + c * P + seg * 8);
-    }
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int idx = it * 256 + t, j = idx >> 5, seg = idx & 31;
-      rx[it] = j < m2 ? *reinterpret_cast<const uint4*>(IX + static_cast<long long>(j) * W + x0 + seg * 8)
-                      : uint4{0, 0, 0, 0};
     }
   };
   long long tile = blockIdx.x;
@@ -448,17 +461,6 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
       for (int i = 0; i < 8; ++i) {
         const int r = seg * 8 + i;
         vs[r * (kMixC + 8) + mix_col64(r, c)] = e[i];
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int idx = it * 256 + t, j = idx >> 5, seg = idx & 31;
-      uint16_t e[8];
-      __builtin_memcpy(e, &rx[it], 16);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int r = seg * 8 + i;
-        xs[r][mix_col32(r, j)] = e[i];
       }
     }
     __syncthreads();
@@ -1118,8 +1120,12 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
     }
     // pointwise + spectral + bias, then GELU (not after the last layer)
     if (f->fused && C == kMixC && W % kMixPix == 0 && 2 * m <= kMixMaxJ) {
-      const long long tiles = static_cast<long long>(B) * H * (W / kMixPix);
-      const dim3 grid(static_cast<unsigned>(tiles < 1024 ? tiles : 1024));
+      // a multiple of the tiles per grid row, so every block keeps one column range (and
+      // its slice of the inverse x basis) for all its tiles
+      const long long per_row = W / kMixPix;
+      const long long tiles = static_cast<long long>(B) * H * per_row;
+      const long long nb = tiles < 1024 ? tiles : 1024;
+      const dim3 grid(static_cast<unsigned>(nb >= per_row ? nb / per_row * per_row : per_row));
       const bool last = l + 1 == f->L;
       uint16_t* zo = last ? f->v[l + 1] : (training ? f->z[l] : nullptr);
       uint16_t* ao = last ? nullptr : f->v[l + 1];
