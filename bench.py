@@ -722,12 +722,21 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
     zx = C * H * 2 * m * 2              # x-transformed rows (BF16, re/im interleaved)
     spec = C * 4 * m * m * 4            # kept modes, FP32 (T, S, dT, dS)
     ops = [("lift", "lift_kernel", 2 * C * Cin * P, Cin * P * 2 + act)]
+    # one-pass x and y transforms (Z stays on chip) on grids of a multiple of 32 rows of a
+    # multiple of 128 cells up to 512, with at most 16 modes
+    one_pass = H % 32 == 0 and W % 128 == 0 and W <= 512 and 1 <= m <= 16
     for l in range(L):
         last = l + 1 == L
-        ops += [(f"L{l} x transform", "gemm_kernel", 2 * C * H * 2 * m * W, act + zx),
-                (f"L{l} y transform (re)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + spec),
-                (f"L{l} y transform (im)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + 2 * spec),
-                (f"L{l} mode mixing", "mix_forward_kernel", 8 * C * C * 2 * m * m,
+        if one_pass:
+            ops += [(f"L{l} x and y transforms", "spectral_in_kernel",
+                     2 * C * H * 2 * m * W + 2 * 2 * C * 4 * m * m * H, act + spec)]
+        else:
+            ops += [(f"L{l} x transform", "gemm_kernel", 2 * C * H * 2 * m * W, act + zx),
+                    (f"L{l} y transform (re)", "gemm_kernel", 2 * C * 4 * m * m * H,
+                     zx // 2 + spec),
+                    (f"L{l} y transform (im)", "gemm_kernel", 2 * C * 4 * m * m * H,
+                     zx // 2 + 2 * spec)]
+        ops += [(f"L{l} mode mixing", "mix_forward_kernel", 8 * C * C * 2 * m * m,
                  spec + 2 * C * C * 2 * m * m * 4 + spec // 2),
                 (f"L{l} inverse y (re)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
                 (f"L{l} inverse y (im)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),

@@ -235,6 +235,8 @@ constexpr int kProjPix = 64, kProjK = 32, kProjMaxC = 64, kProjMaxC2 = 128, kPro
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // GELU in the fused kernels: the Abramowitz & Stegun form of fno_internal.h (with the
 // library erff the GELUs were half of the projection kernel's time: every hidden value
@@ -511,6 +513,212 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
       }
     }
   }
+}
+
+// The x and y transforms of a Fourier layer in one pass over v (grids of rows a multiple
+// of 32 cells, widths a multiple of 128 up to 512 cells, m <= 16 modes):
+//   T[(b,c)][r][kx] = sum_y A1[r][y] Z[y][2kx] + A2[r][y] Z[y][2kx+1],
+//   Z[y][j]         = sum_x v[(b,c)][y][x] Fx[x][j],
+// with Z rounded to BF16 as the separate transforms store it, but never written to
+// memory. One block of 8 waves per plane (b, c) walks the plane in tiles of 32 whole
+// rows, a contiguous 32 W x 2 bytes of memory read 1 KB per wave load instruction; the
+// next tile is in flight while one is worked on. A tile goes through LDS; wave w
+// multiplies its 64-column slices (w, w + 8, ...) with the matching slices of the
+// transposed basis FxT (2m rows, held in LDS for the block) on the matrix cores (32 x 32 x 16 BF16 products, FP32 accumulation), so each
+// wave holds part of the tile's 32 x 2m product Z. The 8 parts meet in LDS (FP32, summed
+// in wave order, then rounded to BF16), and each wave takes one 32 x 32 x 16 product of
+// the y transform: rows 32 (w % 2) .. of T, tile rows 16 ((w / 2) % 2) .., and the real
+// (w < 4: A1 with Z's columns 2kx) or imaginary part (A2 with columns 2kx + 1), with the
+// tile's 32 columns of A1 and A2 staged in LDS beside it. At the end the 8 waves' parts of
+// T are summed in a fixed order.
+constexpr int kSpecCols = 32;   // Z columns: 2m <= 32
+constexpr int kSpecRows = 64;   // T rows: 4m <= 64
+constexpr int kSpecMaxW = 512;
+constexpr int kSpecWaves = 8;
+constexpr int kSpecZp = 36;     // column pitch (floats) of the FP32 parts of Z in LDS
+
+struct SpecLds {
+  int basis, tile, zred, aslc, total;  // byte offsets and size
+};
+
+__host__ __device__ inline SpecLds spec_lds_layout(int W, int m) {
+  SpecLds L;
+  const int ld = W + 8;
+  L.basis = 0;
+  L.tile = (2 * m * ld * 2 + 15) / 16 * 16;
+  const int tile_bytes = 32 * ld * 2;
+  const int zred_bytes = kSpecWaves * 2 * m * kSpecZp * 4;
+  L.zred = L.tile;  // the FP32 parts of Z reuse the tile once it has been multiplied
+  L.aslc = L.tile + (tile_bytes > zred_bytes ? tile_bytes : zred_bytes);
+  L.total = L.aslc + 2 * 4 * m * 40 * 2;
+  const int red = kSpecWaves * 32 * 16 * 4;  // the waves' parts of T, at the end
+  if (L.total < red) L.total = red;
+  return L;
+}
+
+size_t spectral_in_lds(int W, int m) { return static_cast<size_t>(spec_lds_layout(W, m).total); }
+
+bool spectral_in_fits(int H, int W, int m) {
+  return H % 32 == 0 && W % 128 == 0 && W <= kSpecMaxW && m >= 1 && 2 * m <= kSpecCols &&
+         4 * m <= kSpecRows;
+}
+
+template <int NU>
+__global__ __launch_bounds__(64 * kSpecWaves, 4) void spectral_in_kernel(
+    const uint16_t* __restrict__ v, long long sample_stride, long long plane_stride,
+    int planes_per_sample, const uint16_t* __restrict__ fxt, const uint16_t* __restrict__ a1,
+    const uint16_t* __restrict__ a2, int H, int W, int m, float* __restrict__ T) {
+  extern __shared__ __attribute__((aligned(16))) char spec_smem[];
+  constexpr int kThreads = 64 * kSpecWaves;
+  const SpecLds L = spec_lds_layout(W, m);
+  uint16_t* basis = reinterpret_cast<uint16_t*>(spec_smem + L.basis);  // [2m][W + 8]
+  uint16_t* tile = reinterpret_cast<uint16_t*>(spec_smem + L.tile);    // [32][W + 8]
+  float* zred = reinterpret_cast<float*>(spec_smem + L.zred);          // [wave][2m][36]
+  uint16_t* aslc = reinterpret_cast<uint16_t*>(spec_smem + L.aslc);    // [part][4m][40]
+  const int ld = W + 8;
+  const int t = threadIdx.x, lane = t & 63, l32 = lane & 31, h = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
+  const int m2 = 2 * m, r4 = 4 * m, segs = W / 8;
+  // the basis: at most 2m W / 8 / 512 <= 4 pieces of 16 bytes per thread (loads issued
+  // for all four, past the end a spare copy of the last, so their count is fixed)
+  constexpr int kBasisPieces = 4;
+  const int nbp = m2 * segs;
+  u32x4_t bv[kBasisPieces];
+#pragma unroll
+  for (int i = 0; i < kBasisPieces; ++i) {
+    const int idx = min(t + i * kThreads, nbp - 1);
+    bv[i] = *reinterpret_cast<const u32x4_t*>(fxt + static_cast<long long>(idx / segs) * W +
+                                              (idx % segs) * 8);
+  }
+  const int b = blockIdx.x / planes_per_sample, c = blockIdx.x % planes_per_sample;
+  const uint16_t* plane = v + b * sample_stride + c * plane_stride;
+  const int tiles = H / 32;
+  // this thread's share of loading a tile: the 16-byte pieces u 512 + t (u < W / 128) of
+  // the tile's 32 W / 8 (a wave's load instruction reads 1 KB of consecutive rows), and,
+  // for t < 2 * 4m * 4, the 16-byte piece of A1 or A2 at part t / 16m, row (t / 4) % 4m,
+  // columns 8 (t % 4) .. of the tile's 32
+  constexpr int nu = NU;  // W / 128
+  int prow[NU], pcol[NU];
+#pragma unroll
+  for (int u = 0; u < nu; ++u) {
+    prow[u] = (u * kThreads + t) / segs;
+    pcol[u] = (u * kThreads + t) % segs * 8;
+  }
+  const bool has_a = t < 2 * r4 * 4;
+  const int a_part = t / (4 * r4), a_row = (t / 4) % r4, a_col = 8 * (t % 4);
+  const uint16_t* a_src = (a_part ? a2 : a1) + static_cast<long long>(has_a ? a_row : 0) * H + a_col;
+  auto load = [&](u32x4_t(&rv)[NU], u32x4_t& av, int tl) {
+    const uint16_t* p = plane + static_cast<long long>(tl) * 32 * W;
+#pragma unroll
+    for (int u = 0; u < nu; ++u)
+      rv[u] = *reinterpret_cast<const u32x4_t*>(p + static_cast<long long>(prow[u]) * W + pcol[u]);
+    av = *reinterpret_cast<const u32x4_t*>(a_src + tl * 32);  // (a spare copy if !has_a)
+  };
+  // wave w's share of the y transform: T rows 32 rt .., tile rows 16q .. (k slot 8h + i
+  // is tile row 16q + 8h + i), real (part 0: A1, Z column 2kx) or imaginary (part 1: A2,
+  // Z column 2kx + 1) contributions
+  const int rt = w & 1, q = (w >> 1) & 1, part = w >> 2;
+  const int zcol = l32 < m ? 2 * l32 + part : 0;  // columns kx >= m are not kept
+  const int ar = rt * 32 + l32;
+  const bool a_ok = ar < r4;
+  f32x16_t acc = {};
+  auto work = [&](const u32x4_t(&rv)[NU], const u32x4_t& av) {
+    __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+    for (int u = 0; u < nu; ++u) *reinterpret_cast<u32x4_t*>(tile + prow[u] * ld + pcol[u]) = rv[u];
+    if (has_a) *reinterpret_cast<u32x4_t*>(aslc + (a_part * r4 + a_row) * 40 + a_col) = av;
+    __syncthreads();
+    // x transform over this wave's 64-column slices
+    f32x16_t z = {};
+    for (int cs = w; cs < W / 64; cs += kSpecWaves) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 64 * cs + 16 * s + 8 * h;
+        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(tile + l32 * ld + k);
+        bf16x8_t fb = *reinterpret_cast<const bf16x8_t*>(basis + (l32 < m2 ? l32 : 0) * ld + k);
+        if (l32 >= m2) fb = bf16x8_t{};
+        z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, fb, z, 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave has read the tile: its bytes now hold the parts of Z
+    // this wave's part of Z: column j = l32 (< 2m), rows 8i + 4h .. 8i + 4h + 3
+    if (l32 < m2) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const f32x4_t zz = {z[4 * i], z[4 * i + 1], z[4 * i + 2], z[4 * i + 3]};
+        *reinterpret_cast<f32x4_t*>(zred + (w * m2 + l32) * kSpecZp + 8 * i + 4 * h) = zz;
+      }
+    }
+    __syncthreads();
+    // the y-transform product: Z column zcol, tile rows 16q + 8h .. + 7, summed over the
+    // parts in wave order and rounded to BF16; A rows ar, the same tile rows
+    f32x4_t lo = {}, hi = {};
+#pragma unroll 2
+    for (int ww = 0; ww < kSpecWaves; ++ww) {
+      const float* zp = zred + (ww * m2 + zcol) * kSpecZp + 16 * q + 8 * h;
+      lo += *reinterpret_cast<const f32x4_t*>(zp);
+      hi += *reinterpret_cast<const f32x4_t*>(zp + 4);
+    }
+    uint16_t e[8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      e[i] = f32_to_bf16(lo[i]);
+      e[4 + i] = f32_to_bf16(hi[i]);
+    }
+    bf16x8_t af = bf16x8_t{};
+    if (a_ok) af = *reinterpret_cast<const bf16x8_t*>(aslc + (part * r4 + ar) * 40 + 16 * q + 8 * h);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, __builtin_bit_cast(bf16x8_t, e), acc, 0, 0, 0);
+  };
+  // tiles in flight: the one being worked on and the next, in fixed registers. Every
+  // trip issues the same loads (past the last tile, the last one again), so the waits
+  // before a tile's LDS writes leave the next tile's loads in flight.
+  u32x4_t r0[NU], r1[NU], q0, q1;
+  load(r0, q0, 0);
+#pragma unroll
+  for (int i = 0; i < kBasisPieces; ++i) {
+    const int idx = t + i * kThreads;
+    if (idx < nbp) *reinterpret_cast<u32x4_t*>(basis + (idx / segs) * ld + (idx % segs) * 8) = bv[i];
+  }
+  for (int tl = 0; tl < tiles; tl += 2) {
+    load(r1, q1, tl + 1 < tiles ? tl + 1 : tiles - 1);
+    work(r0, q0);
+    if (tl + 1 >= tiles) break;
+    load(r0, q0, tl + 2 < tiles ? tl + 2 : tiles - 1);
+    work(r1, q1);
+  }
+  // T = the sum of the waves' parts, in wave order: wave w holds rows 32 (w % 2) + 8i +
+  // 4h + j, column kx = l32
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(spec_smem);  // [wave][32][16]
+  if (l32 < 16) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[(w * 32 + 8 * i + 4 * h + j) * 16 + l32] = acc[4 * i + j];
+  }
+  __syncthreads();
+  float* Tb = T + static_cast<long long>(blockIdx.x) * r4 * m;
+  for (int idx = t; idx < r4 * m; idx += kThreads) {
+    const int r = idx / m, kx = idx % m, hr = r >> 5, rr = r & 31;
+    float sum = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < kSpecWaves; ww += 2) sum += red[((ww + hr) * 32 + rr) * 16 + kx];
+    Tb[idx] = sum;
+  }
+}
+
+hipError_t launch_spectral_in(const uint16_t* v, long long sample_stride, long long plane_stride,
+                              int planes_per_sample, int planes, const uint16_t* fxt,
+                              const uint16_t* a1, const uint16_t* a2, int H, int W, int m,
+                              float* T, hipStream_t stream) {
+  using Kernel = void (*)(const uint16_t*, long long, long long, int, const uint16_t*,
+                          const uint16_t*, const uint16_t*, int, int, int, float*);
+  static const Kernel table[4] = {spectral_in_kernel<1>, spectral_in_kernel<2>,
+                                  spectral_in_kernel<3>, spectral_in_kernel<4>};
+  hipLaunchKernelGGL(table[W / 128 - 1], dim3(static_cast<unsigned>(planes)),
+                     dim3(64 * kSpecWaves), spectral_in_lds(W, m), stream, v, sample_stride,
+                     plane_stride, planes_per_sample, fxt, a1, a2, H, W, m, T);
+  return hipGetLastError();
 }
 
 // Mode mixing of a Fourier layer and its two backward products. Spectra are
@@ -821,8 +1029,8 @@ struct qla_fno {
   size_t nweights16 = 0;  // BF16 copies: Wp | W_0..W_{L-1} | Q1 | Q2
   float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
   uint16_t* w16 = nullptr;
-  uint16_t *Fx = nullptr, *A1 = nullptr, *A2 = nullptr, *IY1 = nullptr, *IY2 = nullptr,
-           *IX = nullptr;
+  uint16_t *Fx = nullptr, *FxT = nullptr, *A1 = nullptr, *A2 = nullptr, *IY1 = nullptr,
+           *IY2 = nullptr, *IX = nullptr;
   // activations (batch Bmax)
   std::vector<uint16_t*> v, z;
   uint16_t *Zb = nullptr, *Sb = nullptr, *Ub = nullptr, *zq = nullptr, *h = nullptr,
@@ -911,7 +1119,11 @@ qla_status make_bases(qla_fno* f) {
       IY2[size_t(y) * 4 * m + 2 * kyi + 1] = c;   // U_im from S_im
     }
   }
+  std::vector<double> FxT(size_t(2 * m) * W);  // Fx transposed: [2kx+p][x]
+  for (int x = 0; x < W; ++x)
+    for (int j = 0; j < 2 * m; ++j) FxT[size_t(j) * W + x] = Fx[size_t(x) * 2 * m + j];
   qla_status st = upload16(f, &f->Fx, Fx);
+  if (st == QLA_OK) st = upload16(f, &f->FxT, FxT);
   if (st == QLA_OK) st = upload16(f, &f->IX, IX);
   if (st == QLA_OK) st = upload16(f, &f->A1, A1);
   if (st == QLA_OK) st = upload16(f, &f->A2, A2);
@@ -1038,44 +1250,50 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
   }
   for (int l = 0; l < f->L; ++l) {
     const uint16_t* vl = f->v[l];
-    // x transform: Z[(b,c,y)][2kx+p]
-    {
-      GemmDesc g;
-      g.A = vl;
-      g.sAm = W;
-      g.sAk = 1;
-      g.B = f->Fx;
-      g.sBk = 2 * m;
-      g.sBn = 1;
-      g.C = f->Zb;
-      g.sCm = 2 * m;
-      g.sCn = 1;
-      g.M = B * C * H;
-      g.N = 2 * m;
-      g.K = W;
-      g.out_bf16 = 1;
-      QLA_GEMM(g);
-    }
-    // y transform: T[(b,c)] = A1 Zre + A2 Zim
-    for (int part = 0; part < 2; ++part) {
-      GemmDesc g;
-      g.A = part ? f->A2 : f->A1;
-      g.sAm = H;
-      g.sAk = 1;
-      g.B = f->Zb + part;
-      g.sBb = static_cast<long long>(H) * 2 * m;
-      g.sBk = 2 * m;
-      g.sBn = 2;
-      g.C = f->T[l];
-      g.sCb = modes_sz;
-      g.sCm = m;
-      g.sCn = 1;
-      g.M = 4 * m;
-      g.N = m;
-      g.K = H;
-      g.batch = B * C;
-      g.beta = part;
-      QLA_GEMM(g);
+    if (spectral_in_fits(H, W, m)) {
+      // x and y transforms in one pass: T[l] straight from v
+      QLA_HIP(launch_spectral_in(vl, static_cast<long long>(C) * P, static_cast<long long>(P), C,
+                                 B * C, f->FxT, f->A1, f->A2, H, W, m, f->T[l], f->stream));
+    } else {
+      // x transform: Z[(b,c,y)][2kx+p]
+      {
+        GemmDesc g;
+        g.A = vl;
+        g.sAm = W;
+        g.sAk = 1;
+        g.B = f->Fx;
+        g.sBk = 2 * m;
+        g.sBn = 1;
+        g.C = f->Zb;
+        g.sCm = 2 * m;
+        g.sCn = 1;
+        g.M = B * C * H;
+        g.N = 2 * m;
+        g.K = W;
+        g.out_bf16 = 1;
+        QLA_GEMM(g);
+      }
+      // y transform: T[(b,c)] = A1 Zre + A2 Zim
+      for (int part = 0; part < 2; ++part) {
+        GemmDesc g;
+        g.A = part ? f->A2 : f->A1;
+        g.sAm = H;
+        g.sAk = 1;
+        g.B = f->Zb + part;
+        g.sBb = static_cast<long long>(H) * 2 * m;
+        g.sBk = 2 * m;
+        g.sBn = 2;
+        g.C = f->T[l];
+        g.sCb = modes_sz;
+        g.sCm = m;
+        g.sCn = 1;
+        g.M = 4 * m;
+        g.N = m;
+        g.K = H;
+        g.batch = B * C;
+        g.beta = part;
+        QLA_GEMM(g);
+      }
     }
     hipLaunchKernelGGL(mix_forward_kernel, dim3(2 * m * m), dim3(256), 0, f->stream, f->T[l],
                        f->p + f->o_R[l], f->Sb, B, C, m);
@@ -1612,45 +1830,52 @@ qla_status qla_fno_band_fraction(qla_fno* f, const uint16_t* input, int batch, i
   const size_t P = f->P;
   // the truncated transforms of a Fourier layer, applied to the chosen input planes,
   // into the forward pass's transform scratch (every forward pass rewrites it)
-  {
-    GemmDesc g;
-    g.A = input + size_t(first_channel) * P;
-    g.sAb = static_cast<long long>(f->Cin) * P;
-    g.sAm = W;
-    g.sAk = 1;
-    g.B = f->Fx;
-    g.sBk = 2 * m;
-    g.sBn = 1;
-    g.C = f->Zb;
-    g.sCb = static_cast<long long>(channels) * H * 2 * m;
-    g.sCm = 2 * m;
-    g.sCn = 1;
-    g.M = channels * H;
-    g.N = 2 * m;
-    g.K = W;
-    g.batch = batch;
-    g.out_bf16 = 1;
-    QLA_GEMM(g);
-  }
-  for (int part = 0; part < 2; ++part) {
-    GemmDesc g;
-    g.A = part ? f->A2 : f->A1;
-    g.sAm = H;
-    g.sAk = 1;
-    g.B = f->Zb + part;
-    g.sBb = static_cast<long long>(H) * 2 * m;
-    g.sBk = 2 * m;
-    g.sBn = 2;
-    g.C = f->T[0];
-    g.sCb = 4LL * m * m;
-    g.sCm = m;
-    g.sCn = 1;
-    g.M = 4 * m;
-    g.N = m;
-    g.K = H;
-    g.batch = batch * channels;
-    g.beta = part;
-    QLA_GEMM(g);
+  const uint16_t* planes = input + size_t(first_channel) * P;
+  if (spectral_in_fits(H, W, m) && (reinterpret_cast<uintptr_t>(planes) & 15) == 0) {
+    QLA_HIP(launch_spectral_in(planes, static_cast<long long>(f->Cin) * P,
+                               static_cast<long long>(P), channels, batch * channels, f->FxT,
+                               f->A1, f->A2, H, W, m, f->T[0], f->stream));
+  } else {
+    {
+      GemmDesc g;
+      g.A = input + size_t(first_channel) * P;
+      g.sAb = static_cast<long long>(f->Cin) * P;
+      g.sAm = W;
+      g.sAk = 1;
+      g.B = f->Fx;
+      g.sBk = 2 * m;
+      g.sBn = 1;
+      g.C = f->Zb;
+      g.sCb = static_cast<long long>(channels) * H * 2 * m;
+      g.sCm = 2 * m;
+      g.sCn = 1;
+      g.M = channels * H;
+      g.N = 2 * m;
+      g.K = W;
+      g.batch = batch;
+      g.out_bf16 = 1;
+      QLA_GEMM(g);
+    }
+    for (int part = 0; part < 2; ++part) {
+      GemmDesc g;
+      g.A = part ? f->A2 : f->A1;
+      g.sAm = H;
+      g.sAk = 1;
+      g.B = f->Zb + part;
+      g.sBb = static_cast<long long>(H) * 2 * m;
+      g.sBk = 2 * m;
+      g.sBn = 2;
+      g.C = f->T[0];
+      g.sCb = 4LL * m * m;
+      g.sCm = m;
+      g.sCn = 1;
+      g.M = 4 * m;
+      g.N = m;
+      g.K = H;
+      g.batch = batch * channels;
+      g.beta = part;
+      QLA_GEMM(g);
+    }
   }
   QLA_HIP(hipMemsetAsync(f->band, 0, 2 * batch * sizeof(double), f->stream));
   hipLaunchKernelGGL(band_sums_kernel, dim3(64, batch), dim3(kBlock), 0, f->stream, f->T[0],

@@ -127,13 +127,17 @@ def gpu_forward(qla, net, u_bits, B):
 
 # "fused": rows a multiple of 64 cells, where the inverse x transform runs inside the
 # channel-mixing GEMM; "small" and "ragged" take the separate path; "mix256" (width 64,
-# rows of 256 cells) runs the dedicated layer kernel.
+# rows of 256 cells) runs the dedicated layer kernel; "spectral" (a multiple of 32 rows
+# of a multiple of 128 cells, 16 modes: every row and column of the tiles in use) runs
+# the one-pass x and y transform kernel, as do "full" and the 512^2 and 64 x 256 band
+# fraction cases.
 SPECS = {
     "small": fno.Spec(H=40, W=72, cin=4, cout=3, C=16, m=6, L=3, C2=24),
     "ragged": fno.Spec(H=33, W=70, cin=4, cout=3, C=10, m=5, L=2, C2=70),
     "fused": fno.Spec(H=24, W=128, cin=4, cout=3, C=16, m=7, L=3, C2=40),
     # width 64 on rows of 256 cells: the layers run the 256-pixel mixing kernel
     "mix256": fno.Spec(H=16, W=256, cin=4, cout=3, C=64, m=6, L=2, C2=40),
+    "spectral": fno.Spec(H=96, W=384, cin=4, cout=3, C=16, m=16, L=2, C2=40),
 }
 
 
@@ -355,6 +359,7 @@ def _band_inputs(H, W, cin, m, seed):
 
 @pytest.mark.parametrize("H,W,m,first,channels", [
     (512, 512, 12, 1, 3),     # the surrogate's grid and the packet planes (q2, q3, q4)
+    (64, 256, 9, 1, 3),       # the one-pass transform kernel at two row pieces per thread
     (40, 24, 5, 1, 3),        # ragged: rows and columns not multiples of the GEMM tiles
     (40, 24, 5, 0, 4),        # every input plane
 ])
