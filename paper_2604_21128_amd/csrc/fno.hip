@@ -382,43 +382,69 @@ __device__ __forceinline__ int mix_col32(int r, int k) {
   return ((((k >> 3) ^ (r >> 3)) & 3) << 3) | (k & 7);
 }
 
+// kBack = false: the forward layer above. kBack = true: its input-gradient product with
+// the same tiling, roles and operands in the same places,
+//   out[b][c][p] = (sum_o Wl[o][c] dz[b][o][p] + sum_j dZ[b][c][y][j] Fx[x][j]) GELU'(gz)
+// (v = dz, U = dZ, the LDS basis slice Fx instead of IX, no bias; without gz the factor is
+// 1), the sums staged in LDS in FP32 (32 rows at a time) so the factor multiplies the
+// FP32 value, as the GEMM epilogue does.
+template <bool kBack>
 __global__ __launch_bounds__(256) void layer_mix_kernel(
     const uint16_t* __restrict__ v, const uint16_t* __restrict__ wl,
     const float* __restrict__ bias, const uint16_t* __restrict__ U,
     const uint16_t* __restrict__ IX, int m2, int H, int W, int B,
-    uint16_t* __restrict__ zout, uint16_t* __restrict__ aout) {
+    uint16_t* __restrict__ zout, uint16_t* __restrict__ aout, const uint16_t* __restrict__ gz) {
   // v tile [pixel][channel]; after the products the same bytes stage the output rows
   __shared__ __attribute__((aligned(16))) uint16_t vs[kMixPix * (kMixC + 8)];
   __shared__ __attribute__((aligned(16))) uint16_t xs[kMixPix][kMixMaxJ + 8];
   __shared__ float sbias[kMixC];
   uint16_t(*ost)[kMixPix + 8] = reinterpret_cast<uint16_t(*)[kMixPix + 8]>(vs);
+  float(*fst)[kMixPix + 4] = reinterpret_cast<float(*)[kMixPix + 4]>(vs);  // 32 rows, FP32
+  static_assert(sizeof(float) * 32 * (kMixPix + 4) <= sizeof(uint16_t) * kMixPix * (kMixC + 8),
+                "half the FP32 output rows fit where the tile was");
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
   const int hl = lane & 31, kh = 8 * (lane >> 5);
   const long long P = static_cast<long long>(H) * W;
-  if (t < kMixC) sbias[t] = bias[t];
-  // Wl fragments: row 32 wm + hl, channels 16 f + kh .. + 7
+  if (!kBack && t < kMixC) sbias[t] = bias[t];
+  // weight fragments: row 32 wm + hl, k = 16 f + kh .. + 7 of Wl (forward: Wl[row][k]) or
+  // of Wl^T (Wl[k][row])
   bf16x8_t afr[kMixC / 16];
 #pragma unroll
-  for (int f = 0; f < kMixC / 16; ++f)
-    afr[f] = *reinterpret_cast<const bf16x8_t*>(wl + (32 * wm + hl) * kMixC + 16 * f + kh);
+  for (int f = 0; f < kMixC / 16; ++f) {
+    if constexpr (kBack) {
+      uint16_t e[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) e[i] = wl[(16 * f + kh + i) * kMixC + 32 * wm + hl];
+      afr[f] = __builtin_bit_cast(bf16x8_t, e);
+    } else {
+      afr[f] = *reinterpret_cast<const bf16x8_t*>(wl + (32 * wm + hl) * kMixC + 16 * f + kh);
+    }
+  }
   const int per_row = W / kMixPix;
   const long long tiles = static_cast<long long>(B) * H * per_row;
   // The grid is a multiple of per_row (the launch makes it so), so all of this block's
-  // tiles start at the same column x0: its 256 columns of the inverse x basis go into LDS
-  // once.
+  // tiles start at the same column x0: its 256 columns of the x basis (IX[j][x], or
+  // Fx[x][j] backward) go into LDS once.
   {
     const int x0 = static_cast<int>(blockIdx.x % per_row) * kMixPix;
+    if constexpr (kBack) {
+      for (int idx = t; idx < kMixPix * kMixMaxJ; idx += 256) {
+        const int r = idx / kMixMaxJ, j = idx % kMixMaxJ;
+        xs[r][mix_col32(r, j)] = j < m2 ? IX[static_cast<long long>(x0 + r) * m2 + j] : uint16_t(0);
+      }
+    } else {
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int idx = it * 256 + t, j = idx >> 5, seg = idx & 31;
-      const uint4 q = j < m2 ? *reinterpret_cast<const uint4*>(IX + static_cast<long long>(j) * W + x0 + seg * 8)
-                             : uint4{0, 0, 0, 0};
-      uint16_t e[8];
-      __builtin_memcpy(e, &q, 16);
+      for (int it = 0; it < 4; ++it) {
+        const int idx = it * 256 + t, j = idx >> 5, seg = idx & 31;
+        const uint4 q = j < m2 ? *reinterpret_cast<const uint4*>(IX + static_cast<long long>(j) * W + x0 + seg * 8)
+                               : uint4{0, 0, 0, 0};
+        uint16_t e[8];
+        __builtin_memcpy(e, &q, 16);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int r = seg * 8 + i;
-        xs[r][mix_col32(r, j)] = e[i];
+        for (int i = 0; i < 8; ++i) {
+          const int r = seg * 8 + i;
+          xs[r][mix_col32(r, j)] = e[i];
+        }
       }
     }
   }
@@ -486,6 +512,48 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
         const bf16x8_t bb = *reinterpret_cast<const bf16x8_t*>(&xs[r][mix_col32(r, 16 * f + kh)]);
         acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[f], bb, acc[nt], 0, 0, 0);
       }
+    }
+    if constexpr (kBack) {
+      // the FP32 sums, 32 rows at a time, times GELU'(gz), stored BF16
+      uint16_t* db = zout + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0;
+      const uint16_t* gb =
+          gz ? gz + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0 : nullptr;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        __syncthreads();  // the tile (or the previous half) is no longer read
+        if (wm == half) {
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                fst[8 * i + 4 * (lane >> 5) + j][wn * 128 + nt * 32 + hl] = acc[nt][4 * i + j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int idx = it * 256 + t, rr = idx >> 5, seg = idx & 31, row = 32 * half + rr;
+          const f32x4_t lo = *reinterpret_cast<const f32x4_t*>(&fst[rr][seg * 8]);
+          const f32x4_t hi = *reinterpret_cast<const f32x4_t*>(&fst[rr][seg * 8 + 4]);
+          uint16_t gv[8];
+          if (gb) {
+            const u32x4_t q = __builtin_nontemporal_load(
+                reinterpret_cast<const u32x4_t*>(gb + row * P + seg * 8));
+            __builtin_memcpy(gv, &q, 16);
+          }
+          uint16_t e[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            float val = i < 4 ? lo[i] : hi[i - 4];
+            if (gb) val *= gelu_prime_as(bf16_to_f32(gv[i]));
+            e[i] = f32_to_bf16(val);
+          }
+          __builtin_nontemporal_store(__builtin_bit_cast(u32x4_t, e),
+                                      reinterpret_cast<u32x4_t*>(db + row * P + seg * 8));
+        }
+      }
+      continue;
     }
     // outputs: pre-activation, then GELU, each staged in LDS and stored row by row
     uint16_t* outs[2] = {zout, aout};
@@ -1462,9 +1530,9 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
       const bool last = l + 1 == f->L;
       uint16_t* zo = last ? f->v[l + 1] : (training ? f->z[l] : nullptr);
       uint16_t* ao = last ? nullptr : f->v[l + 1];
-      hipLaunchKernelGGL(layer_mix_kernel, grid, dim3(256), 0, f->stream, vl,
+      hipLaunchKernelGGL(layer_mix_kernel<false>, grid, dim3(256), 0, f->stream, vl,
                          f->w16 + f->w16_W(l), f->p + f->o_b[l], f->Ub, f->IX, 2 * m, H, W, B,
-                         zo, ao);
+                         zo, ao, nullptr);
       QLA_HIP(hipGetLastError());
     } else {
       GemmDesc g = pointwise(f->w16 + f->w16_W(l), false, C, C, vl, B, P);
@@ -1641,6 +1709,19 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
     }
     // dv_l = W_l^T dz + dZ Fx^T; dz_{l-1} = dv_l GELU'(z_{l-1}) (v_0 has no activation)
     const uint16_t* gz = l > 0 ? f->z[l - 1] : nullptr;
+    if (f->fused && C == kMixC && W % kMixPix == 0 && 2 * m <= kMixMaxJ) {
+      // the layer kernel's backward mode (same grid as forward)
+      const long long per_row = W / kMixPix;
+      const long long tiles = static_cast<long long>(B) * H * per_row;
+      const long long nb = tiles < 1024 ? tiles : 1024;
+      const dim3 grid(static_cast<unsigned>(nb >= per_row ? nb / per_row * per_row : per_row));
+      hipLaunchKernelGGL(layer_mix_kernel<true>, grid, dim3(256), 0, f->stream, dz,
+                         f->w16 + f->w16_W(l), nullptr, f->dZ, f->Fx, 2 * m, H, W, B, dz_prev,
+                         nullptr, gz);
+      QLA_HIP(hipGetLastError());
+      std::swap(dz, dz_prev);
+      continue;
+    }
     GemmDesc g = pointwise(f->w16 + f->w16_W(l), true, C, C, dz, B, P);
     if (f->fused) {
       add_forward_x_transposed(f, &g);
