@@ -725,6 +725,11 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
     # one-pass x and y transforms (Z stays on chip) on grids of a multiple of 32 rows of a
     # multiple of 128 cells up to 512, with at most 16 modes
     one_pass = H % 32 == 0 and W % 128 == 0 and W <= 512 and 1 <= m <= 16
+    # the inverse y transform (and the backward dZ) as one kernel per plane: m <= 16
+    inv_y = 1 <= m <= 16
+    # the layer kernel (forward, and the backward input gradient): width 64, rows of a
+    # multiple of 256 cells, 2m <= 32
+    layer = "layer_mix_kernel" if C == 64 and W % 256 == 0 and 2 * m <= 32 else "gemm_kernel"
     for l in range(L):
         last = l + 1 == L
         if one_pass:
@@ -737,10 +742,16 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
                     (f"L{l} y transform (im)", "gemm_kernel", 2 * C * 4 * m * m * H,
                      zx // 2 + 2 * spec)]
         ops += [(f"L{l} mode mixing", "mix_forward_kernel", 8 * C * C * 2 * m * m,
-                 spec + 2 * C * C * 2 * m * m * 4 + spec // 2),
-                (f"L{l} inverse y (re)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
-                (f"L{l} inverse y (im)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
-                (f"L{l} pointwise + inverse x + GELU", "layer_mix_kernel",
+                 spec + 2 * C * C * 2 * m * m * 4 + spec // 2)]
+        if inv_y:
+            ops += [(f"L{l} inverse y", "spectral_out_kernel", 2 * 2 * C * H * m * 4 * m,
+                     spec // 2 + zx)]
+        else:
+            ops += [(f"L{l} inverse y (re)", "gemm_kernel", 2 * C * H * m * 4 * m,
+                     spec // 2 + zx // 2),
+                    (f"L{l} inverse y (im)", "gemm_kernel", 2 * C * H * m * 4 * m,
+                     spec // 2 + zx // 2)]
+        ops += [(f"L{l} pointwise + inverse x + GELU", layer,
                  2 * C * C * P + 2 * C * H * W * 2 * m,
                  act + zx + act * (2 if training and not last else 1))]
     if not training:
@@ -767,10 +778,13 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
                 (f"L{l} mode-mixing weight grad", "mix_backward_weight_kernel",
                  8 * C * C * 2 * m * m, 2 * spec),
                 (f"L{l} mode-mixing input grad", "mix_backward_input_kernel",
-                 8 * C * C * 2 * m * m, 2 * spec),
-                (f"L{l} dZ (re)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
-                (f"L{l} dZ (im)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
-                (f"L{l} dv = W^T dz + dZ Fx^T, GELU'", "gemm_kernel",
+                 8 * C * C * 2 * m * m, 2 * spec)]
+        if inv_y:
+            ops += [(f"L{l} dZ", "spectral_out_kernel", 2 * 2 * C * H * m * 4 * m, spec // 2 + zx)]
+        else:
+            ops += [(f"L{l} dZ (re)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2),
+                    (f"L{l} dZ (im)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2)]
+        ops += [(f"L{l} dv = W^T dz + dZ Fx^T, GELU'", layer,
                  2 * C * C * P + 2 * C * H * W * 2 * m, act + zx + (act if l > 0 else 0) + act)]
     ops += [("lift weight grad", "gemm_kernel", 2 * C * Cin * P, act + Cin * P * 2)]
     return ops
