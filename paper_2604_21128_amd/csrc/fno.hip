@@ -41,6 +41,11 @@ namespace {
 
 constexpr int kBlock = 256;
 
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
 using qla::fno::gelu_as;
 using qla::fno::gelu_prime_as;
 
@@ -108,9 +113,8 @@ __global__ __launch_bounds__(256) void lift_kernel(const uint16_t* __restrict__ 
       }
       uint16_t* dst = out + (static_cast<long long>(b) * C + c) * P + p;
       if (full && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-        uint4 q;
-        __builtin_memcpy(&q, o, 16);
-        *reinterpret_cast<uint4*>(dst) = q;
+        // non-temporal: the first layer reads it in a later launch
+        __builtin_nontemporal_store(__builtin_bit_cast(u32x4_t, o), reinterpret_cast<u32x4_t*>(dst));
       } else {
         for (int k = 0; k < 8; ++k)
           if (p + k < P) dst[k] = o[k];
@@ -233,10 +237,6 @@ __global__ __launch_bounds__(256) void narrow_projection_grad_kernel(
 // are zero. Shapes: C <= 64, C2 <= 128, Cout <= 4 (else the two-GEMM path).
 constexpr int kProjPix = 64, kProjK = 32, kProjMaxC = 64, kProjMaxC2 = 128, kProjMaxOut = 4;
 
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
-typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // GELU in the fused kernels: the Abramowitz & Stegun form of fno_internal.h (with the
 // library erff the GELUs were half of the projection kernel's time: every hidden value

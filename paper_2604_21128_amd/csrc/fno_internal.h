@@ -8,11 +8,17 @@
 namespace qla {
 namespace fno {
 
-// BF16 as raw 16-bit patterns: round to nearest even from FP32.
+// BF16 as raw 16-bit patterns: round to nearest even from FP32. On the device the gfx950
+// conversion instruction (v_cvt_pk_bf16_f32, two values per instruction) does it; on the
+// host the same rounding is written out (finite values give the same bits).
 __host__ __device__ inline uint16_t f32_to_bf16(float f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f));
+#else
   uint32_t u = __builtin_bit_cast(uint32_t, f);
   u += 0x7FFFu + ((u >> 16) & 1u);
   return static_cast<uint16_t>(u >> 16);
+#endif
 }
 __host__ __device__ inline float bf16_to_f32(uint16_t h) {
   return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16);
