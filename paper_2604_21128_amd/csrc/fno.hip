@@ -1369,7 +1369,9 @@ GemmDesc weight_grad(const uint16_t* d, int Mo, const uint16_t* x, int K, int B,
   g.N = K;
   g.K = static_cast<int>(P);
   g.batch = B;
-  g.ksplit = static_cast<int>(std::max<size_t>(1, std::min<size_t>(256, P / 2048)));
+  // 1024-pixel splits (at most 256 per sample): measured against 2048-, 4096- and 8192-pixel
+  // splits at 512^2, batch 16 (training 1754 samples/s against 1731, 1657 and 1750)
+  g.ksplit = static_cast<int>(std::max<size_t>(1, std::min<size_t>(256, P / 1024)));
   g.atomic = 1;
   g.rowsum = db;
   return g;
