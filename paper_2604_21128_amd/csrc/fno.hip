@@ -892,20 +892,31 @@ hipError_t launch_spectral_out(const uint16_t* S, const uint16_t* Ya, const uint
   return hipGetLastError();
 }
 
-// Mode mixing of a Fourier layer and its two backward products. Spectra are
-// [(b, c)][2 kyi + p][kx] (p = 0: real part, 1: imaginary part), R is [mode][c][o][2]
-// with mode = kyi m + kx. One block per mode: its spectral values of every (b, c) (4-byte
-// words 2 m apart in memory) are gathered into LDS once, R's C x C block of the mode is read
-// contiguously, and the products run out of LDS (sample b in chunks of kModeRows / C).
+// Mode mixing of a Fourier layer and its two backward products. The spectra T, S and dT are
+// stored per plane, [(b, c)][2 kyi + p][kx] (p = 0: real part, 1: imaginary part); dS, which
+// only the backward mixing reads, is stored mode-major, [2 kyi + p][kx][(b, o)], so that one
+// mode's values of every (b, o) are contiguous (storing T that way as well made the one-pass
+// transform that writes it slower by more than the mixing gained). R is [mode][c][o][2] with
+// mode = kyi m + kx. Blocks (mode, q), q < kModeSplit: the mode's spectral values of every
+// (b, c) are read into LDS, the block's part of R's C x C block of the mode is read
+// contiguously, and the products run out of LDS (sample b in chunks of kModeRows / C); block
+// q computes the q-th quarter of the output channels (of the rows c of dR). One block per mode
+// (288 at 12 modes) left most of the chip idle.
 // The complex products are written as real pairs:
 //   S    = sum_c R[c][o] T[c]:       (rr tr - ri ti, rr ti + ri tr)
 //   dT   = sum_o conj(R[c][o]) dS[o]: (rr dr + ri di, rr di - ri dr)
 //   dR  += sum_b conj(T[b][c]) dS[b][o]: (tr dr + ti di, tr di - ti dr)
 constexpr int kModeC = 64;        // channel limit of the per-mode kernels
 constexpr int kModeRows = 1024;   // (b, c) pairs staged per chunk
+constexpr int kModeSplit = 4;     // blocks per mode, each a quarter of the output channels
 
 __device__ __forceinline__ size_t spec_at(int b, int c, int C, int m, int kyi, int kx) {
   return (static_cast<size_t>(b) * C + c) * (4 * m * m) + static_cast<size_t>(2 * kyi) * m + kx;
+}
+// The mode-major spectrum dS ([2kyi + p][kx][plane] over planes (b, o)): the real parts of
+// mode (kyi, kx) start here, the imaginary parts m * planes further on.
+__device__ __forceinline__ size_t mode_base(int m, int kyi, int kx, size_t planes) {
+  return (static_cast<size_t>(2 * kyi) * m + kx) * planes;
 }
 
 // S[(b,o)] at one mode = sum_c R[mode][c][o] T[(b,c)] (complex), stored BF16.
@@ -913,11 +924,18 @@ __global__ __launch_bounds__(256) void mix_forward_kernel(const float* __restric
                                                           const float* __restrict__ R,
                                                           uint16_t* __restrict__ S, int B, int C,
                                                           int m) {
-  __shared__ float rs[kModeC * kModeC * 2];  // R[c][o][2] of this mode
+  __shared__ float rs[kModeC * kModeC * 2];  // R[c][o][2] of this mode, this block's o
   __shared__ float tre[kModeRows], tim[kModeRows];
   const int mode = blockIdx.x, kyi = mode / m, kx = mode % m, t = threadIdx.x;
+  const int osz = (C + kModeSplit - 1) / kModeSplit, o0 = blockIdx.y * osz;
+  const int no = min(C, o0 + osz) - o0;  // this block's output channels o0 .. o0 + no - 1
+  if (no <= 0) return;
   const float* rm = R + static_cast<size_t>(mode) * C * C * 2;
-  for (int i = t; i < C * C * 2; i += 256) rs[i] = rm[i];
+  for (int i = t; i < C * no; i += 256) {
+    const int c = i / no, ol = i % no;
+    rs[(c * no + ol) * 2] = rm[(c * C + o0 + ol) * 2];
+    rs[(c * no + ol) * 2 + 1] = rm[(c * C + o0 + ol) * 2 + 1];
+  }
   const int per = kModeRows / C;  // samples per chunk
   for (int b0 = 0; b0 < B; b0 += per) {
     const int nb = min(per, B - b0);
@@ -928,11 +946,11 @@ __global__ __launch_bounds__(256) void mix_forward_kernel(const float* __restric
       tim[i] = T[at + m];
     }
     __syncthreads();
-    for (int i = t; i < nb * C; i += 256) {  // output (b, o): consecutive threads, consecutive o
-      const int bl = i / C, o = i % C;
+    for (int i = t; i < nb * no; i += 256) {  // output (b, o): consecutive threads, consecutive o
+      const int bl = i / no, ol = i % no, o = o0 + ol;
       float sr = 0.f, si = 0.f;
       for (int c = 0; c < C; ++c) {
-        const float rr = rs[(c * C + o) * 2], ri = rs[(c * C + o) * 2 + 1];
+        const float rr = rs[(c * no + ol) * 2], ri = rs[(c * no + ol) * 2 + 1];
         const float tr = tre[bl * C + c], ti = tim[bl * C + c];
         sr = fmaf(rr, tr, fmaf(-ri, ti, sr));
         si = fmaf(rr, ti, fmaf(ri, tr, si));
@@ -949,30 +967,34 @@ __global__ __launch_bounds__(256) void mix_backward_input_kernel(const float* __
                                                                  const float* __restrict__ R,
                                                                  uint16_t* __restrict__ dT,
                                                                  int B, int C, int m) {
-  __shared__ float rs[kModeC * kModeC * 2];  // R[o][c][2] of this mode (transposed)
+  __shared__ float rs[kModeC * kModeC * 2];  // R[o][c][2] of this mode (transposed), this block's c
   __shared__ float dre[kModeRows], dim_[kModeRows];
   const int mode = blockIdx.x, kyi = mode / m, kx = mode % m, t = threadIdx.x;
+  const int csz = (C + kModeSplit - 1) / kModeSplit, c0 = blockIdx.y * csz;
+  const int nc = min(C, c0 + csz) - c0;  // this block's output channels c0 .. c0 + nc - 1
+  if (nc <= 0) return;
   const float* rm = R + static_cast<size_t>(mode) * C * C * 2;
-  for (int i = t; i < C * C; i += 256) {  // i = c C + o, read contiguously
-    const int c = i / C, o = i % C;
-    rs[(o * C + c) * 2] = rm[2 * i];
-    rs[(o * C + c) * 2 + 1] = rm[2 * i + 1];
+  for (int i = t; i < nc * C; i += 256) {  // i = cl C + o: R's rows c, read contiguously
+    const int cl = i / C, o = i % C;
+    rs[(o * nc + cl) * 2] = rm[((c0 + cl) * C + o) * 2];
+    rs[(o * nc + cl) * 2 + 1] = rm[((c0 + cl) * C + o) * 2 + 1];
   }
+  const size_t planes = static_cast<size_t>(B) * C, db = mode_base(m, kyi, kx, planes);
+  const size_t mp = static_cast<size_t>(m) * planes;
   const int per = kModeRows / C;
   for (int b0 = 0; b0 < B; b0 += per) {
     const int nb = min(per, B - b0);
     __syncthreads();
-    for (int i = t; i < nb * C; i += 256) {
-      const size_t at = spec_at(b0 + i / C, i % C, C, m, kyi, kx);
-      dre[i] = dS[at];
-      dim_[i] = dS[at + m];
+    for (int i = t; i < nb * C; i += 256) {  // planes b0 C + i, contiguous
+      dre[i] = dS[db + static_cast<size_t>(b0) * C + i];
+      dim_[i] = dS[db + mp + static_cast<size_t>(b0) * C + i];
     }
     __syncthreads();
-    for (int i = t; i < nb * C; i += 256) {  // output (b, c): consecutive threads, consecutive c
-      const int bl = i / C, c = i % C;
+    for (int i = t; i < nb * nc; i += 256) {  // output (b, c): consecutive threads, consecutive c
+      const int bl = i / nc, cl = i % nc, c = c0 + cl;
       float gr = 0.f, gi = 0.f;
       for (int o = 0; o < C; ++o) {
-        const float rr = rs[(o * C + c) * 2], ri = rs[(o * C + c) * 2 + 1];
+        const float rr = rs[(o * nc + cl) * 2], ri = rs[(o * nc + cl) * 2 + 1];
         const float dr = dre[bl * C + o], di = dim_[bl * C + o];
         gr = fmaf(rr, dr, fmaf(ri, di, gr));
         gi = fmaf(rr, di, fmaf(-ri, dr, gi));
@@ -990,28 +1012,34 @@ __global__ __launch_bounds__(256) void mix_backward_weight_kernel(const float* _
                                                                   float* __restrict__ dR, int B,
                                                                   int C, int m) {
   __shared__ float tre[kModeRows], tim[kModeRows], dre[kModeRows], dim_[kModeRows];
-  constexpr int kOut = kModeC * kModeC / 256;  // outputs per thread
+  constexpr int kOut = (kModeC * kModeC / kModeSplit + 255) / 256;  // outputs per thread
   const int mode = blockIdx.x, kyi = mode / m, kx = mode % m, t = threadIdx.x;
+  const int csz = (C + kModeSplit - 1) / kModeSplit, c0 = blockIdx.y * csz;
+  const int nc = min(C, c0 + csz) - c0;  // this block's rows c0 .. c0 + nc - 1 of dR
+  if (nc <= 0) return;
   float ar[kOut], ai[kOut];
 #pragma unroll
   for (int k = 0; k < kOut; ++k) ar[k] = ai[k] = 0.f;
+  const size_t planes = static_cast<size_t>(B) * C, base = mode_base(m, kyi, kx, planes);
+  const size_t mp = static_cast<size_t>(m) * planes;
   const int per = kModeRows / C;
   for (int b0 = 0; b0 < B; b0 += per) {
     const int nb = min(per, B - b0);
     __syncthreads();
     for (int i = t; i < nb * C; i += 256) {
-      const size_t at = spec_at(b0 + i / C, i % C, C, m, kyi, kx);
+      const size_t at = spec_at(b0 + i / C, i % C, C, m, kyi, kx);  // T: per plane
       tre[i] = T[at];
       tim[i] = T[at + m];
-      dre[i] = dS[at];
-      dim_[i] = dS[at + m];
+      const size_t ad = base + static_cast<size_t>(b0) * C + i;      // dS: planes contiguous
+      dre[i] = dS[ad];
+      dim_[i] = dS[ad + mp];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kOut; ++k) {  // output j = c C + o: consecutive threads, consecutive o
+    for (int k = 0; k < kOut; ++k) {  // output j = cl C + o: consecutive threads, consecutive o
       const int j = t + 256 * k;
-      if (j >= C * C) break;
-      const int c = j / C, o = j % C;
+      if (j >= nc * C) break;
+      const int c = c0 + j / C, o = j % C;
       for (int bl = 0; bl < nb; ++bl) {
         const float tr = tre[bl * C + c], ti = tim[bl * C + c];
         const float dr = dre[bl * C + o], di = dim_[bl * C + o];
@@ -1020,11 +1048,11 @@ __global__ __launch_bounds__(256) void mix_backward_weight_kernel(const float* _
       }
     }
   }
-  float* rm = dR + static_cast<size_t>(mode) * C * C * 2;
+  float* rm = dR + (static_cast<size_t>(mode) * C + c0) * C * 2;  // rows c0 ..
 #pragma unroll
   for (int k = 0; k < kOut; ++k) {
     const int j = t + 256 * k;
-    if (j >= C * C) break;
+    if (j >= nc * C) break;
     rm[2 * j] += ar[k];
     rm[2 * j + 1] += ai[k];
   }
@@ -1476,7 +1504,7 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
         QLA_GEMM(g);
       }
     }
-    hipLaunchKernelGGL(mix_forward_kernel, dim3(2 * m * m), dim3(256), 0, f->stream, f->T[l],
+    hipLaunchKernelGGL(mix_forward_kernel, dim3(2 * m * m, kModeSplit), dim3(256), 0, f->stream, f->T[l],
                        f->p + f->o_R[l], f->Sb, B, C, m);
     QLA_HIP(hipGetLastError());
     // inverse y: U[(b,o)][y][2kx+p] = IY_p S
@@ -1667,10 +1695,10 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
       g.sBb = static_cast<long long>(H) * 2 * m;
       g.sBk = 2 * m;
       g.sBn = 2;
-      g.C = f->dS;
-      g.sCb = modes_sz;
-      g.sCm = m;
-      g.sCn = 1;
+      g.C = f->dS;  // mode-major: [2kyi + p][kx][(b, o)]
+      g.sCb = 1;
+      g.sCm = static_cast<long long>(m) * B * C;
+      g.sCn = static_cast<long long>(B) * C;
       g.M = 4 * m;
       g.N = m;
       g.K = H;
@@ -1678,10 +1706,10 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
       g.beta = part;
       QLA_GEMM(g);
     }
-    hipLaunchKernelGGL(mix_backward_weight_kernel, dim3(2 * m * m), dim3(256), 0, f->stream,
+    hipLaunchKernelGGL(mix_backward_weight_kernel, dim3(2 * m * m, kModeSplit), dim3(256), 0, f->stream,
                        f->dS, f->T[l], f->g + f->o_R[l], B, C, m);
     QLA_HIP(hipGetLastError());
-    hipLaunchKernelGGL(mix_backward_input_kernel, dim3(2 * m * m), dim3(256), 0, f->stream,
+    hipLaunchKernelGGL(mix_backward_input_kernel, dim3(2 * m * m, kModeSplit), dim3(256), 0, f->stream,
                        f->dS, f->p + f->o_R[l], f->dT, B, C, m);
     QLA_HIP(hipGetLastError());
     // dZ_p = A_p^T dT  (p = re, im)
