@@ -885,6 +885,98 @@ __global__ __launch_bounds__(256) void spectral_out_kernel(
   }
 }
 
+// The backward of the inverse y transform, into the mode-major dS:
+//   dS[r][kx][plane] = sum_y YaT[r][y] Z[plane][y][2kx] + YbT[r][y] Z[plane][y][2kx + 1]
+// (YaT, YbT: the transposed inverse y bases IY1^T, IY2^T, [4m][H]; Z = dU, [plane][H][2m]).
+// One block per plane; each of its 4 waves takes 32-row tiles of y (w, w + 4, ...): the tile
+// (32 rows of 2m BF16, contiguous) is loaded with 16-byte loads and stored transposed into the
+// wave's LDS tile, whose rows (one per column j of Z) are the B operands of 32 x 32 x 16
+// products; the rows of YaT and YbT are the A operands. The waves' accumulators (two 32-row
+// tiles of T's 4m rows) are summed in a fixed order at the end.
+__global__ __launch_bounds__(256) void spectral_y_kernel(
+    const uint16_t* __restrict__ Z, const uint16_t* __restrict__ YaT,
+    const uint16_t* __restrict__ YbT, int H, int m, float* __restrict__ dS) {
+  __shared__ __attribute__((aligned(16))) uint16_t zt[4][32][40];  // [wave][column j][row]
+  __shared__ float red[4][64][17];
+  const int lane = threadIdx.x & 63, l32 = lane & 31, h = lane >> 5, w = threadIdx.x >> 6;
+  const int plane = blockIdx.x, planes = gridDim.x;
+  const int m2 = 2 * m, r4 = 4 * m, tiles = (H + 31) / 32;
+  const uint16_t* Zp = Z + static_cast<long long>(plane) * H * m2;
+  const bool vec = (H * m2) % 8 == 0;
+  f32x16_t acc[2] = {};
+  for (int tl = w; tl < tiles; tl += 4) {
+    const int y0 = tl * 32, rows = min(32, H - y0), n = rows * m2;
+    const uint16_t* src = Zp + static_cast<long long>(y0) * m2;
+    // the tile, transposed into zt[j][y - y0] (rows beyond H and columns beyond 2m are zero)
+    for (int i = lane; i < 32 * 32; i += 64) zt[w][i >> 5][i & 31] = 0;
+    __builtin_amdgcn_wave_barrier();
+    if (vec) {  // 16-byte pieces (H 2m a multiple of 8: every piece aligned and whole)
+      for (int cidx = lane; cidx < n / 8; cidx += 64) {
+        const u32x4_t q = *reinterpret_cast<const u32x4_t*>(src + 8 * cidx);
+        uint16_t e[8];
+        __builtin_memcpy(e, &q, 16);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int el = 8 * cidx + i;
+          zt[w][el % m2][el / m2] = e[i];
+        }
+      }
+    } else {
+      for (int el = lane; el < n; el += 64) zt[w][el % m2][el / m2] = src[el];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {  // tile rows 16 s + 8 h .. + 7 in the k slots of lane half h
+      const int ks = 16 * s + 8 * h;
+      const bf16x8_t bre = *reinterpret_cast<const bf16x8_t*>(&zt[w][(2 * l32) & 31][ks]);
+      const bf16x8_t bim = *reinterpret_cast<const bf16x8_t*>(&zt[w][(2 * l32 + 1) & 31][ks]);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const int r = rt * 32 + l32, y = y0 + ks;
+        bf16x8_t fa = bf16x8_t{}, fb = bf16x8_t{};
+        if (r < r4 && y + 8 <= H && H % 8 == 0) {  // rows of the bases 16-byte aligned
+          fa = *reinterpret_cast<const bf16x8_t*>(YaT + static_cast<long long>(r) * H + y);
+          fb = *reinterpret_cast<const bf16x8_t*>(YbT + static_cast<long long>(r) * H + y);
+        } else if (r < r4) {
+          uint16_t ea[8], eb[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            ea[i] = y + i < H ? YaT[static_cast<long long>(r) * H + y + i] : uint16_t(0);
+            eb[i] = y + i < H ? YbT[static_cast<long long>(r) * H + y + i] : uint16_t(0);
+          }
+          fa = __builtin_bit_cast(bf16x8_t, ea);
+          fb = __builtin_bit_cast(bf16x8_t, eb);
+        }
+        acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, bre, acc[rt], 0, 0, 0);
+        acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fb, bim, acc[rt], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // the tile is read before the next one is stored
+  }
+  // lane kx (< m) holds rows rt 32 + 8i + 4h + jj of column kx; sum the waves in order
+  if (l32 < 16) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) red[w][rt * 32 + 8 * i + 4 * h + jj][l32] = acc[rt][4 * i + jj];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < r4 * m; idx += 256) {
+    const int r = idx / m, kx = idx % m;
+    dS[static_cast<long long>(idx) * planes + plane] =
+        red[0][r][kx] + red[1][r][kx] + red[2][r][kx] + red[3][r][kx];
+  }
+}
+
+hipError_t launch_spectral_y(const uint16_t* Z, const uint16_t* YaT, const uint16_t* YbT,
+                             int planes, int H, int m, float* dS, hipStream_t stream) {
+  hipLaunchKernelGGL(spectral_y_kernel, dim3(static_cast<unsigned>(planes)), dim3(256), 0,
+                     stream, Z, YaT, YbT, H, m, dS);
+  return hipGetLastError();
+}
+
 hipError_t launch_spectral_out(const uint16_t* S, const uint16_t* Ya, const uint16_t* Yb,
                                int planes, int H, int m, uint16_t* U, hipStream_t stream) {
   hipLaunchKernelGGL(spectral_out_kernel, dim3(static_cast<unsigned>(planes)), dim3(256), 0,
@@ -1229,7 +1321,8 @@ struct qla_fno {
   float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
   uint16_t* w16 = nullptr;
   uint16_t *Fx = nullptr, *FxT = nullptr, *A1 = nullptr, *A2 = nullptr, *A1T = nullptr,
-           *A2T = nullptr, *IY1 = nullptr, *IY2 = nullptr, *IX = nullptr;
+           *A2T = nullptr, *IY1 = nullptr, *IY2 = nullptr, *IY1T = nullptr, *IY2T = nullptr,
+           *IX = nullptr;
   // activations (batch Bmax)
   std::vector<uint16_t*> v, z;
   uint16_t *Zb = nullptr, *Sb = nullptr, *Ub = nullptr, *zq = nullptr, *h = nullptr,
@@ -1326,6 +1419,14 @@ qla_status make_bases(qla_fno* f) {
   if (st == QLA_OK) st = upload16(f, &f->IX, IX);
   if (st == QLA_OK) st = upload16(f, &f->A1, A1);
   if (st == QLA_OK) st = upload16(f, &f->A2, A2);
+  std::vector<double> IY1T(IY1.size()), IY2T(IY2.size());  // [2kyi + p'][y]
+  for (int y = 0; y < H; ++y)
+    for (int k = 0; k < 4 * m; ++k) {
+      IY1T[size_t(k) * H + y] = IY1[size_t(y) * 4 * m + k];
+      IY2T[size_t(k) * H + y] = IY2[size_t(y) * 4 * m + k];
+    }
+  if (st == QLA_OK) st = upload16(f, &f->IY1T, IY1T);
+  if (st == QLA_OK) st = upload16(f, &f->IY2T, IY2T);
   std::vector<double> A1T(A1.size()), A2T(A2.size());  // [y][2kyi + p']
   for (int k = 0; k < 4 * m; ++k)
     for (int y = 0; y < H; ++y) {
@@ -1686,6 +1787,9 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
       QLA_GEMM(g);
     }
     // dS = IY1^T dUre + IY2^T dUim
+    if (spectral_out_fits(m)) {
+      QLA_HIP(launch_spectral_y(f->dU, f->IY1T, f->IY2T, B * C, H, m, f->dS, f->stream));
+    } else {
     for (int part = 0; part < 2; ++part) {
       GemmDesc g;
       g.A = part ? f->IY2 : f->IY1;
@@ -1705,6 +1809,7 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
       g.batch = B * C;
       g.beta = part;
       QLA_GEMM(g);
+    }
     }
     hipLaunchKernelGGL(mix_backward_weight_kernel, dim3(2 * m * m, kModeSplit), dim3(256), 0, f->stream,
                        f->dS, f->T[l], f->g + f->o_R[l], B, C, m);
