@@ -725,7 +725,8 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
     # one-pass x and y transforms (Z stays on chip) on grids of a multiple of 32 rows of a
     # multiple of 128 cells up to 512, with at most 16 modes
     one_pass = H % 32 == 0 and W % 128 == 0 and W <= 512 and 1 <= m <= 16
-    # the inverse y transform (and the backward dZ and dS) as one kernel per plane: m <= 16
+    # the inverse y transform (and the backward dZ, and dS where the one-pass kernel does not
+    # fit) as one kernel per plane: m <= 16
     inv_y = 1 <= m <= 16
     # the layer kernel (forward, and the backward input gradient): width 64, rows of a
     # multiple of 256 cells, 2m <= 32
@@ -771,14 +772,19 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
             ("projection 1 weight grad", "gemm_kernel", 2 * C2 * C * P, hid + act),
             ("projection 1 input grad", "gemm_kernel", 2 * C2 * C * P, hid + act)]
     for l in reversed(range(L)):
-        ops += [(f"L{l} weight grad", "gemm_kernel", 2 * C * C * P, 2 * act),
-                (f"L{l} dU = dz IX^T", "gemm_kernel", 2 * C * H * W * 2 * m, act + zx),
-]
-        if inv_y:
-            ops += [(f"L{l} dS", "spectral_y_kernel", 2 * 2 * C * 4 * m * m * H, zx + spec)]
+        ops += [(f"L{l} weight grad", "gemm_kernel", 2 * C * C * P, 2 * act)]
+        if one_pass:
+            # dU = dz IX^T and dS = IY^T dU in one pass over dz (dU stays on chip)
+            ops += [(f"L{l} dS = IY^T (dz IX^T)", "spectral_in_kernel",
+                     2 * C * H * 2 * m * W + 2 * 2 * C * 4 * m * m * H, act + spec)]
         else:
-            ops += [(f"L{l} dS (re)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + spec),
-                    (f"L{l} dS (im)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + 2 * spec)]
+            ops += [(f"L{l} dU = dz IX^T", "gemm_kernel", 2 * C * H * W * 2 * m, act + zx)]
+            if inv_y:
+                ops += [(f"L{l} dS", "spectral_y_kernel", 2 * 2 * C * 4 * m * m * H, zx + spec)]
+            else:
+                ops += [(f"L{l} dS (re)", "gemm_kernel", 2 * C * 4 * m * m * H, zx // 2 + spec),
+                        (f"L{l} dS (im)", "gemm_kernel", 2 * C * 4 * m * m * H,
+                         zx // 2 + 2 * spec)]
         ops += [(f"L{l} mode-mixing weight grad", "mix_backward_weight_kernel",
                  8 * C * C * 2 * m * m, 2 * spec),
                 (f"L{l} mode-mixing input grad", "mix_backward_input_kernel",

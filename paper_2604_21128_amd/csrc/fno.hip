@@ -635,7 +635,7 @@ bool spectral_in_fits(int H, int W, int m) {
          4 * m <= kSpecRows;
 }
 
-template <int NU>
+template <int NU, bool kModeMajor>
 __global__ __launch_bounds__(64 * kSpecWaves, 4) void spectral_in_kernel(
     const uint16_t* __restrict__ v, long long sample_stride, long long plane_stride,
     int planes_per_sample, const uint16_t* __restrict__ fxt, const uint16_t* __restrict__ a1,
@@ -770,25 +770,33 @@ __global__ __launch_bounds__(64 * kSpecWaves, 4) void spectral_in_kernel(
       for (int j = 0; j < 4; ++j) red[(w * 32 + 8 * i + 4 * h + j) * 16 + l32] = acc[4 * i + j];
   }
   __syncthreads();
-  float* Tb = T + static_cast<long long>(blockIdx.x) * r4 * m;
+  // per plane, [plane][r][kx]; or mode-major, [r][kx][plane] (the backward's dS)
   for (int idx = t; idx < r4 * m; idx += kThreads) {
     const int r = idx / m, kx = idx % m, hr = r >> 5, rr = r & 31;
     float sum = 0.f;
 #pragma unroll
     for (int ww = 0; ww < kSpecWaves; ww += 2) sum += red[((ww + hr) * 32 + rr) * 16 + kx];
-    Tb[idx] = sum;
+    if constexpr (kModeMajor) {
+      T[static_cast<long long>(idx) * gridDim.x + blockIdx.x] = sum;
+    } else {
+      T[static_cast<long long>(blockIdx.x) * r4 * m + idx] = sum;
+    }
   }
 }
 
+// mode_major: T stored [r][kx][plane] instead of [plane][r][kx]
 hipError_t launch_spectral_in(const uint16_t* v, long long sample_stride, long long plane_stride,
                               int planes_per_sample, int planes, const uint16_t* fxt,
                               const uint16_t* a1, const uint16_t* a2, int H, int W, int m,
-                              float* T, hipStream_t stream) {
+                              float* T, hipStream_t stream, bool mode_major = false) {
   using Kernel = void (*)(const uint16_t*, long long, long long, int, const uint16_t*,
                           const uint16_t*, const uint16_t*, int, int, int, float*);
-  static const Kernel table[4] = {spectral_in_kernel<1>, spectral_in_kernel<2>,
-                                  spectral_in_kernel<3>, spectral_in_kernel<4>};
-  hipLaunchKernelGGL(table[W / 128 - 1], dim3(static_cast<unsigned>(planes)),
+  static const Kernel table[2][4] = {
+      {spectral_in_kernel<1, false>, spectral_in_kernel<2, false>, spectral_in_kernel<3, false>,
+       spectral_in_kernel<4, false>},
+      {spectral_in_kernel<1, true>, spectral_in_kernel<2, true>, spectral_in_kernel<3, true>,
+       spectral_in_kernel<4, true>}};
+  hipLaunchKernelGGL(table[mode_major][W / 128 - 1], dim3(static_cast<unsigned>(planes)),
                      dim3(64 * kSpecWaves), spectral_in_lds(W, m), stream, v, sample_stride,
                      plane_stride, planes_per_sample, fxt, a1, a2, H, W, m, T);
   return hipGetLastError();
@@ -1768,48 +1776,56 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
   for (int l = L - 1; l >= 0; --l) {
     const uint16_t* vl = f->v[l];
     QLA_GEMM(weight_grad(dz, C, vl, C, B, P, f->g + f->o_W[l], f->g + f->o_b[l]));
-    // spectral branch: dU = dz IX^T
-    {
-      GemmDesc g;
-      g.A = dz;
-      g.sAm = W;
-      g.sAk = 1;
-      g.B = f->IX;
-      g.sBk = 1;
-      g.sBn = W;
-      g.C = f->dU;
-      g.sCm = 2 * m;
-      g.sCn = 1;
-      g.M = B * C * H;
-      g.N = 2 * m;
-      g.K = W;
-      g.out_bf16 = 1;
-      QLA_GEMM(g);
-    }
-    // dS = IY1^T dUre + IY2^T dUim
-    if (spectral_out_fits(m)) {
-      QLA_HIP(launch_spectral_y(f->dU, f->IY1T, f->IY2T, B * C, H, m, f->dS, f->stream));
+    // spectral branch: dS = IY1^T dUre + IY2^T dUim with dU = dz IX^T, in one pass over dz
+    // (the forward's x and y transform kernel with IX for the x basis and the transposed
+    // inverse y bases), or as the two products below
+    if (spectral_in_fits(H, W, m)) {
+      QLA_HIP(launch_spectral_in(dz, static_cast<long long>(C) * P, static_cast<long long>(P), C,
+                                 B * C, f->IX, f->IY1T, f->IY2T, H, W, m, f->dS, f->stream,
+                                 true));
     } else {
-    for (int part = 0; part < 2; ++part) {
-      GemmDesc g;
-      g.A = part ? f->IY2 : f->IY1;
-      g.sAm = 1;
-      g.sAk = 4 * m;
-      g.B = f->dU + part;
-      g.sBb = static_cast<long long>(H) * 2 * m;
-      g.sBk = 2 * m;
-      g.sBn = 2;
-      g.C = f->dS;  // mode-major: [2kyi + p][kx][(b, o)]
-      g.sCb = 1;
-      g.sCm = static_cast<long long>(m) * B * C;
-      g.sCn = static_cast<long long>(B) * C;
-      g.M = 4 * m;
-      g.N = m;
-      g.K = H;
-      g.batch = B * C;
-      g.beta = part;
-      QLA_GEMM(g);
-    }
+      {
+        GemmDesc g;
+        g.A = dz;
+        g.sAm = W;
+        g.sAk = 1;
+        g.B = f->IX;
+        g.sBk = 1;
+        g.sBn = W;
+        g.C = f->dU;
+        g.sCm = 2 * m;
+        g.sCn = 1;
+        g.M = B * C * H;
+        g.N = 2 * m;
+        g.K = W;
+        g.out_bf16 = 1;
+        QLA_GEMM(g);
+      }
+      // dS = IY1^T dUre + IY2^T dUim
+      if (spectral_out_fits(m)) {
+        QLA_HIP(launch_spectral_y(f->dU, f->IY1T, f->IY2T, B * C, H, m, f->dS, f->stream));
+      } else {
+        for (int part = 0; part < 2; ++part) {
+          GemmDesc g;
+          g.A = part ? f->IY2 : f->IY1;
+          g.sAm = 1;
+          g.sAk = 4 * m;
+          g.B = f->dU + part;
+          g.sBb = static_cast<long long>(H) * 2 * m;
+          g.sBk = 2 * m;
+          g.sBn = 2;
+          g.C = f->dS;  // mode-major: [2kyi + p][kx][(b, o)]
+          g.sCb = 1;
+          g.sCm = static_cast<long long>(m) * B * C;
+          g.sCn = static_cast<long long>(B) * C;
+          g.M = 4 * m;
+          g.N = m;
+          g.K = H;
+          g.batch = B * C;
+          g.beta = part;
+          QLA_GEMM(g);
+        }
+      }
     }
     hipLaunchKernelGGL(mix_backward_weight_kernel, dim3(2 * m * m, kModeSplit), dim3(256), 0, f->stream,
                        f->dS, f->T[l], f->g + f->o_R[l], B, C, m);
