@@ -496,6 +496,20 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
     }
     __syncthreads();
     if (tile + gridDim.x < tiles) load_tile(tile + gridDim.x);  // in flight during the products
+    // backward: GELU'(z) of the first 32 output rows, in flight during the products (the
+    // second 32 rows' are loaded before their half of the epilogue)
+    u32x4_t gq[4];
+    const uint16_t* gb = nullptr;
+    if constexpr (kBack) {
+      if (gz) {
+        gb = gz + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int idx = it * 256 + t, rr = idx >> 5, seg = idx & 31;
+          gq[it] = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(gb + rr * P + seg * 8));
+        }
+      }
+    }
     f32x16_t acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -516,10 +530,16 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
     if constexpr (kBack) {
       // the FP32 sums, 32 rows at a time, times GELU'(gz), stored BF16
       uint16_t* db = zout + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0;
-      const uint16_t* gb =
-          gz ? gz + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0 : nullptr;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
+        if (half == 1 && gb) {
+#pragma unroll
+          for (int it = 0; it < 4; ++it) {
+            const int idx = it * 256 + t, rr = idx >> 5, seg = idx & 31;
+            gq[it] = __builtin_nontemporal_load(
+                reinterpret_cast<const u32x4_t*>(gb + (32 + rr) * P + seg * 8));
+          }
+        }
         __syncthreads();  // the tile (or the previous half) is no longer read
         if (wm == half) {
 #pragma unroll
@@ -537,11 +557,7 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
           const f32x4_t lo = *reinterpret_cast<const f32x4_t*>(&fst[rr][seg * 8]);
           const f32x4_t hi = *reinterpret_cast<const f32x4_t*>(&fst[rr][seg * 8 + 4]);
           uint16_t gv[8];
-          if (gb) {
-            const u32x4_t q = __builtin_nontemporal_load(
-                reinterpret_cast<const u32x4_t*>(gb + row * P + seg * 8));
-            __builtin_memcpy(gv, &q, 16);
-          }
+          if (gb) __builtin_memcpy(gv, &gq[it], 16);
           uint16_t e[8];
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
