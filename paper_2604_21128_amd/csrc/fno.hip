@@ -470,17 +470,21 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
     const long long rem = tile % (static_cast<long long>(H) * per_row);
     const int y = static_cast<int>(rem / per_row), x0 = static_cast<int>(rem % per_row) * kMixPix;
     // U fragments of this tile's grid row: row 32 wm + hl, modes kh .. kh + 7 and 16 + kh ..
+    // (16-byte loads when 2m is a multiple of 8: each group of 8 modes then lies wholly in or
+    // out of the row, and rows start 16-byte aligned)
     bf16x8_t a2[2];
+    const uint16_t* usrc = U + ((static_cast<long long>(b) * kMixC + 32 * wm + hl) * H + y) * m2;
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      uint16_t e[8];
-      const uint16_t* src = U + ((static_cast<long long>(b) * kMixC + 32 * wm + hl) * H + y) * m2;
+      const int j0 = 16 * f + kh;
+      if (m2 % 8 == 0) {
+        a2[f] = j0 < m2 ? *reinterpret_cast<const bf16x8_t*>(usrc + j0) : bf16x8_t{};
+      } else {
+        uint16_t e[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int j = 16 * f + kh + i;
-        e[i] = j < m2 ? src[j] : uint16_t(0);
+        for (int i = 0; i < 8; ++i) e[i] = j0 + i < m2 ? usrc[j0 + i] : uint16_t(0);
+        a2[f] = __builtin_bit_cast(bf16x8_t, e);
       }
-      a2[f] = __builtin_bit_cast(bf16x8_t, e);
     }
     __syncthreads();  // the previous tile's output staging has been read
 #pragma unroll
