@@ -709,6 +709,18 @@ def surrogate_study(qla, torch, args):
     return res
 
 
+def wgrad_ops(name, Mo, K, P, flops, nbytes):
+    """A pointwise layer's weight gradient (Mo x K): the matrix-core weight-gradient kernel and
+    its fixed-order sum of the per-block partials where the channel counts fit it (at most
+    128 each, at most 8 tiles of 32 x 32, pixels a multiple of 64), else the split GEMM."""
+    up = lambda n: 1 if n <= 32 else 2 if n <= 64 else 4 if n <= 128 else 0
+    if (up(Mo) and up(K) and up(Mo) * up(K) <= 8 and P % 64 == 0
+            and max(Mo, K) * P * 2 < 2 ** 31):
+        return [(name, "wgrad_kernel", flops, nbytes),
+                (name + " (block sums)", "wgrad_final_kernel", 0, 0)]
+    return [(name, "gemm_kernel", flops, nbytes)]
+
+
 def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
     """The surrogate network's kernel launches for one sample, in launch order: (op, kernel
     name fragment, algorithmic flops, algorithmic HBM bytes). Bytes count one read of each
@@ -765,14 +777,15 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
             ("projection 2", "narrow_projection_kernel", 2 * Cout * C2 * P, hid + Cout * P * 4),
             ("loss sums", "loss_partial_kernel", 4 * Cout * P, Cout * P * 6),
             ("loss", "loss_final_kernel", 0, 0),
-            ("loss gradient", "loss_grad_kernel", 3 * Cout * P, Cout * P * (6 + 2)),
-            ("projection 2 weight grad", "gemm_kernel", 2 * Cout * C2 * P, Cout * P * 2 + hid),
-            ("projection 2 input grad", "narrow_projection_grad_kernel", 2 * Cout * C2 * P,
-             Cout * P * 2 + 2 * hid),
-            ("projection 1 weight grad", "gemm_kernel", 2 * C2 * C * P, hid + act),
-            ("projection 1 input grad", "gemm_kernel", 2 * C2 * C * P, hid + act)]
+            ("loss gradient", "loss_grad_kernel", 3 * Cout * P, Cout * P * (6 + 2))]
+    ops += wgrad_ops("projection 2 weight grad", Cout, C2, P, 2 * Cout * C2 * P,
+                     Cout * P * 2 + hid)
+    ops += [("projection 2 input grad", "narrow_projection_grad_kernel", 2 * Cout * C2 * P,
+             Cout * P * 2 + 2 * hid)]
+    ops += wgrad_ops("projection 1 weight grad", C2, C, P, 2 * C2 * C * P, hid + act)
+    ops += [("projection 1 input grad", "gemm_kernel", 2 * C2 * C * P, hid + act)]
     for l in reversed(range(L)):
-        ops += [(f"L{l} weight grad", "gemm_kernel", 2 * C * C * P, 2 * act)]
+        ops += wgrad_ops(f"L{l} weight grad", C, C, P, 2 * C * C * P, 2 * act)
         if one_pass:
             # dU = dz IX^T and dS = IY^T dU in one pass over dz (dU stays on chip)
             ops += [(f"L{l} dS = IY^T (dz IX^T)", "spectral_in_kernel",
@@ -796,7 +809,7 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
                     (f"L{l} dZ (im)", "gemm_kernel", 2 * C * H * m * 4 * m, spec // 2 + zx // 2)]
         ops += [(f"L{l} dv = W^T dz + dZ Fx^T, GELU'", layer,
                  2 * C * C * P + 2 * C * H * W * 2 * m, act + zx + (act if l > 0 else 0) + act)]
-    ops += [("lift weight grad", "gemm_kernel", 2 * C * Cin * P, act + Cin * P * 2)]
+    ops += wgrad_ops("lift weight grad", C, Cin, P, 2 * C * Cin * P, act + Cin * P * 2)
     return ops
 
 

@@ -19,6 +19,7 @@
 // the GEMMs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -1178,6 +1179,264 @@ __global__ __launch_bounds__(256) void mix_backward_weight_kernel(const float* _
   }
 }
 
+// Weight and bias gradients of a pointwise (1x1) layer on the matrix cores, for Mo <= 32 MH
+// output and K <= 32 NH input channels: dW[mo][k] += sum_{b,p} d[b][mo][p] x[b][k][p] and
+// db[mo] += sum_{b,p} d[b][mo][p]. A block takes a contiguous run of steps of PX pixels of one
+// sample. In a step its waves copy the step's slice of every row of d and x to LDS with
+// direct-to-LDS loads, each load one contiguous 1 KB (two rows of 512 bytes, or four of 256),
+// then every wave multiplies a quarter of the slice on the MFMAs, reading its fragments
+// (lane l: row l % 32, 8 pixels) from LDS. The 16-byte chunk c of staged row r sits in slot
+// c ^ (r % 16), so the 16 rows that one LDS read phase touches fall in distinct banks. Rows
+// past Mo or K are not loaded (or load the last row) and only reach outputs that are never
+// stored; pixels past the end of a sample (P a multiple of 64, not of PX) are zeroed. The bias
+// gradient adds the d fragments by dot products with ones. The waves of a block add their
+// sums in LDS in a fixed order into one partial per block, and wgrad_final_kernel adds the
+// partials of all blocks in a fixed order: the result does not depend on scheduling.
+constexpr int kWgWaves = 4, kWgPix = 64, kWgBlocks = 1024;
+constexpr int kWgMaxE = 8 * 1024 + 4 * 64;  // floats of one partial at MH NH = 8, MH = 4
+
+// 16 bytes per lane from global memory straight into LDS: lane i's bytes land at lds + 16 i
+// (lds wave-uniform). The builtin is kept out of the host pass, where it would drop the
+// host-side launch stubs of the kernel templates that use it.
+__device__ __forceinline__ void load_to_lds16(const void* src, void* lds) {
+#if __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_global_load_lds(src, lds, 16, 0, 0);
+#endif
+}
+
+template <int MH, int NH>
+struct WgShape {
+  static constexpr int kRows = 32 * (MH + NH);                 // staged rows: d, then x
+  static constexpr int kPx = kRows <= 128 ? 256 : 128;          // pixels per step
+  static constexpr int kRowBytes = 2 * kPx;
+  static constexpr int kLds = kRows * kRowBytes;
+  static constexpr int kE = MH * NH * 1024 + MH * 64;          // floats of one partial
+};
+
+template <int MH, int NH>
+__global__ __launch_bounds__(64 * kWgWaves, 2) void wgrad_kernel(
+    const uint16_t* __restrict__ d, int Mo, const uint16_t* __restrict__ x, int K, long long P,
+    long long steps, float* __restrict__ part) {
+  using S = WgShape<MH, NH>;
+  constexpr int kT = MH * NH, kE = S::kE, kPx = S::kPx, kRB = S::kRowBytes;
+  constexpr int kChunks = kPx / 8;                 // 16-byte chunks of a staged row
+  constexpr int kRowsPerLoad = 64 / kChunks;       // rows one wave load fills (2 or 4)
+  constexpr int kLoads = S::kRows / kRowsPerLoad;  // wave loads per step
+  constexpr int kSub = kPx / (16 * kWgWaves);      // MFMA k steps per wave per step
+  static_assert(S::kLds >= kE * 4, "the partial fits the staging buffer");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[S::kLds];
+  const int lane = threadIdx.x & 63, r = lane & 31, hf = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long spp = (P + kPx - 1) / kPx;  // steps per sample
+  long long s = steps * blockIdx.x / gridDim.x;
+  const long long s1 = steps * (blockIdx.x + 1) / gridDim.x;
+  long long b = s / spp, p0 = (s - b * spp) * kPx;
+  const int lr = lane / kChunks, slot = lane % kChunks;  // this lane's row and slot in a load
+  f32x16_t acc[MH][NH];
+  float dsum[MH];
+#pragma unroll
+  for (int i = 0; i < MH; ++i) {
+    dsum[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NH; ++j) acc[i][j] = f32x16_t{};
+  }
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  const bf16x2_t ones = {static_cast<__bf16>(1.f), static_cast<__bf16>(1.f)};
+  for (; s < s1; ++s) {
+    for (int q = wave; q < kLoads; q += kWgWaves) {
+      const int row0 = q * kRowsPerLoad, row = row0 + lr;  // staged rows of this load
+      const bool is_d = row0 < 32 * MH;
+      const int first = is_d ? row0 : row0 - 32 * MH, n = is_d ? Mo : K;
+      if (first >= n) continue;  // every row of this load is past the last one
+      const int c = slot ^ (row & 15);
+      const long long pc = p0 + 8 * c, px = pc < P - 8 ? pc : P - 8;
+      const uint16_t* src = is_d ? d + (b * Mo + min(row, Mo - 1)) * P + px
+                                 : x + (b * K + min(row - 32 * MH, K - 1)) * P + px;
+      load_to_lds16(src, lds + row0 * kRB);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kSub; ++t) {
+      const int pl = (wave * kSub + t) * 16 + 8 * hf;  // this lane's 8 pixels in the step
+      const bool ok = p0 + pl < P;
+      const int c = pl / 8;
+      u32x4_t fb[NH];
+#pragma unroll
+      for (int j = 0; j < NH; ++j) {
+        const int row = 32 * MH + 32 * j + r;
+        fb[j] = *reinterpret_cast<const u32x4_t*>(lds + row * kRB + ((c ^ (row & 15)) << 4));
+        if (!ok) fb[j] = u32x4_t{};
+      }
+#pragma unroll
+      for (int i = 0; i < MH; ++i) {
+        const int row = 32 * i + r;
+        u32x4_t fa = *reinterpret_cast<const u32x4_t*>(lds + row * kRB + ((c ^ (row & 15)) << 4));
+        if (!ok) fa = u32x4_t{};
+        const bf16x8_t av = __builtin_bit_cast(bf16x8_t, fa);
+#pragma unroll
+        for (int j = 0; j < NH; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              av, __builtin_bit_cast(bf16x8_t, fb[j]), acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          // a copy: __builtin_bit_cast of a vector element in place reads element 0
+          const unsigned w = fa[e];
+          dsum[i] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, w), ones,
+                                                    dsum[i], false);
+        }
+      }
+    }
+    __syncthreads();
+    p0 += kPx;
+    if (p0 >= P) {
+      p0 = 0;
+      ++b;
+    }
+  }
+  // waves 3, 2, 1 pass their running sum down through LDS; wave 0 stores the block's
+  // (separate LDS and global stores: one pointer that may be either costs flat addresses)
+  float* red = reinterpret_cast<float*>(lds);
+  auto to_lds = [&](bool add) {
+#pragma unroll
+    for (int i = 0; i < MH; ++i) {
+#pragma unroll
+      for (int j = 0; j < NH; ++j)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = ((i * NH + j) * 16 + q) * 64 + lane;
+          red[e] = add ? acc[i][j][q] + red[e] : acc[i][j][q];
+        }
+      const int e = kT * 1024 + i * 64 + lane;
+      red[e] = add ? dsum[i] + red[e] : dsum[i];
+    }
+  };
+  __syncthreads();
+  if (wave == kWgWaves - 1) to_lds(false);
+  for (int w = kWgWaves - 2; w >= 1; --w) {
+    __syncthreads();
+    if (wave == w) to_lds(true);
+  }
+  __syncthreads();
+  if (wave == 0) {
+    float* mine = part + static_cast<size_t>(blockIdx.x) * kE;
+#pragma unroll
+    for (int i = 0; i < MH; ++i) {
+#pragma unroll
+      for (int j = 0; j < NH; ++j)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = ((i * NH + j) * 16 + q) * 64 + lane;
+          mine[e] = acc[i][j][q] + red[e];
+        }
+      const int e = kT * 1024 + i * 64 + lane;
+      mine[e] = dsum[i] + red[e];
+    }
+  }
+}
+
+// dW[mo][k] += and db[mo] += the sums over the nblk partials of wgrad_kernel. Output element
+// f is a tile accumulator element (f < 1024 MH NH: register (f / 64) % 16 of lane f % 64 of
+// tile f / 1024) or a bias row (both pixel halves of lanes r and r + 32). A block takes 16
+// elements; its 64 groups of 16 threads each add every 64th partial, and the 64 sums are
+// then added in order.
+template <int MH, int NH>
+__global__ __launch_bounds__(1024) void wgrad_final_kernel(const float* __restrict__ part,
+                                                           int nblk, int Mo, int K,
+                                                           float* __restrict__ dW,
+                                                           float* __restrict__ db) {
+  constexpr int kT = MH * NH, kE = WgShape<MH, NH>::kE, kF = kT * 1024 + MH * 32;
+  __shared__ double tot[64][17];
+  const int el = threadIdx.x & 15, sub = threadIdx.x >> 4;
+  const int f = blockIdx.x * 16 + el;
+  const bool tile = f < kT * 1024;
+  int e0 = f, e1 = -1;  // the partial elements that make up f
+  if (!tile) {
+    const int g = f - kT * 1024;
+    e0 = kT * 1024 + (g / 32) * 64 + g % 32;
+    e1 = e0 + 32;
+  }
+  double acc = 0.0;
+  if (f < kF) {
+#pragma unroll 4
+    for (int j = sub; j < nblk; j += 64) {
+      const float* pj = part + static_cast<size_t>(j) * kE;
+      acc += e1 < 0 ? static_cast<double>(pj[e0])
+                    : static_cast<double>(pj[e0]) + static_cast<double>(pj[e1]);
+    }
+  }
+  tot[sub][el] = acc;
+  __syncthreads();
+  if (sub != 0 || f >= kF) return;
+  double v = 0.0;
+  for (int q = 0; q < 64; ++q) v += tot[q][el];
+  if (tile) {
+    const int t = f / 1024, q = (f / 64) % 16, lane = f % 64, tm = t / NH, tn = t % NH;
+    const int mo = 32 * tm + 8 * (q / 4) + 4 * (lane / 32) + q % 4, k = 32 * tn + lane % 32;
+    if (mo < Mo && k < K) dW[static_cast<size_t>(mo) * K + k] += static_cast<float>(v);
+  } else if (db) {
+    const int mo = f - kT * 1024;
+    if (mo < Mo) db[mo] += static_cast<float>(v);
+  }
+}
+
+// The tile shape (MH, NH) of wgrad_kernel for Mo output and K input channels, or false.
+bool wgrad_shape(int Mo, int K, long long P, int* mh, int* nh) {
+  auto up = [](int n) { return n <= 32 ? 1 : n <= 64 ? 2 : n <= 128 ? 4 : 0; };
+  const int a = up(Mo), c = up(K);
+  if (Mo < 1 || K < 1 || !a || !c || a * c > 8 || P < kWgPix || P % kWgPix) return false;
+  if (static_cast<long long>(Mo > K ? Mo : K) * P * 2 >= (1LL << 31)) return false;
+  *mh = a;
+  *nh = c;
+  return true;
+}
+
+// One round of resident blocks (each then takes the same number of steps), at most what the
+// partial buffer holds and at most one block per step.
+template <int MH, int NH>
+hipError_t launch_wgrad_t(const uint16_t* d, int Mo, const uint16_t* x, int K, int B, long long P,
+                          int cus, float* part, float* dW, float* db, hipStream_t stream) {
+  constexpr long long kE = WgShape<MH, NH>::kE, kPx = WgShape<MH, NH>::kPx;
+  static const int occ = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wgrad_kernel<MH, NH>, 64 * kWgWaves,
+                                                     0) != hipSuccess || n < 1)
+      n = 1;
+    return n;
+  }();
+  const long long steps = static_cast<long long>(B) * ((P + kPx - 1) / kPx);
+  long long nb = std::min(steps, static_cast<long long>(occ) * std::max(cus, 1));
+  nb = std::min(nb, static_cast<long long>(kWgBlocks) * kWgMaxE / kE);
+  const int nblk = static_cast<int>(nb);
+  hipLaunchKernelGGL((wgrad_kernel<MH, NH>), dim3(nblk), dim3(64 * kWgWaves), 0, stream, d, Mo,
+                     x, K, P, steps, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((wgrad_final_kernel<MH, NH>), dim3((MH * NH * 1024 + MH * 32 + 15) / 16),
+                     dim3(1024), 0, stream, part, nblk, Mo, K, dW, db);
+  return hipGetLastError();
+}
+
+// dW (Mo x K, row-major) += d x^T and db += d 1 over every pixel of the batch, on a device
+// with cus compute units; part holds kWgBlocks * kWgMaxE floats. The shape must pass
+// wgrad_shape.
+hipError_t launch_wgrad(const uint16_t* d, int Mo, const uint16_t* x, int K, int B, long long P,
+                        int cus, float* part, float* dW, float* db, hipStream_t stream) {
+  int mh = 0, nh = 0;
+  if (B < 1 || !wgrad_shape(Mo, K, P, &mh, &nh)) return hipErrorInvalidValue;
+  switch (mh * 8 + nh) {
+    case 9: return launch_wgrad_t<1, 1>(d, Mo, x, K, B, P, cus, part, dW, db, stream);
+    case 10: return launch_wgrad_t<1, 2>(d, Mo, x, K, B, P, cus, part, dW, db, stream);
+    case 12: return launch_wgrad_t<1, 4>(d, Mo, x, K, B, P, cus, part, dW, db, stream);
+    case 17: return launch_wgrad_t<2, 1>(d, Mo, x, K, B, P, cus, part, dW, db, stream);
+    case 18: return launch_wgrad_t<2, 2>(d, Mo, x, K, B, P, cus, part, dW, db, stream);
+    case 20: return launch_wgrad_t<2, 4>(d, Mo, x, K, B, P, cus, part, dW, db, stream);
+    case 33: return launch_wgrad_t<4, 1>(d, Mo, x, K, B, P, cus, part, dW, db, stream);
+    case 34: return launch_wgrad_t<4, 2>(d, Mo, x, K, B, P, cus, part, dW, db, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // dz = dv * GELU'(z)
 __global__ void gelu_grad_kernel(const float* __restrict__ dv, const uint16_t* __restrict__ z,
                                  uint16_t* __restrict__ dz, size_t n) {
@@ -1339,7 +1598,7 @@ struct Rng {
 
 struct qla_fno {
   int H = 0, W = 0, P = 0, Cin = 0, C = 0, C2 = 0, Cout = 0, L = 0, m = 0, Bmax = 0;
-  int device = 0;
+  int device = 0, cus = 1;  // device and its compute units
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // flat parameter layout
@@ -1360,6 +1619,7 @@ struct qla_fno {
   // spec and dv (FP32) only when W is not a multiple of the GEMM column tile, where
   // the inverse x transform cannot be fused into the channel-mixing GEMM
   float *spec = nullptr, *out = nullptr, *dS = nullptr, *dv = nullptr, *loss = nullptr;
+  float* wpart = nullptr;  // per-block partial sums of the weight-gradient kernel
   bool fused = false;
   double* sums = nullptr;
   double* band = nullptr;  // per-sample band sums of qla_fno_band_fraction
@@ -1535,6 +1795,16 @@ GemmDesc weight_grad(const uint16_t* d, int Mo, const uint16_t* x, int K, int B,
 }
 
 #define QLA_GEMM(desc) QLA_HIP(qla::fno::launch_gemm((desc), f->stream))
+
+// dW (Mo x K) += d x^T and db += d 1 over the batch: the matrix-core weight-gradient kernel
+// where the channel counts fit it, else the split GEMM.
+hipError_t weight_grad_run(const qla_fno* f, const uint16_t* d, int Mo, const uint16_t* x, int K,
+                           int B, float* dW, float* db) {
+  int mh = 0, nh = 0;
+  if (wgrad_shape(Mo, K, f->P, &mh, &nh))
+    return launch_wgrad(d, Mo, x, K, B, f->P, f->cus, f->wpart, dW, db, f->stream);
+  return qla::fno::launch_gemm(weight_grad(d, Mo, x, K, B, f->P, dW, db), f->stream);
+}
 
 // The inverse x transform of the spectral branch as a second contraction of the
 // channel-mixing GEMM g (whose columns are pixels): adds sum_j U[(b,o), y][j] IX[j][x].
@@ -1767,7 +2037,7 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
                      f->sums, f->dout, B, per);
   QLA_HIP(hipGetLastError());
   // projection 2, then dzq = (Q2^T dout) GELU'(zq)
-  QLA_GEMM(weight_grad(f->dout, f->Cout, f->h, C2, B, P, f->g + f->o_Q2, f->g + f->o_bq2));
+  QLA_HIP(weight_grad_run(f, f->dout, f->Cout, f->h, C2, B, f->g + f->o_Q2, f->g + f->o_bq2));
   if (f->Cout <= kNarrowOut && C2 <= kNarrowC2 && P % 8 == 0) {
     const long long threads = static_cast<long long>(P) / 8 * B;
     const long long blocks = (threads + 255) / 256;
@@ -1784,7 +2054,7 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
     QLA_GEMM(g);
   }
   // projection 1, then dz_{L-1} = Q1^T dzq (no activation after the last layer)
-  QLA_GEMM(weight_grad(f->dzq, C2, f->v[L], C, B, P, f->g + f->o_Q1, f->g + f->o_bq1));
+  QLA_HIP(weight_grad_run(f, f->dzq, C2, f->v[L], C, B, f->g + f->o_Q1, f->g + f->o_bq1));
   uint16_t* dz = f->dza;       // gradient with respect to z_l
   uint16_t* dz_prev = f->dzb;  // gradient with respect to z_{l-1} (or v_0)
   {
@@ -1795,7 +2065,7 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
   }
   for (int l = L - 1; l >= 0; --l) {
     const uint16_t* vl = f->v[l];
-    QLA_GEMM(weight_grad(dz, C, vl, C, B, P, f->g + f->o_W[l], f->g + f->o_b[l]));
+    QLA_HIP(weight_grad_run(f, dz, C, vl, C, B, f->g + f->o_W[l], f->g + f->o_b[l]));
     // spectral branch: dS = IY1^T dUre + IY2^T dUim with dU = dz IX^T, in one pass over dz
     // (the forward's x and y transform kernel with IX for the x basis and the transposed
     // inverse y bases), or as the two products below
@@ -1931,7 +2201,7 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
     std::swap(dz, dz_prev);
   }
   // lift (dz now holds the gradient with respect to v_0)
-  QLA_GEMM(weight_grad(dz, C, in, f->Cin, B, P, f->g + f->o_Wp, f->g + f->o_bp));
+  QLA_HIP(weight_grad_run(f, dz, C, in, f->Cin, B, f->g + f->o_Wp, f->g + f->o_bp));
   return QLA_OK;
 }
 
@@ -1972,6 +2242,8 @@ qla_status qla_fno_create(int height, int width, int in_channels, int out_channe
   f->m = modes;
   f->Bmax = max_batch;
   hipError_t e = hipGetDevice(&f->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&f->cus, hipDeviceAttributeMultiprocessorCount, f->device);
   if (e == hipSuccess && hip_stream) {
     f->stream = static_cast<hipStream_t>(hip_stream);
   } else if (e == hipSuccess) {
@@ -2039,6 +2311,7 @@ qla_status qla_fno_create(int height, int width, int in_channels, int out_channe
   A(&f->dS, B * C * 4 * m * m);
   A(&f->dT, B * C * 4 * m * m);
   A(&f->dZ, B * C * height * 2 * m);
+  A(&f->wpart, size_t(kWgBlocks) * kWgMaxE);
   A(&f->loss, 1);
   A(&f->sums, 2 * B);
   A(&f->band, 2 * B);

@@ -130,7 +130,11 @@ def gpu_forward(qla, net, u_bits, B):
 # rows of 256 cells) runs the dedicated layer kernel; "spectral" (a multiple of 32 rows
 # of a multiple of 128 cells, 16 modes: every row and column of the tiles in use) runs
 # the one-pass x and y transform kernel, as do "full" and the 512^2 and 64 x 256 band
-# fraction cases.
+# fraction cases. The weight gradients of the pointwise layers run the matrix-core
+# weight-gradient kernel wherever the pixels per sample are a multiple of 64 (all but
+# "ragged"), in each of its tile shapes: up to 64 x 64 output x input channels in these
+# cases, 128 x 32 (projection 1) and 64 x 128 (projection 2 with 40 outputs) in "wide",
+# and 128 x 64 (projection 1) and 32 x 128 (projection 2) in "full".
 SPECS = {
     "small": fno.Spec(H=40, W=72, cin=4, cout=3, C=16, m=6, L=3, C2=24),
     "ragged": fno.Spec(H=33, W=70, cin=4, cout=3, C=10, m=5, L=2, C2=70),
@@ -138,6 +142,7 @@ SPECS = {
     # width 64 on rows of 256 cells: the layers run the 256-pixel mixing kernel
     "mix256": fno.Spec(H=16, W=256, cin=4, cout=3, C=64, m=6, L=2, C2=40),
     "spectral": fno.Spec(H=96, W=384, cin=4, cout=3, C=16, m=16, L=2, C2=40),
+    "wide": fno.Spec(H=16, W=128, cin=4, cout=40, C=32, m=4, L=1, C2=128),
 }
 
 
