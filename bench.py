@@ -776,6 +776,7 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
     ops += [("projection 1", "gemm_kernel", 2 * C2 * C * P, act + 2 * hid),
             ("projection 2", "narrow_projection_kernel", 2 * Cout * C2 * P, hid + Cout * P * 4),
             ("loss sums", "loss_partial_kernel", 4 * Cout * P, Cout * P * 6),
+            ("loss sums, blocks in order", "loss_sums_kernel", 0, 0),
             ("loss", "loss_final_kernel", 0, 0),
             ("loss gradient", "loss_grad_kernel", 3 * Cout * P, Cout * P * (6 + 2))]
     ops += wgrad_ops("projection 2 weight grad", Cout, C2, P, 2 * Cout * C2 * P,

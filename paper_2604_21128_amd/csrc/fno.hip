@@ -1447,9 +1447,12 @@ __global__ void gelu_grad_kernel(const float* __restrict__ dv, const uint16_t* _
     dz[i] = f32_to_bf16(dv[i] * gelu_prime_as(bf16_to_f32(z[i])));
 }
 
-// sums[2b] += sum (out - target)^2, sums[2b+1] += sum target^2 over sample b
+// Block x of sample b writes part[2 (b X + x)] = its share of sum (out - target)^2 and
+// part[2 (b X + x) + 1] = its share of sum target^2 (X = gridDim.x blocks per sample);
+// loss_sums_kernel adds the shares in block order, so the sums repeat bit for bit.
+constexpr int kLossBlocks = 256;
 __global__ void loss_partial_kernel(const float* __restrict__ out, const uint16_t* __restrict__ tg,
-                                    double* __restrict__ sums, size_t per) {
+                                    double* __restrict__ part, size_t per) {
   __shared__ double r0[kBlock], r1[kBlock];
   const int b = blockIdx.y;
   double a0 = 0.0, a1 = 0.0;
@@ -1470,9 +1473,22 @@ __global__ void loss_partial_kernel(const float* __restrict__ out, const uint16_
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(&sums[2 * b], r0[0]);
-    atomicAdd(&sums[2 * b + 1], r1[0]);
+    const size_t at = 2 * (static_cast<size_t>(b) * gridDim.x + blockIdx.x);
+    part[at] = r0[0];
+    part[at + 1] = r1[0];
   }
+}
+
+// sums[2b + k] = sum over the nblk shares part[2 (b nblk + x) + k] in order of x (one
+// thread per sample and sum)
+__global__ void loss_sums_kernel(const double* __restrict__ part, int nblk, int B,
+                                 double* __restrict__ sums) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // 2 b + k
+  if (i >= 2 * B) return;
+  const int b = i / 2, k = i % 2;
+  double acc = 0.0;
+  for (int x = 0; x < nblk; ++x) acc += part[2 * (static_cast<size_t>(b) * nblk + x) + k];
+  sums[i] = acc;
 }
 
 // loss = mean_b |out_b - t_b| / |t_b|;  dout = (out - t) / (B |out_b - t_b| |t_b|)
@@ -1625,6 +1641,7 @@ struct qla_fno {
   float* wpart = nullptr;  // per-block partial sums of the weight-gradient kernel
   bool fused = false;
   double* sums = nullptr;
+  double* lpart = nullptr;  // per-block shares of the loss sums
   double* band = nullptr;  // per-sample band sums of qla_fno_band_fraction
   int64_t adam_t = 0;
   std::vector<void*> allocs;
@@ -2030,9 +2047,11 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
   const int C = f->C, C2 = f->C2, H = f->H, W = f->W, m = f->m, L = f->L;
   const size_t per = size_t(f->Cout) * P;
   const long long modes_sz = 4LL * m * m;
-  QLA_HIP(hipMemsetAsync(f->sums, 0, 2 * B * sizeof(double), f->stream));
-  hipLaunchKernelGGL(loss_partial_kernel, dim3(256, B), dim3(kBlock), 0, f->stream, f->out,
-                     target, f->sums, per);
+  hipLaunchKernelGGL(loss_partial_kernel, dim3(kLossBlocks, B), dim3(kBlock), 0, f->stream,
+                     f->out, target, f->lpart, per);
+  QLA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(loss_sums_kernel, dim3((2 * B + 63) / 64), dim3(64), 0, f->stream, f->lpart,
+                     kLossBlocks, B, f->sums);
   QLA_HIP(hipGetLastError());
   hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, f->stream, f->sums, B, f->loss);
   QLA_HIP(hipGetLastError());
@@ -2317,6 +2336,7 @@ qla_status qla_fno_create(int height, int width, int in_channels, int out_channe
   A(&f->wpart, size_t(kWgBlocks) * kWgMaxE);
   A(&f->loss, 1);
   A(&f->sums, 2 * B);
+  A(&f->lpart, 2 * B * kLossBlocks);
   A(&f->band, 2 * B);
   if (st == QLA_OK) st = make_bases(f);
   if (st != QLA_OK) {

@@ -198,6 +198,34 @@ def test_gradient_matches_fp64_reference(qla, net_factory, name):
     assert abs(g @ d - fd) <= GRAD_TOL * abs(fd)
 
 
+@pytest.mark.parametrize("name", ["mix256", "wide", "full"])
+def test_gradients_repeat_bit_for_bit(qla, net_factory, name):
+    """No sum in the loss and its gradient depends on scheduling: the weight and bias
+    gradients of the pointwise layers (lift, layer weights, both projections) come from the
+    matrix-core weight-gradient kernel, whose per-block partial sums are added in a fixed
+    order, the loss sums add their per-block shares in block order, and every other
+    reduction has one writer per output. Two backward passes over the same batch give
+    identical bits in every parameter block. "full" is the surrogate's 512^2, width-64
+    shape (batch 1)."""
+    s = SPECS.get(name) or fno.Spec(H=512, W=512, cin=4, cout=3, C=64, m=12, L=4, C2=128)
+    B = 2 if name in SPECS else 1
+    net = net_factory(s, B)
+    qla.qla_fno_set_params(net.h, make_params(s, 91))
+    u, t = inputs(s, B, 92)
+    ud, td = to_device(u), to_device(t)
+    grads = []
+    for _ in range(2):
+        qla.qla_fno_loss_grad(net.h, ud, td, B)
+        grads.append(qla.qla_fno_get_grads(net.h))
+    off = 0
+    for pname, shape in fno.param_shapes(s):
+        n = int(np.prod(shape))
+        np.testing.assert_array_equal(grads[0][off:off + n], grads[1][off:off + n],
+                                      err_msg=f"{name} {pname}")
+        assert np.abs(grads[0][off:off + n]).max() > 0, pname
+        off += n
+
+
 def test_adam_step_matches_the_reference_update(qla, net_factory):
     s = SPECS["small"]
     net = net_factory(s, 2)
