@@ -773,7 +773,11 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
                 ("output copy", "copyBuffer", 0, 2 * Cout * P * 4)]
         return ops
     hid = C2 * P * 2
-    ops += [("projection 1", "gemm_kernel", 2 * C2 * C * P, act + 2 * hid),
+    # training's first projection: its own kernel for width 64 on rows of a multiple of 256
+    # cells with 64 or 128 projection channels, else the GEMM
+    proj1 = ("proj1_train_kernel" if C == 64 and W % 256 == 0 and C2 % 64 == 0 and C2 <= 128
+             else "gemm_kernel")
+    ops += [("projection 1", proj1, 2 * C2 * C * P, act + 2 * hid),
             ("projection 2", "narrow_projection_kernel", 2 * Cout * C2 * P, hid + Cout * P * 4),
             ("loss sums", "loss_partial_kernel", 4 * Cout * P, Cout * P * 6),
             ("loss sums, blocks in order", "loss_sums_kernel", 0, 0),

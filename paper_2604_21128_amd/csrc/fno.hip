@@ -607,6 +607,113 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
   }
 }
 
+// Training's first projection, zq = Q1 v + bq1 and h = GELU(zq), for 64 input and 64 G
+// output channels (G = 1 or 2) on rows of a multiple of 256 cells: a block takes 256-pixel
+// tiles of grid rows in turn, stages each tile once in LDS ([pixel][channel], the layer
+// kernel's swizzle, the next tile in flight) and multiplies it by each 64-row group of Q1;
+// a group's outputs go through a staging buffer of their own (the tile stays for the next
+// group) and are stored row by row with 16-byte non-temporal stores. The GEMM it replaces
+// read v once per 64 output channels through 64-pixel tiles.
+constexpr int kProj1MaxGroups = 2;
+__global__ __launch_bounds__(256, 2) void proj1_train_kernel(
+    const uint16_t* __restrict__ v, const uint16_t* __restrict__ q1,
+    const float* __restrict__ bias, int groups, int H, int W, int B, uint16_t* __restrict__ zq,
+    uint16_t* __restrict__ hout) {
+  __shared__ __attribute__((aligned(16))) uint16_t vs[kMixPix * (kMixC + 8)];
+  __shared__ __attribute__((aligned(16))) uint16_t ost[kMixC][kMixPix + 8];
+  __shared__ float sbias[kProj1MaxGroups * kMixC];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+  const int hl = lane & 31, kh = 8 * (lane >> 5);
+  const long long P = static_cast<long long>(H) * W;
+  const int nout = groups * kMixC;
+  if (t < nout) sbias[t] = bias[t];
+  // Q1 fragments of each group: row 64 g + 32 wm + hl, k = 16 f + kh .. + 7
+  bf16x8_t afr[kProj1MaxGroups][kMixC / 16];
+#pragma unroll
+  for (int g = 0; g < kProj1MaxGroups; ++g)
+#pragma unroll
+    for (int f = 0; f < kMixC / 16; ++f)
+      afr[g][f] = g < groups ? *reinterpret_cast<const bf16x8_t*>(
+                                   q1 + (kMixC * g + 32 * wm + hl) * kMixC + 16 * f + kh)
+                             : bf16x8_t{};
+  const int per_row = W / kMixPix;
+  const long long tiles = static_cast<long long>(B) * H * per_row;
+  uint4 rv[8];
+  auto load_tile = [&](long long tile) {
+    const int b = static_cast<int>(tile / (static_cast<long long>(H) * per_row));
+    const long long rem = tile % (static_cast<long long>(H) * per_row);
+    const int y = static_cast<int>(rem / per_row), x0 = static_cast<int>(rem % per_row) * kMixPix;
+    const uint16_t* vb = v + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = it * 256 + t, c = idx >> 5, seg = idx & 31;
+      rv[it] = __builtin_bit_cast(
+          uint4, __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(vb + c * P + seg * 8)));
+    }
+  };
+  long long tile = blockIdx.x;
+  if (tile < tiles) load_tile(tile);
+  for (; tile < tiles; tile += gridDim.x) {
+    const int b = static_cast<int>(tile / (static_cast<long long>(H) * per_row));
+    const long long rem = tile % (static_cast<long long>(H) * per_row);
+    const int y = static_cast<int>(rem / per_row), x0 = static_cast<int>(rem % per_row) * kMixPix;
+    __syncthreads();  // the previous tile is no longer read
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = it * 256 + t, c = idx >> 5, seg = idx & 31;
+      uint16_t e[8];
+      __builtin_memcpy(e, &rv[it], 16);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = seg * 8 + i;
+        vs[r * (kMixC + 8) + mix_col64(r, c)] = e[i];
+      }
+    }
+    __syncthreads();
+    if (tile + gridDim.x < tiles) load_tile(tile + gridDim.x);  // in flight during the products
+    for (int g = 0; g < groups; ++g) {
+      f32x16_t acc[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        acc[nt] = f32x16_t{};
+        const int r = wn * 128 + nt * 32 + hl;
+#pragma unroll
+        for (int f = 0; f < kMixC / 16; ++f) {
+          const bf16x8_t bb =
+              *reinterpret_cast<const bf16x8_t*>(&vs[r * (kMixC + 8) + mix_col64(r, 16 * f + kh)]);
+          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g ? afr[1][f] : afr[0][f], bb,
+                                                            acc[nt], 0, 0, 0);
+        }
+      }
+      // pre-activation, then GELU, each staged in LDS and stored row by row
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        __syncthreads();  // the staging buffer is no longer read
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int row = 32 * wm + 8 * i + 4 * (lane >> 5) + j;
+              const float val = acc[nt][4 * i + j] + sbias[kMixC * g + row];
+              ost[row][wn * 128 + nt * 32 + hl] = f32_to_bf16(pass ? gelu_f(val) : val);
+            }
+        __syncthreads();
+        uint16_t* db = (pass ? hout : zq) +
+                       (static_cast<long long>(b) * nout + kMixC * g) * P +
+                       static_cast<long long>(y) * W + x0;
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int idx = it * 256 + t, row = idx >> 5, seg = idx & 31;
+          __builtin_nontemporal_store(*reinterpret_cast<const u32x4_t*>(&ost[row][seg * 8]),
+                                      reinterpret_cast<u32x4_t*>(db + row * P + seg * 8));
+        }
+      }
+    }
+  }
+}
+
 // The x and y transforms of a Fourier layer in one pass over v (grids of rows a multiple
 // of 32 cells, widths a multiple of 128 up to 512 cells, m <= 16 modes):
 //   T[(b,c)][r][kx] = sum_y A1[r][y] Z[y][2kx] + A2[r][y] Z[y][2kx+1],
@@ -2015,7 +2122,16 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
     QLA_HIP(hipGetLastError());
     return QLA_OK;
   }
-  {
+  if (training && C == kMixC && W % kMixPix == 0 && f->C2 % kMixC == 0 &&
+      f->C2 <= kProj1MaxGroups * kMixC) {
+    // one resident round of blocks (two per compute unit), each striding over tiles
+    const long long tiles = static_cast<long long>(B) * H * (W / kMixPix);
+    const long long want = 2LL * std::max(f->cus, 1);
+    hipLaunchKernelGGL(proj1_train_kernel, dim3(static_cast<unsigned>(std::min(tiles, want))),
+                       dim3(256), 0, f->stream, f->v[f->L], f->w16 + f->w16_Q1(),
+                       f->p + f->o_bq1, f->C2 / kMixC, H, W, B, f->zq, f->h);
+    QLA_HIP(hipGetLastError());
+  } else {
     GemmDesc g = pointwise(f->w16 + f->w16_Q1(), false, f->C2, C, f->v[f->L], B, P);
     g.bias = f->p + f->o_bq1;
     g.C = training ? f->zq : nullptr;

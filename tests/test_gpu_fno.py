@@ -143,6 +143,9 @@ SPECS = {
     "mix256": fno.Spec(H=16, W=256, cin=4, cout=3, C=64, m=6, L=2, C2=40),
     "spectral": fno.Spec(H=96, W=384, cin=4, cout=3, C=16, m=16, L=2, C2=40),
     "wide": fno.Spec(H=16, W=128, cin=4, cout=40, C=32, m=4, L=1, C2=128),
+    # width 64 on rows of 256 cells with 128 projection channels: training's first
+    # projection runs its dedicated kernel (two groups of 64 outputs), as in "full"
+    "proj": fno.Spec(H=8, W=256, cin=4, cout=3, C=64, m=4, L=1, C2=128),
 }
 
 
