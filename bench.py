@@ -714,8 +714,7 @@ def wgrad_ops(name, Mo, K, P, flops, nbytes):
     its fixed-order sum of the per-block partials where the channel counts fit it (at most
     128 each, at most 8 tiles of 32 x 32, pixels a multiple of 64), else the split GEMM."""
     up = lambda n: 1 if n <= 32 else 2 if n <= 64 else 4 if n <= 128 else 0
-    if (up(Mo) and up(K) and up(Mo) * up(K) <= 8 and P % 64 == 0
-            and max(Mo, K) * P * 2 < 2 ** 31):
+    if up(Mo) and up(K) and up(Mo) * up(K) <= 8 and P % 64 == 0:
         return [(name, "wgrad_kernel", flops, nbytes),
                 (name + " (block sums)", "wgrad_final_kernel", 0, 0)]
     return [(name, "gemm_kernel", flops, nbytes)]

@@ -1495,7 +1495,6 @@ bool wgrad_shape(int Mo, int K, long long P, int* mh, int* nh) {
   auto up = [](int n) { return n <= 32 ? 1 : n <= 64 ? 2 : n <= 128 ? 4 : 0; };
   const int a = up(Mo), c = up(K);
   if (Mo < 1 || K < 1 || !a || !c || a * c > 8 || P < kWgPix || P % kWgPix) return false;
-  if (static_cast<long long>(Mo > K ? Mo : K) * P * 2 >= (1LL << 31)) return false;
   *mh = a;
   *nh = c;
   return true;
