@@ -774,10 +774,17 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
     hid = C2 * P * 2
     # training's first projection: its own kernel for width 64 on rows of a multiple of 256
     # cells with 64 or 128 projection channels, else the GEMM
+    # (with the narrow second projection formed in the same pass from the staged hidden layer)
     proj1 = ("proj1_train_kernel" if C == 64 and W % 256 == 0 and C2 % 64 == 0 and C2 <= 128
              else "gemm_kernel")
-    ops += [("projection 1", proj1, 2 * C2 * C * P, act + 2 * hid),
-            ("projection 2", "narrow_projection_kernel", 2 * Cout * C2 * P, hid + Cout * P * 4),
+    if proj1 == "proj1_train_kernel" and Cout <= 4:
+        ops += [("projection 1 + projection 2", proj1, 2 * C2 * C * P + 2 * Cout * C2 * P,
+                 act + 2 * hid + Cout * P * 4)]
+    else:
+        ops += [("projection 1", proj1, 2 * C2 * C * P, act + 2 * hid),
+                ("projection 2", "narrow_projection_kernel", 2 * Cout * C2 * P,
+                 hid + Cout * P * 4)]
+    ops += [
             ("loss sums", "loss_partial_kernel", 4 * Cout * P, Cout * P * 6),
             ("loss sums, blocks in order", "loss_sums_kernel", 0, 0),
             ("loss", "loss_final_kernel", 0, 0),

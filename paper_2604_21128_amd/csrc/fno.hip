@@ -613,20 +613,31 @@ __global__ __launch_bounds__(256) void layer_mix_kernel(
 // kernel's swizzle, the next tile in flight) and multiplies it by each 64-row group of Q1;
 // a group's outputs go through a staging buffer of their own (the tile stays for the next
 // group) and are stored row by row with 16-byte non-temporal stores. The GEMM it replaces
-// read v once per 64 output channels through 64-pixel tiles.
+// read v once per 64 output channels through 64-pixel tiles. With out set (Cout <=
+// kNarrowOut) the second projection, out = Q2 h + bq2, is formed from the staged BF16 h as
+// narrow_projection_kernel forms it (bias first, then one FMA per hidden channel in order:
+// the same bits), so h is not read back from memory; thread t takes pixel t of the tile.
 constexpr int kProj1MaxGroups = 2;
 __global__ __launch_bounds__(256, 2) void proj1_train_kernel(
     const uint16_t* __restrict__ v, const uint16_t* __restrict__ q1,
     const float* __restrict__ bias, int groups, int H, int W, int B, uint16_t* __restrict__ zq,
-    uint16_t* __restrict__ hout) {
+    uint16_t* __restrict__ hout, const uint16_t* __restrict__ q2,
+    const float* __restrict__ bias2, int Cout, float* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) uint16_t vs[kMixPix * (kMixC + 8)];
   __shared__ __attribute__((aligned(16))) uint16_t ost[kMixC][kMixPix + 8];
   __shared__ float sbias[kProj1MaxGroups * kMixC];
+  __shared__ float sw2[kNarrowOut][kProj1MaxGroups * kMixC];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
   const int hl = lane & 31, kh = 8 * (lane >> 5);
   const long long P = static_cast<long long>(H) * W;
   const int nout = groups * kMixC;
   if (t < nout) sbias[t] = bias[t];
+  if (out) {
+    for (int i = t; i < kNarrowOut * kProj1MaxGroups * kMixC; i += 256) {
+      const int o = i / (kProj1MaxGroups * kMixC), c = i % (kProj1MaxGroups * kMixC);
+      sw2[o][c] = (o < Cout && c < nout) ? bf16_to_f32(q2[o * nout + c]) : 0.f;
+    }
+  }
   // Q1 fragments of each group: row 64 g + 32 wm + hl, k = 16 f + kh .. + 7
   bf16x8_t afr[kProj1MaxGroups][kMixC / 16];
 #pragma unroll
@@ -671,6 +682,9 @@ __global__ __launch_bounds__(256, 2) void proj1_train_kernel(
     }
     __syncthreads();
     if (tile + gridDim.x < tiles) load_tile(tile + gridDim.x);  // in flight during the products
+    float oacc[kNarrowOut];
+#pragma unroll
+    for (int o = 0; o < kNarrowOut; ++o) oacc[o] = (out && o < Cout) ? bias2[o] : 0.f;
     for (int g = 0; g < groups; ++g) {
       f32x16_t acc[4];
 #pragma unroll
@@ -709,7 +723,22 @@ __global__ __launch_bounds__(256, 2) void proj1_train_kernel(
           __builtin_nontemporal_store(*reinterpret_cast<const u32x4_t*>(&ost[row][seg * 8]),
                                       reinterpret_cast<u32x4_t*>(db + row * P + seg * 8));
         }
+        // the second projection's share of this group's channels, while the stores drain
+        if (pass == 1 && out) {
+          for (int r = 0; r < kMixC; ++r) {
+            const float x = bf16_to_f32(ost[r][t]);
+#pragma unroll
+            for (int o = 0; o < kNarrowOut; ++o) oacc[o] = fmaf(sw2[o][kMixC * g + r], x, oacc[o]);
+          }
+        }
       }
+    }
+    if (out) {
+#pragma unroll
+      for (int o = 0; o < kNarrowOut; ++o)
+        if (o < Cout)
+          out[(static_cast<long long>(b) * Cout + o) * P + static_cast<long long>(y) * W + x0 +
+              t] = oacc[o];
     }
   }
 }
@@ -2126,10 +2155,15 @@ qla_status forward(qla_fno* f, const uint16_t* in, int B, bool training) {
     // one resident round of blocks (two per compute unit), each striding over tiles
     const long long tiles = static_cast<long long>(B) * H * (W / kMixPix);
     const long long want = 2LL * std::max(f->cus, 1);
+    // the second projection in the same pass where it is narrow (h is then not read back)
+    const bool with_out = f->Cout <= kNarrowOut;
     hipLaunchKernelGGL(proj1_train_kernel, dim3(static_cast<unsigned>(std::min(tiles, want))),
                        dim3(256), 0, f->stream, f->v[f->L], f->w16 + f->w16_Q1(),
-                       f->p + f->o_bq1, f->C2 / kMixC, H, W, B, f->zq, f->h);
+                       f->p + f->o_bq1, f->C2 / kMixC, H, W, B, f->zq, f->h,
+                       f->w16 + f->w16_Q2(), f->p + f->o_bq2, f->Cout,
+                       with_out ? f->out : nullptr);
     QLA_HIP(hipGetLastError());
+    if (with_out) return QLA_OK;
   } else {
     GemmDesc g = pointwise(f->w16 + f->w16_Q1(), false, f->C2, C, f->v[f->L], B, P);
     g.bias = f->p + f->o_bq1;
