@@ -791,10 +791,16 @@ def fno_ops(H, W, C, m, L, Cin, Cout, C2, nparam, training):
             ("loss gradient", "loss_grad_kernel", 3 * Cout * P, Cout * P * (6 + 2))]
     ops += wgrad_ops("projection 2 weight grad", Cout, C2, P, 2 * Cout * C2 * P,
                      Cout * P * 2 + hid)
-    ops += [("projection 2 input grad", "narrow_projection_grad_kernel", 2 * Cout * C2 * P,
-             Cout * P * 2 + 2 * hid)]
-    ops += wgrad_ops("projection 1 weight grad", C2, C, P, 2 * C2 * C * P, hid + act)
-    ops += [("projection 1 input grad", "gemm_kernel", 2 * C2 * C * P, hid + act)]
+    if proj1 == "proj1_train_kernel" and Cout <= 4:
+        # dzq (stored) and dz = Q1^T dzq in one pass over zq
+        ops += [("projection 2 + projection 1 input grads", "proj_grad_kernel",
+                 2 * Cout * C2 * P + 2 * C2 * C * P, Cout * P * 2 + 2 * hid + act)]
+        ops += wgrad_ops("projection 1 weight grad", C2, C, P, 2 * C2 * C * P, hid + act)
+    else:
+        ops += [("projection 2 input grad", "narrow_projection_grad_kernel", 2 * Cout * C2 * P,
+                 Cout * P * 2 + 2 * hid)]
+        ops += wgrad_ops("projection 1 weight grad", C2, C, P, 2 * C2 * C * P, hid + act)
+        ops += [("projection 1 input grad", "gemm_kernel", 2 * C2 * C * P, hid + act)]
     for l in reversed(range(L)):
         ops += wgrad_ops(f"L{l} weight grad", C, C, P, 2 * C * C * P, 2 * act)
         if one_pass:

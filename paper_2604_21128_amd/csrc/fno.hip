@@ -743,6 +743,148 @@ __global__ __launch_bounds__(256, 2) void proj1_train_kernel(
   }
 }
 
+// Backward through training's two projections in one pass over zq (64 input channels, 64 G
+// hidden channels with G = 1 or 2, Cout <= kNarrowOut outputs, rows of a multiple of 256
+// cells):
+//   dzq[b][h][p] = GELU'(zq[b][h][p]) sum_o Q2[o][h] dout[b][o][p]  (stored: the first
+//                  projection's weight gradient reads it),
+//   dz[b][c][p]  = sum_h Q1[h][c] dzq[b][h][p].
+// dzq is formed as narrow_projection_grad_kernel forms it (the same bits) and goes
+// straight into the product's LDS tile ([pixel][channel], the layer kernel's swizzle), 64
+// hidden channels at a time, the next group's zq in flight during the products; the GEMM
+// this replaces read dzq back from memory. dz is staged in the same LDS and stored row by
+// row with 16-byte non-temporal stores.
+__global__ __launch_bounds__(256, 2) void proj_grad_kernel(
+    const uint16_t* __restrict__ dout, const uint16_t* __restrict__ q2,
+    const uint16_t* __restrict__ zq, const uint16_t* __restrict__ q1, int groups, int Cout,
+    int H, int W, int B, uint16_t* __restrict__ dzq, uint16_t* __restrict__ dz) {
+  __shared__ __attribute__((aligned(16))) uint16_t vs[kMixPix * (kMixC + 8)];
+  __shared__ float sw[kProj1MaxGroups * kMixC][kNarrowOut];
+  uint16_t(*ost)[kMixPix + 8] = reinterpret_cast<uint16_t(*)[kMixPix + 8]>(vs);
+  static_assert(kMixC * (kMixPix + 8) <= kMixPix * (kMixC + 8), "dz staging fits the tile");
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+  const int hl = lane & 31, kh = 8 * (lane >> 5), seg = t & 31;
+  const long long P = static_cast<long long>(H) * W;
+  const int C2 = groups * kMixC;
+  for (int i = t; i < kProj1MaxGroups * kMixC * kNarrowOut; i += 256) {
+    const int c = i / kNarrowOut, o = i % kNarrowOut;
+    sw[c][o] = (o < Cout && c < C2) ? bf16_to_f32(q2[o * C2 + c]) : 0.f;
+  }
+  // Q1^T fragments of each group: row c = 32 wm + hl, k = h = 64 g + 16 f + kh .. + 7
+  bf16x8_t afr[kProj1MaxGroups][kMixC / 16];
+#pragma unroll
+  for (int g = 0; g < kProj1MaxGroups; ++g)
+#pragma unroll
+    for (int f = 0; f < kMixC / 16; ++f) {
+      uint16_t e[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        e[i] = g < groups ? q1[(kMixC * g + 16 * f + kh + i) * kMixC + 32 * wm + hl] : uint16_t(0);
+      afr[g][f] = __builtin_bit_cast(bf16x8_t, e);
+    }
+  const int per_row = W / kMixPix;
+  const long long tiles = static_cast<long long>(B) * H * per_row;
+  auto tile_at = [&](long long tile, int* b, int* y, int* x0) {
+    *b = static_cast<int>(tile / (static_cast<long long>(H) * per_row));
+    const long long rem = tile % (static_cast<long long>(H) * per_row);
+    *y = static_cast<int>(rem / per_row);
+    *x0 = static_cast<int>(rem % per_row) * kMixPix;
+  };
+  // zq of one group of one tile: 8 x 16 bytes per thread (channel 64 g + (idx >> 5), the
+  // thread's 8 pixels seg * 8 ..)
+  uint4 rz[8];
+  auto load_z = [&](long long tile, int g) {
+    int b, y, x0;
+    tile_at(tile, &b, &y, &x0);
+    const uint16_t* zb = zq + (static_cast<long long>(b) * C2 + kMixC * g) * P +
+                         static_cast<long long>(y) * W + x0 + seg * 8;
+#pragma unroll
+    for (int it = 0; it < 8; ++it)
+      rz[it] = __builtin_bit_cast(uint4, __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(
+                                             zb + ((it * 256 + t) >> 5) * P)));
+  };
+  long long tile = blockIdx.x;
+  if (tile < tiles) load_z(tile, 0);
+  for (; tile < tiles; tile += gridDim.x) {
+    int b, y, x0;
+    tile_at(tile, &b, &y, &x0);
+    const long long pix = static_cast<long long>(y) * W + x0 + seg * 8;
+    float d[kNarrowOut][8];
+#pragma unroll
+    for (int o = 0; o < kNarrowOut; ++o) {
+      if (o < Cout) {
+        load8_bf16(dout + (static_cast<long long>(b) * Cout + o) * P + pix, d[o]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d[o][k] = 0.f;
+      }
+    }
+    f32x16_t acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x16_t{};
+    for (int g = 0; g < groups; ++g) {
+      __syncthreads();  // the tile (previous group's, or previous tile's dz staging) is free
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int c = (it * 256 + t) >> 5, h = kMixC * g + c;
+        uint16_t zv[8], e[8];
+        __builtin_memcpy(zv, &rz[it], 16);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          float v = 0.f;
+#pragma unroll
+          for (int o = 0; o < kNarrowOut; ++o) v = fmaf(sw[h][o], d[o][k], v);
+          e[k] = f32_to_bf16(v * gelu_prime_as(bf16_to_f32(zv[k])));
+        }
+        __builtin_nontemporal_store(__builtin_bit_cast(u32x4_t, e),
+                                    reinterpret_cast<u32x4_t*>(
+                                        dzq + (static_cast<long long>(b) * C2 + h) * P + pix));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int r = seg * 8 + i;
+          vs[r * (kMixC + 8) + mix_col64(r, c)] = e[i];
+        }
+      }
+      __syncthreads();
+      // the next group's (or the next tile's first group's) zq, in flight during the products
+      if (g + 1 < groups) {
+        load_z(tile, g + 1);
+      } else if (tile + gridDim.x < tiles) {
+        load_z(tile + gridDim.x, 0);
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const int r = wn * 128 + nt * 32 + hl;
+#pragma unroll
+        for (int f = 0; f < kMixC / 16; ++f) {
+          const bf16x8_t bb =
+              *reinterpret_cast<const bf16x8_t*>(&vs[r * (kMixC + 8) + mix_col64(r, 16 * f + kh)]);
+          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g ? afr[1][f] : afr[0][f], bb,
+                                                            acc[nt], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // the last group's tile is no longer read
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = 32 * wm + 8 * i + 4 * (lane >> 5) + j;
+          ost[row][wn * 128 + nt * 32 + hl] = f32_to_bf16(acc[nt][4 * i + j]);
+        }
+    __syncthreads();
+    uint16_t* db = dz + static_cast<long long>(b) * kMixC * P + static_cast<long long>(y) * W + x0;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = it * 256 + t, row = idx >> 5, sg = idx & 31;
+      __builtin_nontemporal_store(*reinterpret_cast<const u32x4_t*>(&ost[row][sg * 8]),
+                                  reinterpret_cast<u32x4_t*>(db + row * P + sg * 8));
+    }
+  }
+}
+
 // The x and y transforms of a Fourier layer in one pass over v (grids of rows a multiple
 // of 32 cells, widths a multiple of 128 up to 512 cells, m <= 16 modes):
 //   T[(b,c)][r][kx] = sum_y A1[r][y] Z[y][2kx] + A2[r][y] Z[y][2kx+1],
@@ -2209,26 +2351,36 @@ qla_status backward(qla_fno* f, const uint16_t* in, const uint16_t* target, int 
   QLA_HIP(hipGetLastError());
   // projection 2, then dzq = (Q2^T dout) GELU'(zq)
   QLA_HIP(weight_grad_run(f, f->dout, f->Cout, f->h, C2, B, f->g + f->o_Q2, f->g + f->o_bq2));
-  if (f->Cout <= kNarrowOut && C2 <= kNarrowC2 && P % 8 == 0) {
-    const long long threads = static_cast<long long>(P) / 8 * B;
-    const long long blocks = (threads + 255) / 256;
-    hipLaunchKernelGGL(narrow_projection_grad_kernel,
-                       dim3(static_cast<unsigned>(blocks < 8192 ? blocks : 8192)), dim3(256), 0,
-                       f->stream, f->dout, f->w16 + f->w16_Q2(), f->zq, C2, f->Cout,
-                       static_cast<long long>(P), B, f->dzq);
-    QLA_HIP(hipGetLastError());
-  } else {
-    GemmDesc g = pointwise(f->w16 + f->w16_Q2(), true, C2, f->Cout, f->dout, B, P);
-    g.C = f->dzq;
-    g.out_bf16 = 1;
-    g.gz = f->zq;
-    QLA_GEMM(g);
-  }
-  // projection 1, then dz_{L-1} = Q1^T dzq (no activation after the last layer)
-  QLA_HIP(weight_grad_run(f, f->dzq, C2, f->v[L], C, B, f->g + f->o_Q1, f->g + f->o_bq1));
   uint16_t* dz = f->dza;       // gradient with respect to z_l
   uint16_t* dz_prev = f->dzb;  // gradient with respect to z_{l-1} (or v_0)
-  {
+  if (C == kMixC && W % kMixPix == 0 && C2 % kMixC == 0 && C2 <= kProj1MaxGroups * kMixC &&
+      f->Cout <= kNarrowOut) {
+    // dzq and dz_{L-1} = Q1^T dzq in one pass (no activation after the last layer)
+    const long long tiles = static_cast<long long>(B) * H * (W / kMixPix);
+    const long long want = 2LL * std::max(f->cus, 1);
+    hipLaunchKernelGGL(proj_grad_kernel, dim3(static_cast<unsigned>(std::min(tiles, want))),
+                       dim3(256), 0, f->stream, f->dout, f->w16 + f->w16_Q2(), f->zq,
+                       f->w16 + f->w16_Q1(), C2 / kMixC, f->Cout, H, W, B, f->dzq, dz);
+    QLA_HIP(hipGetLastError());
+    QLA_HIP(weight_grad_run(f, f->dzq, C2, f->v[L], C, B, f->g + f->o_Q1, f->g + f->o_bq1));
+  } else {
+    if (f->Cout <= kNarrowOut && C2 <= kNarrowC2 && P % 8 == 0) {
+      const long long threads = static_cast<long long>(P) / 8 * B;
+      const long long blocks = (threads + 255) / 256;
+      hipLaunchKernelGGL(narrow_projection_grad_kernel,
+                         dim3(static_cast<unsigned>(blocks < 8192 ? blocks : 8192)), dim3(256),
+                         0, f->stream, f->dout, f->w16 + f->w16_Q2(), f->zq, C2, f->Cout,
+                         static_cast<long long>(P), B, f->dzq);
+      QLA_HIP(hipGetLastError());
+    } else {
+      GemmDesc g = pointwise(f->w16 + f->w16_Q2(), true, C2, f->Cout, f->dout, B, P);
+      g.C = f->dzq;
+      g.out_bf16 = 1;
+      g.gz = f->zq;
+      QLA_GEMM(g);
+    }
+    // projection 1, then dz_{L-1} = Q1^T dzq (no activation after the last layer)
+    QLA_HIP(weight_grad_run(f, f->dzq, C2, f->v[L], C, B, f->g + f->o_Q1, f->g + f->o_bq1));
     GemmDesc g = pointwise(f->w16 + f->w16_Q1(), true, C, C2, f->dzq, B, P);
     g.C = dz;
     g.out_bf16 = 1;
