@@ -134,7 +134,9 @@ def gpu_forward(qla, net, u_bits, B):
 # weight-gradient kernel wherever the pixels per sample are a multiple of 64 (all but
 # "ragged"), in each of its tile shapes: up to 64 x 64 output x input channels in these
 # cases, 128 x 32 (projection 1) and 64 x 128 (projection 2 with 40 outputs) in "wide",
-# and 128 x 64 (projection 1) and 32 x 128 (projection 2) in "full".
+# and 128 x 64 (projection 1) and 32 x 128 (projection 2) in "full". Training's projection
+# kernels (width 64, rows of a multiple of 256 cells) run with two groups of 64 projection
+# channels in "proj" and "full" and with one in "proj64" (two outputs).
 SPECS = {
     "small": fno.Spec(H=40, W=72, cin=4, cout=3, C=16, m=6, L=3, C2=24),
     "ragged": fno.Spec(H=33, W=70, cin=4, cout=3, C=10, m=5, L=2, C2=70),
@@ -146,6 +148,8 @@ SPECS = {
     # width 64 on rows of 256 cells with 128 projection channels: training's first
     # projection runs its dedicated kernel (two groups of 64 outputs), as in "full"
     "proj": fno.Spec(H=8, W=256, cin=4, cout=3, C=64, m=4, L=1, C2=128),
+    # the same with 64 projection channels: one group of 64 outputs in both projection kernels
+    "proj64": fno.Spec(H=8, W=512, cin=4, cout=2, C=64, m=4, L=1, C2=64),
 }
 
 
