@@ -1470,8 +1470,8 @@ __global__ __launch_bounds__(256) void mix_backward_weight_kernel(const float* _
 // gradient adds the d fragments by dot products with ones. The waves of a block add their
 // sums in LDS in a fixed order into one partial per block, and wgrad_final_kernel adds the
 // partials of all blocks in a fixed order: the result does not depend on scheduling.
-// eight waves per block measured 1% faster in training than four (2098 against 2080 samples/s
-// at 512^2, batch 16), and four-wave blocks on 128-pixel steps 1% slower again
+// Eight waves per block measured 1% faster in training than four (2098 against 2080 samples/s
+// at 512^2, batch 16); 128-pixel steps for every shape on top of that, 1% slower.
 constexpr int kWgWaves = 8, kWgPix = 64, kWgBlocks = 1024;
 constexpr int kWgMaxE = 8 * 1024 + 4 * 64;  // floats of one partial at MH NH = 8, MH = 4
 
