@@ -47,9 +47,11 @@ __device__ __forceinline__ ErfTail erf_tail(float x) {
   const float e = __builtin_amdgcn_exp2f(-z * z * 1.4426950408889634f);
   return {poly * t * e, e};
 }
+// x Phi(x) = max(x, 0) - |x| c / 2 for either sign (no select): for x >= 0 the same fused
+// multiply-add as x - x c / 2, for x < 0 the one rounding of x c / 2.
 __device__ __forceinline__ float gelu_as(float x) {
   const float c = erf_tail(x).c;
-  return x >= 0.0f ? fmaf(-0.5f * x, c, x) : 0.5f * x * c;
+  return fmaf(-0.5f * fabsf(x), c, fmaxf(x, 0.0f));
 }
 __device__ __forceinline__ float gelu_prime_as(float x) {
   const ErfTail r = erf_tail(x);
