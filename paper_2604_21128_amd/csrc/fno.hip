@@ -233,8 +233,13 @@ __global__ __launch_bounds__(256) void narrow_projection_grad_kernel(
 // and stores them pixel-major, 8-channel groups XORed with bits 3-4 of the pixel so
 // the transposing stores spread over the banks), the waves multiply with the
 // 32x32x16 BF16 matrix instruction (accumulator 4i + j = hidden row 8i + 4(lane/32)
-// + j, pixel lane % 32), add the bias, apply GELU in FP32 and fold their rows into the
-// Cout output sums, which meet in LDS. Channels, rows and pixels beyond C, C2 and P
+// + j, pixel lane % 32), add the bias and apply GELU in FP32. The second projection runs
+// on the matrix cores too, straight from those registers: accumulator registers 8m ..
+// 8m + 7 of a lane hold hidden rows 16m + 4(lane/32) + {0..3, 8..11} of its pixel,
+// exactly the 8 k slots a 32x32x16 B operand takes from that lane, so two products with
+// Q2 fragments (rows: outputs, k slots in the same order of hidden rows) fold a wave's 32
+// rows into the Cout output rows (GELU rounded to BF16 on the way, as the training path
+// stores it); the waves' sums meet in LDS. Channels, rows and pixels beyond C, C2 and P
 // are zero. Shapes: C <= 64, C2 <= 128, Cout <= 4 (else the two-GEMM path).
 constexpr int kProjPix = 64, kProjK = 32, kProjMaxC = 64, kProjMaxC2 = 128, kProjMaxOut = 4;
 
@@ -255,13 +260,23 @@ __global__ __launch_bounds__(256) void projection_fused_kernel(
     float* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) uint16_t vs[kProjPix][kProjK + 8];
   __shared__ float red[4][kProjMaxOut][kProjPix];
-  __shared__ float sb1[kProjMaxC2], sq2[kProjMaxOut][kProjMaxC2];
+  __shared__ float sb1[kProjMaxC2];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int hl = lane & 31, kh = 8 * (lane >> 5);
   for (int i = t; i < kProjMaxC2; i += 256) sb1[i] = i < C2 ? bq1[i] : 0.f;
-  for (int i = t; i < kProjMaxOut * kProjMaxC2; i += 256) {
-    const int o = i / kProjMaxC2, h = i % kProjMaxC2;
-    sq2[o][h] = (o < Cout && h < C2) ? bf16_to_f32(q2[o * C2 + h]) : 0.f;
+  // Q2 fragments of this wave's hidden rows: output row hl, k slot e of product m is hidden
+  // row 32 w + 8 (2 m + e / 4) + 4 (lane / 32) + e % 4 (the accumulator's row of register
+  // 8 m + e)
+  bf16x8_t q2f[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    uint16_t e8[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int h = 32 * w + 8 * (2 * m + e / 4) + 4 * (lane >> 5) + e % 4;
+      e8[e] = (hl < Cout && h < C2) ? q2[hl * C2 + h] : uint16_t(0);
+    }
+    q2f[m] = __builtin_bit_cast(bf16x8_t, e8);
   }
   // this lane's A fragments: row 32w + hl of Q1, channels kc + kk + kh .. + 7
   const int hr = 32 * w + hl;
@@ -313,38 +328,33 @@ __global__ __launch_bounds__(256) void projection_fused_kernel(
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[(kc + kk) / 16], b1, acc1, 0, 0, 0);
       }
     }
-    float part[kProjMaxOut][2];
-#pragma unroll
-    for (int o = 0; o < kProjMaxOut; ++o) part[o][0] = part[o][1] = 0.f;
+    f32x16_t o0 = {}, o1 = {};
     if (32 * w < C2) {
+      uint16_t g0[16], g1[16];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int h = 32 * w + 8 * i + 4 * (lane >> 5) + j;  // < kProjMaxC2
-          const float bias = sb1[h];
-          const float g0 = gelu_f(acc0[4 * i + j] + bias);
-          const float g1 = gelu_f(acc1[4 * i + j] + bias);
-#pragma unroll
-          for (int o = 0; o < kProjMaxOut; ++o) {
-            const float q = sq2[o][h];  // zero beyond C2 and Cout
-            part[o][0] += q * g0;
-            part[o][1] += q * g1;
-          }
+          const float bias = sb1[32 * w + 8 * i + 4 * (lane >> 5) + j];  // < kProjMaxC2
+          g0[4 * i + j] = f32_to_bf16(gelu_f(acc0[4 * i + j] + bias));
+          g1[4 * i + j] = f32_to_bf16(gelu_f(acc1[4 * i + j] + bias));
         }
       }
-    }
-    // lanes l and l + 32 hold the same pixels (different hidden rows)
 #pragma unroll
-    for (int o = 0; o < kProjMaxOut; ++o) {
-      part[o][0] += __shfl_xor(part[o][0], 32);
-      part[o][1] += __shfl_xor(part[o][1], 32);
+      for (int m = 0; m < 2; ++m) {
+        bf16x8_t b0, b1;
+        __builtin_memcpy(&b0, g0 + 8 * m, 16);
+        __builtin_memcpy(&b1, g1 + 8 * m, 16);
+        o0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(q2f[m], b0, o0, 0, 0, 0);
+        o1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(q2f[m], b1, o1, 0, 0, 0);
+      }
     }
+    // output row o of the products: register o of lanes 0 .. 31 (o < 4), pixel lane
     if (lane < 32) {
 #pragma unroll
       for (int o = 0; o < kProjMaxOut; ++o) {
-        red[w][o][lane] = part[o][0];
-        red[w][o][32 + lane] = part[o][1];
+        red[w][o][lane] = o0[o];
+        red[w][o][32 + lane] = o1[o];
       }
     }
     __syncthreads();
