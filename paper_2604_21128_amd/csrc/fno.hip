@@ -1491,6 +1491,9 @@ constexpr int kWgMaxE = 8 * 1024 + 4 * 64;  // floats of one partial at MH NH = 
 __device__ __forceinline__ void load_to_lds16(const void* src, void* lds) {
 #if __HIP_DEVICE_COMPILE__
   __builtin_amdgcn_global_load_lds(src, lds, 16, 0, 0);
+#else
+  (void)src;
+  (void)lds;
 #endif
 }
 
